@@ -1,0 +1,85 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module only draws inputs (numpy PCG64 streams) and states workload
+shapes; it holds none of the method's arithmetic.  The paper's own redistribute
+and sorting experiments feed Gaussian random numbers through MVR (Sec. 5.1.1);
+the workloads below follow that recipe at the sizes used here.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# Resample + redistribute alone: N = 2^24 particles, d = 16 FP32 state,
+# log-weights N(0, s^2) with s in {0.5, 2, 8}.
+RESAMPLE_N = 1 << 24
+RESAMPLE_D = 16
+RESAMPLE_SCALES = (0.5, 2.0, 8.0)
+LOGW_SEEDS = {0.5: 101, 2.0: 102, 8.0: 103}
+X_SEED = 100
+R_SEED = 7
+
+
+def logw_normal(n: int, s: float, seed: int) -> np.ndarray:
+    """Log-weights l_i = s * z_i, z_i iid N(0, 1), FP64."""
+    rng = np.random.default_rng(seed)
+    return s * rng.standard_normal(n)
+
+
+def particles(n: int, d: int, seed: int, dtype=np.float32) -> np.ndarray:
+    """Particle rows [n][d], iid N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, d), dtype=np.float64 if dtype == np.float64 else np.float32
+                               ).astype(dtype, copy=False)
+
+
+def offset_word(seed: int) -> int:
+    """One 64-bit word used as the systematic offset source."""
+    rng = np.random.default_rng(seed)
+    return int(rng.integers(0, 2**64, dtype=np.uint64))
+
+
+# 1-D Gaussian target N(2, 1), q0 = N(0, 9), random walk sd 0.5, N = 1024,
+# 20 iterations.
+GAUSS1D = dict(n=1024, d=1, mean=[2.0], var=[1.0], init_mean=0.0, init_sd=3.0, rw_sd=0.5,
+               iters=20)
+
+
+def gauss_log_norm(var) -> float:
+    """Additive constant -0.5 * sum log(2 pi var_k) of a diagonal Gaussian."""
+    v = [float(a) for a in np.asarray(var, dtype=np.float64).ravel()]
+    return float(-0.5 * (len(v) * math.log(2.0 * math.pi) + sum(math.log(a) for a in v)))
+
+
+def iso_gauss_log_norm(d: int, sd: float) -> float:
+    return float(-0.5 * d * math.log(2.0 * math.pi * sd * sd))
+
+
+def student_log_norm(nu: float) -> float:
+    return (math.lgamma(0.5 * (nu + 1.0)) - math.lgamma(0.5 * nu)
+            - 0.5 * math.log(nu * math.pi))
+
+
+# Bayesian logistic regression: M rows, D features iid N(0, 1) (rounded to
+# bf16 at generation so both precisions read the same data), theta* ~ N(0, I),
+# labels ~ Bernoulli(sigmoid(x . theta*)), prior N(0, 10 I).
+LOGREG = dict(m_rows=65536, d=32, n=1 << 16, iters=50, prior_var=10.0, rw_sd=0.01)
+
+
+def bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round FP32 values to the nearest bfloat16 (ties to even), as FP32."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def logreg_data(m_rows: int, d: int, seed: int):
+    rng = np.random.default_rng(seed)
+    X = bf16_round(rng.standard_normal((m_rows, d), dtype=np.float32))
+    theta = rng.standard_normal(d)
+    z = X.astype(np.float64) @ theta
+    p = 1.0 / (1.0 + np.exp(-z))
+    y = (rng.random(m_rows) < p).astype(np.float64)
+    return X, y, theta
