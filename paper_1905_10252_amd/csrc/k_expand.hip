@@ -1,0 +1,311 @@
+// Redistribute (Alg 5 semantics) as a load-balanced expand.
+//
+// With A_j = (number of output rows taken from sources 0..j), output row p
+// comes from anc(p) = #{j : A_j <= p}, so the ancestors are non-decreasing and
+// the output order is exactly that of the sequential redistribute.  Copies per
+// source range from 0 to N, so a source-parallel copy is unbalanced; instead
+// the merge of the two sorted sequences (A_j + j over sources, p over outputs)
+// is cut into equal segments of kSegLen merge steps (merge path).  Every
+// workgroup owns one segment: a few sources and a few outputs, never more than
+// kSegLen in total, whatever the weights.
+//
+// A_j is computed from the fixed-point prefix as floor((N S_j + U) / S), or is
+// the prefix of caller-supplied counts, or j + 1 when the ESS rule decided not
+// to resample.  The segment boundaries are found by a 64-ary search run by one
+// wavefront; the test A_j + j < k is evaluated as N S_j + U < (k - j) S in
+// 128-bit integers (no division).
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace smc {
+
+struct AFun {
+    i64 n;
+    const u64 *pref;
+    int mode;  // 0: identity, 1: systematic from S_j, 2: caller counts (A_j = pref[j])
+    u64 S, U;
+    double invS;
+
+    __device__ inline bool pred(i64 j, i64 k) const  // A_j + j < k
+    {
+        if (mode == 0) return 2 * j + 1 < k;
+        if (mode == 2) return (i64)pref[j] + j < k;
+        const i64 c = k - j;
+        if (c <= 0) return false;
+        const U128 lhs = add128(mul64((u64)n, pref[j]), U);
+        const U128 rhs = mul64((u64)c, S);
+        return lt128(lhs, rhs);
+    }
+
+    __device__ inline u64 A(i64 j) const
+    {
+        if (mode == 0) return (u64)(j + 1);
+        if (mode == 2) return pref[j];
+        const u64 sj = pref[j];
+        const U128 num = add128(mul64((u64)n, sj), U);
+        const double est = ((double)n * (double)sj + (double)U) * invS;
+        u64 a = est > 0.0 ? (u64)est : 0ull;
+        // exact correction to a S <= num < (a + 1) S
+        U128 aS = mul64(a, S);
+        while (lt128(num, aS)) {
+            --a;
+            aS = mul64(a, S);
+        }
+        U128 a1S = add128(aS, S);
+        while (!lt128(num, a1S)) {
+            ++a;
+            a1S = add128(a1S, S);
+        }
+        return a;
+    }
+};
+
+// Number of sources j in [lo, hi) with A_j + j < k (the predicate is true on
+// a prefix), found by rounds of 64 probes, one per lane.
+__device__ inline i64 wave_search(const AFun &f, i64 k, i64 lo, i64 hi)
+{
+    const int lane = threadIdx.x & 63;
+    while (hi > lo) {
+        const i64 len = hi - lo;
+        const i64 stride = (len + 63) / 64;
+        const i64 pos = lo + (i64)lane * stride;
+        const bool t = pos < hi ? f.pred(pos, k) : false;
+        const int c = __popcll(__ballot(t));
+        if (c == 0) {
+            hi = lo;
+            break;
+        }
+        const i64 nlo = lo + (i64)(c - 1) * stride + 1;
+        i64 nhi = lo + (i64)c * stride;
+        if (nhi > hi) nhi = hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    return lo;
+}
+
+// Chooses the A function of this call; false if nothing may be written.
+__device__ inline bool make_afun(const Ctrl *ctrl, const u64 *pref, i64 n, int count_mode,
+                                 AFun &f, bool report)
+{
+    f.n = n;
+    f.pref = pref;
+    f.S = 1;
+    f.U = 0;
+    f.invS = 1.0;
+    if (count_mode) {
+        if (ctrl->ncopy_bad || pref[n - 1] != (u64)n) {
+            if (report) {
+                Ctrl *c = const_cast<Ctrl *>(ctrl);
+                c->err_call = kErrArg;
+                if (!c->err_latch) c->err_latch = kErrArg;
+            }
+            return false;
+        }
+        f.mode = 2;
+        return true;
+    }
+    if (!ctrl->pending || ctrl->err_call) return false;
+    f.mode = ctrl->resample ? 1 : 0;
+    f.S = ctrl->S;
+    f.U = ctrl->U;
+    f.invS = 1.0 / (double)ctrl->S;
+    return true;
+}
+
+template <int VEC>
+struct VecT;
+template <>
+struct VecT<16> {
+    typedef uint4 T;
+};
+template <>
+struct VecT<8> {
+    typedef uint2 T;
+};
+template <>
+struct VecT<4> {
+    typedef unsigned T;
+};
+
+// Copies np rows [p0, p0 + np) of dst from rows sAnc[] of src, VEC bytes per
+// lane access; consecutive lanes write consecutive addresses.
+template <int VEC>
+__device__ inline void copy_rows(const unsigned char *__restrict__ src,
+                                 unsigned char *__restrict__ dst, int row_bytes, int cpr_shift,
+                                 const unsigned *sAnc, i64 p0, int np)
+{
+    typedef typename VecT<VEC>::T V;
+    const int cpr = row_bytes / VEC;
+    const int total = np * cpr;
+    const int tid = threadIdx.x;
+    constexpr int U = 4;
+    int c = tid;
+    for (; c + (U - 1) * kExpandThreads < total; c += U * kExpandThreads) {
+        V v[U];
+        i64 doff[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int cc = c + u * kExpandThreads;
+            int r, col;
+            if (cpr_shift >= 0) {
+                r = cc >> cpr_shift;
+                col = cc & (cpr - 1);
+            } else {
+                r = cc / cpr;
+                col = cc - r * cpr;
+            }
+            v[u] = *reinterpret_cast<const V *>(src + (i64)sAnc[r] * row_bytes + col * VEC);
+            doff[u] = (p0 + r) * (i64)row_bytes + col * VEC;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) *reinterpret_cast<V *>(dst + doff[u]) = v[u];
+    }
+    for (; c < total; c += kExpandThreads) {
+        int r, col;
+        if (cpr_shift >= 0) {
+            r = c >> cpr_shift;
+            col = c & (cpr - 1);
+        } else {
+            r = c / cpr;
+            col = c - r * cpr;
+        }
+        const V v = *reinterpret_cast<const V *>(src + (i64)sAnc[r] * row_bytes + col * VEC);
+        *reinterpret_cast<V *>(dst + (p0 + r) * (i64)row_bytes + col * VEC) = v;
+    }
+}
+
+struct ExpandArgs {
+    i64 n;
+    const u64 *pref;
+    const Ctrl *ctrl;
+    int count_mode;
+    const unsigned char *x;
+    unsigned char *xo;
+    int row_bytes, cpr_shift;
+    const unsigned char *aux;
+    unsigned char *auxo;
+    int aux_bytes, aux_shift;
+    i64 *nc_out;
+    i64 *anc_out;
+};
+
+template <int VEC>
+__global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
+{
+    __shared__ unsigned sA[kSegLen + 1];
+    __shared__ unsigned sAnc[kSegLen];
+    __shared__ i64 s_j[2];
+    const int tid = threadIdx.x, wid = tid >> 6;
+    AFun f;
+    if (!make_afun(a.ctrl, a.pref, a.n, a.count_mode, f, blockIdx.x == 0 && tid == 0)) return;
+
+    const i64 n = a.n;
+    const i64 k0 = (i64)blockIdx.x * kSegLen;
+    const i64 k1 = (k0 + kSegLen < 2 * n) ? k0 + kSegLen : 2 * n;
+    if (wid < 2) {
+        const i64 k = wid == 0 ? k0 : k1;
+        const i64 lo = k - n > 0 ? k - n : 0;
+        const i64 hi = k < n ? k : n;
+        const i64 j = wave_search(f, k, lo, hi);
+        if ((tid & 63) == 0) s_j[wid] = j;
+    }
+    __syncthreads();
+    const i64 j0 = s_j[0], j1 = s_j[1];
+    const i64 p0 = k0 - j0;
+    const int ns = (int)(j1 - j0), np = (int)((k1 - j1) - p0);
+
+    for (int i = tid; i <= ns; i += kExpandThreads) {
+        const i64 j = j0 - 1 + i;
+        sA[i] = j < 0 ? 0u : (unsigned)f.A(j);
+    }
+    __syncthreads();
+    if (a.nc_out)
+        for (int i = tid; i < ns; i += kExpandThreads)
+            a.nc_out[j0 + i] = (i64)sA[i + 1] - (i64)sA[i];
+    for (int i = tid; i < np; i += kExpandThreads) {
+        const unsigned p = (unsigned)(p0 + i);
+        int lo = 0, hi = ns;  // first t with sA[1 + t] > p
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (sA[1 + mid] <= p) lo = mid + 1;
+            else hi = mid;
+        }
+        i64 anc = j0 + lo;
+        anc = anc < n ? anc : n - 1;
+        sAnc[i] = (unsigned)anc;
+        if (a.anc_out) a.anc_out[p0 + i] = anc;
+    }
+    __syncthreads();
+    copy_rows<VEC>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np);
+    if (a.aux) copy_rows<8>(a.aux, a.auxo, a.aux_bytes, a.aux_shift, sAnc, p0, np);
+}
+
+static int shift_of(int v)
+{
+    if (v <= 0 || (v & (v - 1))) return -1;
+    int s = 0;
+    while ((1 << s) < v) ++s;
+    return s;
+}
+
+hipError_t launch_expand(const Work &w, int64_t n, int count_mode, const void *x, void *x_out,
+                         int row_bytes, const void *aux, void *aux_out, int aux_bytes,
+                         int64_t *ncopies_out, int64_t *anc_out, hipStream_t s)
+{
+    ExpandArgs a;
+    a.n = n;
+    a.pref = w.pref;
+    a.ctrl = w.ctrl;
+    a.count_mode = count_mode;
+    a.x = reinterpret_cast<const unsigned char *>(x);
+    a.xo = reinterpret_cast<unsigned char *>(x_out);
+    a.row_bytes = row_bytes;
+    a.aux = reinterpret_cast<const unsigned char *>(aux);
+    a.auxo = reinterpret_cast<unsigned char *>(aux_out);
+    a.aux_bytes = aux_bytes;
+    a.aux_shift = shift_of(aux_bytes / 8);
+    a.nc_out = reinterpret_cast<i64 *>(ncopies_out);
+    a.anc_out = reinterpret_cast<i64 *>(anc_out);
+    const uintptr_t al = (uintptr_t)x | (uintptr_t)x_out | (uintptr_t)row_bytes;
+    const int64_t segs = (2 * n + kSegLen - 1) / kSegLen;
+    if ((al & 15) == 0) {
+        a.cpr_shift = shift_of(row_bytes / 16);
+        hipLaunchKernelGGL(k_expand<16>, dim3((unsigned)segs), dim3(kExpandThreads), 0, s, a);
+    } else if ((al & 7) == 0) {
+        a.cpr_shift = shift_of(row_bytes / 8);
+        hipLaunchKernelGGL(k_expand<8>, dim3((unsigned)segs), dim3(kExpandThreads), 0, s, a);
+    } else {
+        a.cpr_shift = shift_of(row_bytes / 4);
+        hipLaunchKernelGGL(k_expand<4>, dim3((unsigned)segs), dim3(kExpandThreads), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+// ncopies_j = A_j - A_{j-1} for every source (elementwise).
+__global__ __launch_bounds__(256) void k_ncopies(const Ctrl *ctrl, const u64 *pref, i64 n,
+                                                 int count_mode, i64 *nc)
+{
+    AFun f;
+    if (!make_afun(ctrl, pref, n, count_mode, f, false)) return;
+    const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
+    for (i64 j = gtid; j < n; j += gsz) {
+        const u64 a1 = f.A(j);
+        const u64 a0 = j > 0 ? f.A(j - 1) : 0;
+        nc[j] = (i64)(a1 - a0);
+    }
+}
+
+hipError_t launch_ncopies(const Work &w, int64_t n, int count_mode, int64_t *ncopies,
+                          hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    blocks = blocks > 4096 ? 4096 : blocks;
+    hipLaunchKernelGGL(k_ncopies, dim3((unsigned)blocks), dim3(256), 0, s, w.ctrl, w.pref, (i64)n,
+                       count_mode, reinterpret_cast<i64 *>(ncopies));
+    return hipGetLastError();
+}
+
+}  // namespace smc

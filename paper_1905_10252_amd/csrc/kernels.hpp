@@ -1,0 +1,64 @@
+// Host-side launchers of the libsmc kernels (one translation unit per kernel
+// family).  Every launcher enqueues on `s` and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace smc {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kTile = kScanThreads * kScanItems;  // 4096 elements per scan tile
+constexpr int kMaxBlocks = 1024;                  // grid of the max / reweight passes
+constexpr int kExpandThreads = 256;
+constexpr int kSegLen = 2048;                     // merge-path steps per expand workgroup
+
+struct TilePart {
+    double Z, Z2;
+    u64 q2lo, q2hi;
+};
+
+// Device pointers into the caller's workspace.
+struct Work {
+    Ctrl *ctrl;
+    u64 *blk_key;       // [kMaxBlocks] per-block max keys
+    unsigned *blk_bad;  // [kMaxBlocks] per-block non-finite flags
+    u64 *status;        // [n_tiles] lookback words
+    TilePart *tpart;    // [n_tiles]
+    u64 *pref;          // [n] inclusive prefix (S_j, or A_j for foreign counts)
+    // sampler state (NULL when no target)
+    double *lp;         // [n] cached log-target of the current particles
+    double *lp_new;     // [n] proposal log-target (costly targets)
+    double *x_scr;      // [n * d] redistribute destination
+    double *lp_scr;     // [n]
+    double *is_part;    // [kMaxBlocks * (2 + 2d)] per-block estimate sums
+    double *rec_num;    // [2d] recycled estimate sums
+    int n_tiles;
+};
+
+inline int n_tiles_of(int64_t n) { return (int)((n + kTile - 1) / kTile); }
+inline int max_blocks_of(int64_t n)
+{
+    int64_t b = (n + 2 * 256 * 8 - 1) / (2 * 256 * 8);
+    return (int)(b < 1 ? 1 : (b > kMaxBlocks ? kMaxBlocks : b));
+}
+
+struct InfoOut;  // smc_resample_info, written by the finalize kernels
+
+hipError_t launch_init_ctrl(const Work &w, hipStream_t s);
+hipError_t launch_max(const Work &w, const double *lw, int64_t n, hipStream_t s);
+hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, hipStream_t s);
+hipError_t launch_finalize_resample(const Work &w, int64_t n, uint64_t r, int mode, int ess_num,
+                                    int ess_den, int K, void *info, hipStream_t s);
+hipError_t launch_clear_scan(const Work &w, hipStream_t s);
+hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, hipStream_t s);
+hipError_t launch_ncopies(const Work &w, int64_t n, int count_mode, int64_t *ncopies,
+                          hipStream_t s);
+hipError_t launch_expand(const Work &w, int64_t n, int count_mode, const void *x, void *x_out,
+                         int row_bytes, const void *aux, void *aux_out, int aux_bytes,
+                         int64_t *ncopies_out, int64_t *anc_out, hipStream_t s);
+
+}  // namespace smc

@@ -1,0 +1,262 @@
+// libsmc C ABI: argument checking, workspace layout and the launch sequence
+// of each entry point.  No entry point allocates device memory or
+// synchronises (except smc_sync_error); everything is enqueued on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "../../include/smc.h"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "step.hpp"
+
+using namespace smc;
+
+struct smc_ctx {
+    smc_config cfg;
+    Work w;
+    void *ws;
+    size_t ws_bytes;
+    int K;
+    bool pending;   // the workspace prefix belongs to the last smc_resample
+    uint32_t t;     // sampler iteration counter (Alg 2 t)
+};
+
+namespace {
+
+struct Layout {
+    size_t ctrl, blk_key, blk_bad, status, tpart, pref;
+    size_t lp, lp_new, x_scr, lp_scr, is_part, rec_num;
+    size_t total;
+};
+
+bool config_ok(const smc_config *c)
+{
+    if (!c) return false;
+    if (c->n < 1 || c->n > 0x7fffffffLL) return false;
+    if (c->d < 1) return false;
+    if (c->x_dtype != SMC_DTYPE_F32 && c->x_dtype != SMC_DTYPE_F64) return false;
+    if (c->ess_num < 0 || c->ess_num > 16 || c->ess_den < 1 || c->ess_den > 16) return false;
+    if (c->mode < SMC_MODE_AUTO || c->mode > SMC_MODE_NEVER) return false;
+    if (c->target < SMC_TARGET_NONE || c->target > SMC_TARGET_LOGREG) return false;
+    if (c->target != SMC_TARGET_NONE) {
+        if (c->d > kMaxDim || c->x_dtype != SMC_DTYPE_F64) return false;
+        if (!(c->rw_sd >= 0.0) || !(c->init_sd > 0.0)) return false;
+        if (c->target == SMC_TARGET_GAUSS && (!c->mean || !c->prec)) return false;
+        if (c->target == SMC_TARGET_STUDENT && (c->d != 1 || !(c->nu > 0.0))) return false;
+        if (c->target == SMC_TARGET_LOGREG &&
+            (!c->X || !c->y || c->m_rows < 1 || !(c->prior_prec > 0.0) ||
+             (c->loglik_precision != SMC_PREC_F64 && c->loglik_precision != SMC_PREC_BF16)))
+            return false;
+    }
+    return true;
+}
+
+Layout layout_of(const smc_config *c)
+{
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t n = (size_t)c->n, d = (size_t)c->d;
+    const size_t nt = (size_t)n_tiles_of(c->n);
+    L.ctrl = take(sizeof(Ctrl));
+    L.blk_key = take(8 * kMaxBlocks);
+    L.blk_bad = take(4 * kMaxBlocks);
+    L.status = take(8 * nt);
+    L.tpart = take(sizeof(TilePart) * nt);
+    L.pref = take(8 * n);
+    L.lp = L.lp_new = L.x_scr = L.lp_scr = L.is_part = L.rec_num = 0;
+    if (c->target != SMC_TARGET_NONE) {
+        L.lp = take(8 * n);
+        L.lp_new = take(8 * n);
+        L.x_scr = take(8 * n * d);
+        L.lp_scr = take(8 * n);
+        L.is_part = take(8 * (size_t)kMaxBlocks * (2 + 2 * d));
+        L.rec_num = take(8 * 2 * d);
+    }
+    L.total = off;
+    return L;
+}
+
+inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool overlap(const void *a, const void *b, size_t bytes)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bytes && y < x + bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *smc_status_string(smc_status s)
+{
+    switch (s) {
+    case SMC_OK: return "ok";
+    case SMC_E_ARG: return "invalid argument";
+    case SMC_E_NONFINITE: return "non-finite log-weight (NaN or +inf)";
+    case SMC_E_DEGENERATE: return "all weights are zero";
+    case SMC_E_NOMEM: return "workspace too small";
+    case SMC_E_DEVICE: return "HIP runtime error";
+    case SMC_E_UNSUPPORTED: return "unsupported configuration";
+    }
+    return "unknown status";
+}
+
+size_t smc_workspace_bytes(const smc_config *h_cfg)
+{
+    if (!config_ok(h_cfg)) return 0;
+    return layout_of(h_cfg).total;
+}
+
+smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
+                    size_t workspace_bytes, void *x, double *logw, void *stream)
+{
+    if (!h_out) return SMC_E_ARG;
+    *h_out = nullptr;
+    if (!config_ok(h_cfg) || !workspace || ((uintptr_t)workspace & 255)) return SMC_E_ARG;
+    const Layout L = layout_of(h_cfg);
+    if (workspace_bytes < L.total) return SMC_E_NOMEM;
+    if (h_cfg->target != SMC_TARGET_NONE && (!x || !logw)) return SMC_E_ARG;
+    smc_ctx *ctx = new (std::nothrow) smc_ctx;
+    if (!ctx) return SMC_E_NOMEM;
+    ctx->cfg = *h_cfg;
+    ctx->ws = workspace;
+    ctx->ws_bytes = workspace_bytes;
+    ctx->pending = false;
+    ctx->t = 0;
+    {
+        int c = 0;
+        while ((1LL << c) < h_cfg->n) ++c;
+        ctx->K = 61 - c < 52 ? 61 - c : 52;
+    }
+    unsigned char *b = reinterpret_cast<unsigned char *>(workspace);
+    Work &w = ctx->w;
+    w.ctrl = reinterpret_cast<Ctrl *>(b + L.ctrl);
+    w.blk_key = reinterpret_cast<u64 *>(b + L.blk_key);
+    w.blk_bad = reinterpret_cast<unsigned *>(b + L.blk_bad);
+    w.status = reinterpret_cast<u64 *>(b + L.status);
+    w.tpart = reinterpret_cast<TilePart *>(b + L.tpart);
+    w.pref = reinterpret_cast<u64 *>(b + L.pref);
+    w.n_tiles = n_tiles_of(h_cfg->n);
+    const bool samp = h_cfg->target != SMC_TARGET_NONE;
+    w.lp = samp ? reinterpret_cast<double *>(b + L.lp) : nullptr;
+    w.lp_new = samp ? reinterpret_cast<double *>(b + L.lp_new) : nullptr;
+    w.x_scr = samp ? reinterpret_cast<double *>(b + L.x_scr) : nullptr;
+    w.lp_scr = samp ? reinterpret_cast<double *>(b + L.lp_scr) : nullptr;
+    w.is_part = samp ? reinterpret_cast<double *>(b + L.is_part) : nullptr;
+    w.rec_num = samp ? reinterpret_cast<double *>(b + L.rec_num) : nullptr;
+    if (launch_init_ctrl(w, S(stream)) != hipSuccess) {
+        delete ctx;
+        return SMC_E_DEVICE;
+    }
+    if (samp) {
+        const smc_status st = step_init(ctx->cfg, w, reinterpret_cast<double *>(x), logw,
+                                        S(stream));
+        if (st != SMC_OK) {
+            delete ctx;
+            return st;
+        }
+    }
+    *h_out = ctx;
+    return SMC_OK;
+}
+
+smc_status smc_resample(smc_ctx *ctx, const double *logw, int64_t n, uint64_t r, int32_t mode,
+                        int64_t *ncopies, smc_resample_info *info, void *stream)
+{
+    if (!ctx || !logw || n != ctx->cfg.n) return SMC_E_ARG;
+    if (mode < SMC_MODE_AUTO || mode > SMC_MODE_NEVER) return SMC_E_ARG;
+    if (((uintptr_t)logw & 7) || ((uintptr_t)ncopies & 7) || ((uintptr_t)info & 7))
+        return SMC_E_ARG;
+    const Work &w = ctx->w;
+    hipStream_t s = S(stream);
+    if (launch_max(w, logw, n, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_quant_scan(w, logw, n, ctx->K, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_finalize_resample(w, n, r, mode, ctx->cfg.ess_num, ctx->cfg.ess_den, ctx->K, info,
+                                 s) != hipSuccess)
+        return SMC_E_DEVICE;
+    ctx->pending = true;
+    if (ncopies && launch_ncopies(w, n, 0, ncopies, s) != hipSuccess) return SMC_E_DEVICE;
+    return SMC_OK;
+}
+
+smc_status smc_redistribute(smc_ctx *ctx, const int64_t *ncopies, const void *x, void *x_out,
+                            int64_t n, int32_t row_bytes, int64_t *ncopies_out, int64_t *anc,
+                            void *stream)
+{
+    if (!ctx || !x || !x_out || n != ctx->cfg.n) return SMC_E_ARG;
+    if (row_bytes <= 0 || (row_bytes & 3)) return SMC_E_ARG;
+    if (((uintptr_t)x & 3) || ((uintptr_t)x_out & 3)) return SMC_E_ARG;
+    if (((uintptr_t)ncopies & 7) || ((uintptr_t)ncopies_out & 7) || ((uintptr_t)anc & 7))
+        return SMC_E_ARG;
+    if ((uint64_t)n * (uint64_t)row_bytes > (1ull << 46)) return SMC_E_ARG;
+    if (overlap(x, x_out, (size_t)n * (size_t)row_bytes)) return SMC_E_ARG;
+    if (!ncopies && !ctx->pending) return SMC_E_ARG;
+    const Work &w = ctx->w;
+    hipStream_t s = S(stream);
+    int count_mode = 0;
+    if (ncopies) {
+        if (launch_clear_scan(w, s) != hipSuccess) return SMC_E_DEVICE;
+        if (launch_count_scan(w, ncopies, n, s) != hipSuccess) return SMC_E_DEVICE;
+        ctx->pending = false;
+        count_mode = 1;
+    }
+    if (launch_expand(w, n, count_mode, x, x_out, row_bytes, nullptr, nullptr, 0, ncopies_out, anc,
+                      s) != hipSuccess)
+        return SMC_E_DEVICE;
+    return SMC_OK;
+}
+
+smc_status smc_step(smc_ctx *ctx, void *x, double *logw, smc_resample_info *info, double *est,
+                    void *stream)
+{
+    if (!ctx || !x || !logw || ctx->cfg.target == SMC_TARGET_NONE) return SMC_E_ARG;
+    if (((uintptr_t)x & 7) || ((uintptr_t)logw & 7) || ((uintptr_t)info & 7) ||
+        ((uintptr_t)est & 7))
+        return SMC_E_ARG;
+    ctx->t += 1;
+    const smc_status st = step_run(ctx->cfg, ctx->w, ctx->K, ctx->t, reinterpret_cast<double *>(x),
+                                   logw, info, est, S(stream));
+    ctx->pending = false;  // the step reuses the prefix buffer
+    return st;
+}
+
+smc_status smc_log_target(smc_ctx *ctx, const double *x, int64_t n, double *lp, void *stream)
+{
+    if (!ctx || !x || !lp || n < 1 || ctx->cfg.target == SMC_TARGET_NONE) return SMC_E_ARG;
+    return step_log_target(ctx->cfg, ctx->w, x, n, lp, S(stream));
+}
+
+smc_status smc_sync_error(smc_ctx *ctx, void *stream)
+{
+    if (!ctx) return SMC_E_ARG;
+    if (hipStreamSynchronize(S(stream)) != hipSuccess) return SMC_E_DEVICE;
+    unsigned err = 0;
+    if (hipMemcpy(&err, &ctx->w.ctrl->err_latch, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess)
+        return SMC_E_DEVICE;
+    if (err) {
+        const unsigned zero = 0;
+        if (hipMemcpy(&ctx->w.ctrl->err_latch, &zero, sizeof(zero), hipMemcpyHostToDevice) !=
+            hipSuccess)
+            return SMC_E_DEVICE;
+    }
+    return (smc_status)err;
+}
+
+smc_status smc_destroy(smc_ctx *ctx)
+{
+    delete ctx;
+    return SMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,20 @@
+// Sampler (Alg 2) launch sequences: initialisation, one iteration, and the
+// batch log-target evaluation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/smc.h"
+#include "kernels.hpp"
+
+namespace smc {
+
+constexpr int kMaxDim = 64;
+
+smc_status step_init(const smc_config &cfg, const Work &w, double *x, double *logw, hipStream_t s);
+smc_status step_run(const smc_config &cfg, const Work &w, int K, uint32_t t, double *x,
+                    double *logw, smc_resample_info *info, double *est, hipStream_t s);
+smc_status step_log_target(const smc_config &cfg, const Work &w, const double *x, int64_t n,
+                           double *lp, hipStream_t s);
+
+}  // namespace smc

@@ -1,0 +1,206 @@
+"""GPU parity of smc_resample + smc_redistribute against the CPU oracle.
+
+Integer outputs (ncopies, ancestors, redistributed rows, S, U, sum q^2,
+decision) must be bit-exact; FP64 outputs (log Z, ESS) within 1e-12 relative.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_10252_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def smc(dev):
+    from paper_1905_10252_amd import smc as S
+    return S
+
+
+def run_gpu(smc, dev, lw, x, r, mode, ncopies=True, anc=True):
+    import torch
+    n = lw.size
+    R = smc.Resampler(n, device=dev)
+    tlw = torch.from_numpy(lw).to(dev)
+    tx = torch.from_numpy(x).to(dev)
+    nc = torch.full((n,), -7, dtype=torch.int64, device=dev)
+    an = torch.full((n,), -7, dtype=torch.int64, device=dev) if anc else None
+    R.resample(tlw, r, mode)
+    xo = R.redistribute(tx, ncopies_out=nc, anc=an)
+    torch.cuda.synchronize()
+    info = R.info()
+    return (xo.cpu().numpy(), nc.cpu().numpy(), None if an is None else an.cpu().numpy(), info, R)
+
+
+def compare(lw, x, r, mode, smc, dev):
+    xo, nc, an, info, _ = run_gpu(smc, dev, lw, x, r, mode)
+    onc, oinfo = O.resample(lw, r, mode)
+    assert info["err"] == oinfo["err"] == 0
+    for k in ("S", "U", "Q2_hi", "Q2_lo", "K", "resampled"):
+        assert info[k] == oinfo[k], (k, info[k], oinfo[k])
+    assert info["m"] == oinfo["m"]
+    assert abs(info["logZ"] - oinfo["logZ"]) <= RTOL * max(1.0, abs(oinfo["logZ"]))
+    assert abs(info["ess"] - oinfo["ess"]) <= RTOL * oinfo["ess"]
+    assert np.array_equal(nc, onc)
+    ox, oanc = O.redistribute(onc, x)
+    assert np.array_equal(an, oanc)
+    assert np.array_equal(xo.view(np.uint8), ox.view(np.uint8))
+    return oinfo
+
+
+SIZES = [1, 2, 3, 5, 64, 1023, 4096, 4097, 3 * 4096 + 17, 65537, (1 << 20) + 7]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("s", I.RESAMPLE_SCALES)
+def test_resample_parity_forced(smc, dev, n, s):
+    _say("case n=%d s=%g" % (n, s))
+    lw = I.logw_normal(n, s, 1000 + n)
+    x = I.particles(n, 3, 2000 + n)
+    compare(lw, x, I.offset_word(3000 + n), O.MODE_FORCE, smc, dev)
+
+
+@pytest.mark.parametrize("n", [7, 4097, 100000])
+@pytest.mark.parametrize("s", [0.1, 0.5, 0.83, 2.0])
+def test_resample_parity_auto(smc, dev, n, s):
+    _say("case auto n=%d s=%g" % (n, s))
+    lw = I.logw_normal(n, s, 11 + n)
+    x = I.particles(n, 2, 12 + n, dtype=np.float64)
+    compare(lw, x, I.offset_word(13), O.MODE_AUTO, smc, dev)
+
+
+@pytest.mark.parametrize("row", [1, 2, 3, 5, 16, 64])
+def test_row_widths(smc, dev, row):
+    n = 9000
+    lw = I.logw_normal(n, 2.0, 5)
+    x = I.particles(n, row, 6)
+    compare(lw, x, 99, O.MODE_FORCE, smc, dev)
+
+
+def test_never_is_identity(smc, dev):
+    n = 5000
+    lw = I.logw_normal(n, 8.0, 5)
+    x = I.particles(n, 4, 6)
+    xo, nc, an, info, _ = run_gpu(smc, dev, lw, x, 1, O.MODE_NEVER)
+    assert info["resampled"] == 0
+    assert np.all(nc == 1) and np.array_equal(an, np.arange(n))
+    assert np.array_equal(xo, x)
+
+
+def test_equal_and_single_weights(smc, dev):
+    n = 777
+    x = I.particles(n, 2, 1)
+    compare(np.full(n, 1.5), x, 5, O.MODE_FORCE, smc, dev)
+    compare(np.full(n, 1.5), x, 5, O.MODE_AUTO, smc, dev)
+    lw = np.full(n, -np.inf)
+    lw[400] = -3.0
+    info = compare(lw, x, 5, O.MODE_AUTO, smc, dev)
+    assert info["resampled"] == 1
+
+
+def test_heavy_tail_with_minus_inf(smc, dev):
+    n = 70000
+    lw = I.logw_normal(n, 8.0, 21)
+    lw[::3] = -np.inf
+    compare(lw, I.particles(n, 4, 22), 2**64 - 1, O.MODE_FORCE, smc, dev)
+    compare(lw, I.particles(n, 4, 22), 0, O.MODE_FORCE, smc, dev)
+
+
+@pytest.mark.parametrize("bad,code", [(np.nan, O.E_NONFINITE), (np.inf, O.E_NONFINITE)])
+def test_nonfinite_reported(smc, dev, bad, code):
+    import torch
+    n = 5000
+    lw = I.logw_normal(n, 1.0, 3)
+    lw[1234] = bad
+    x = I.particles(n, 2, 4)
+    R = smc.Resampler(n, device=dev)
+    tx = torch.from_numpy(x).to(dev)
+    xo = torch.zeros_like(tx)
+    R.resample(torch.from_numpy(lw).to(dev), 1, O.MODE_FORCE)
+    R.redistribute(tx, xo)
+    torch.cuda.synchronize()
+    assert R.info()["err"] == code
+    assert np.all(xo.cpu().numpy() == 0)  # nothing written
+    assert R.sync_error() == code
+    assert R.sync_error() == 0  # cleared
+
+
+def test_all_zero_weights_reported(smc, dev):
+    import torch
+    n = 100
+    R = smc.Resampler(n, device=dev)
+    R.resample(torch.full((n,), -math.inf, dtype=torch.float64, device=dev), 1)
+    torch.cuda.synchronize()
+    assert R.info()["err"] == O.E_DEGENERATE
+    assert R.sync_error() == O.E_DEGENERATE
+
+
+def test_foreign_ncopies(smc, dev):
+    import torch
+    rng = np.random.default_rng(7)
+    for n in [1, 10, 4097, 200003]:
+        q = rng.integers(0, 3, n).astype(np.uint64)
+        q[0] += 1
+        onc = O.systematic_ncopies(q, int(rng.integers(0, int(q.sum()))))
+        x = I.particles(n, 5, n)
+        R = smc.Resampler(n, device=dev)
+        an = torch.zeros(n, dtype=torch.int64, device=dev)
+        xo = R.redistribute(torch.from_numpy(x).to(dev),
+                            ncopies=torch.from_numpy(onc).to(dev), anc=an)
+        ox, oanc = O.redistribute(onc, x)
+        assert np.array_equal(xo.cpu().numpy(), ox)
+        assert np.array_equal(an.cpu().numpy(), oanc)
+        assert R.sync_error() == 0
+
+
+def test_foreign_ncopies_rejected(smc, dev):
+    import torch
+    n = 1000
+    x = torch.ones((n, 2), dtype=torch.float32, device=dev)
+    R = smc.Resampler(n, device=dev)
+    neg = np.ones(n, dtype=np.int64)
+    neg[0], neg[1] = -1, 3  # sums to N but has a negative count
+    for nc in (np.full(n, 2), neg):
+        xo = torch.zeros_like(x)
+        R.redistribute(x, xo, ncopies=torch.from_numpy(nc.astype(np.int64)).to(dev))
+        torch.cuda.synchronize()
+        assert np.all(xo.cpu().numpy() == 0)
+        assert R.sync_error() == O.E_ARG
+
+
+def test_repeat_calls_are_independent(smc, dev):
+    import torch
+    n = 30000
+    R = smc.Resampler(n, device=dev)
+    x = I.particles(n, 4, 1)
+    tx = torch.from_numpy(x).to(dev)
+    for it, s in enumerate([8.0, 0.5, 2.0, 8.0]):
+        lw = I.logw_normal(n, s, 40 + it)
+        nc = torch.zeros(n, dtype=torch.int64, device=dev)
+        R.resample(torch.from_numpy(lw).to(dev), 1000 + it, O.MODE_FORCE, ncopies=nc)
+        xo = R.redistribute(tx)
+        onc, _ = O.resample(lw, 1000 + it, O.MODE_FORCE)
+        assert np.array_equal(nc.cpu().numpy(), onc)
+        assert np.array_equal(xo.cpu().numpy(), O.redistribute(onc, x)[0])
+
+
+@pytest.mark.parametrize("s", I.RESAMPLE_SCALES)
+def test_full_size_parity(smc, dev, s):
+    """N = 2^24, d = 16 FP32: the configuration the benchmark times."""
+    n, d = I.RESAMPLE_N, I.RESAMPLE_D
+    _say("full-size case s=%g" % s)
+    lw = I.logw_normal(n, s, I.LOGW_SEEDS[s])
+    x = I.particles(n, d, I.X_SEED)
+    oinfo = compare(lw, x, I.offset_word(I.R_SEED), O.MODE_FORCE, smc, dev)
+    _say("  unique survivors %d of %d" % (oinfo["unique"], n))
