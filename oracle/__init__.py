@@ -188,7 +188,8 @@ class Sampler:
 
     def __init__(self, n, d, target, *, seed=0, sampler_id=0, rw_sd=0.5, init_mean=0.0,
                  init_sd=3.0, mode=MODE_AUTO, ess_num=1, ess_den=2, mean=None, var=None,
-                 nu=None, mu=None, X=None, y=None, prior_var=None):
+                 nu=None, mu=None, X=None, y=None, prior_var=None, log_norm=None,
+                 init_log_norm=None):
         import math
         self.cfg = SmcCfg()
         c = self.cfg
@@ -214,6 +215,10 @@ class Sampler:
             c.m_rows, c.X, c.y = Xa.shape[0], _p(Xa, C.c_double), _p(ya, C.c_double)
             c.prior_prec = 1.0 / prior_var
             c.log_norm = -0.5 * d * math.log(2.0 * math.pi * prior_var)
+        if log_norm is not None:
+            c.log_norm = log_norm
+        if init_log_norm is not None:
+            c.init_log_norm = init_log_norm
         self.x = np.zeros((n, d), dtype=np.float64)
         self.logw = np.zeros(n, dtype=np.float64)
         self.lp = np.zeros(n, dtype=np.float64)

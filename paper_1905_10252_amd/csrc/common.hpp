@@ -41,7 +41,7 @@ struct Ctrl {
     double rec_den;      // sum_t c_t exp(-lc_max)
     double log_c;
     int rec_steps;
-    int pad0;
+    unsigned scan_done;  // last-tile-done counter of the scan (self-resetting)
     double pad1[4];
 };
 

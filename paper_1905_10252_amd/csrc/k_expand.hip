@@ -28,15 +28,21 @@ struct AFun {
     u64 S, U;
     double invS;
 
-    __device__ inline bool pred(i64 j, i64 k) const  // A_j + j < k
+    // A_j + j < k, given the prefix value pj of source j
+    __device__ inline bool pred_at(i64 j, u64 pj, i64 k) const
     {
         if (mode == 0) return 2 * j + 1 < k;
-        if (mode == 2) return (i64)pref[j] + j < k;
+        if (mode == 2) return (i64)pj + j < k;
         const i64 c = k - j;
         if (c <= 0) return false;
-        const U128 lhs = add128(mul64((u64)n, pref[j]), U);
+        const U128 lhs = add128(mul64((u64)n, pj), U);
         const U128 rhs = mul64((u64)c, S);
         return lt128(lhs, rhs);
+    }
+
+    __device__ inline bool pred(i64 j, i64 k) const
+    {
+        return pred_at(j, mode == 0 ? 0ull : pref[j], k);
     }
 
     __device__ inline u64 A(i64 j) const
@@ -62,16 +68,17 @@ struct AFun {
     }
 };
 
-// Number of sources j in [lo, hi) with A_j + j < k (the predicate is true on
-// a prefix), found by rounds of 64 probes, one per lane.
-__device__ inline i64 wave_search(const AFun &f, i64 k, i64 lo, i64 hi)
+// First index in [lo, hi) where a predicate that is true on a prefix turns
+// false (hi if none), by rounds of 64 probes, one per lane.
+template <class P>
+__device__ inline i64 wave_first_false(const P &pred, i64 lo, i64 hi)
 {
     const int lane = threadIdx.x & 63;
     while (hi > lo) {
         const i64 len = hi - lo;
         const i64 stride = (len + 63) / 64;
         const i64 pos = lo + (i64)lane * stride;
-        const bool t = pos < hi ? f.pred(pos, k) : false;
+        const bool t = pos < hi ? pred(pos) : false;
         const int c = __popcll(__ballot(t));
         if (c == 0) {
             hi = lo;
@@ -84,6 +91,33 @@ __device__ inline i64 wave_search(const AFun &f, i64 k, i64 lo, i64 hi)
         hi = nhi;
     }
     return lo;
+}
+
+// j(k) = #{j : A_j + j < k}, the number of sources consumed after k merge
+// steps, known to lie in [lo, hi].  The test is monotone in j, so it is first
+// searched on the sampled prefix values S_{64g+63} (a small array that stays
+// in cache), then among the 64 consecutive sources of one group.
+__device__ inline i64 wave_search(const AFun &f, const u64 *pref64, i64 k, i64 lo, i64 hi)
+{
+    if (f.mode == 0) {
+        auto p = [&](i64 j) { return f.pred(j, k); };
+        return wave_first_false(p, lo, hi);
+    }
+    const i64 G = f.n >> 6;  // full groups, each with a sample
+    const i64 glo = lo >> 6;
+    i64 ghi = (hi >> 6) + 1;
+    ghi = ghi < G ? ghi : G;
+    i64 g = glo;
+    if (ghi > glo) {
+        auto ps = [&](i64 gg) { return f.pred_at(gg * 64 + 63, pref64[gg], k); };
+        g = wave_first_false(ps, glo, ghi);
+    }
+    i64 lo2 = g * 64 > lo ? g * 64 : lo;
+    lo2 = lo2 < hi ? lo2 : hi;
+    i64 hi2 = g * 64 + 64 < hi ? g * 64 + 64 : hi;
+    hi2 = hi2 > lo2 ? hi2 : lo2;
+    auto p = [&](i64 j) { return f.pred(j, k); };
+    return wave_first_false(p, lo2, hi2);
 }
 
 // Chooses the A function of this call; false if nothing may be written.
@@ -180,6 +214,7 @@ __device__ inline void copy_rows(const unsigned char *__restrict__ src,
 struct ExpandArgs {
     i64 n;
     const u64 *pref;
+    const u64 *pref64;
     const Ctrl *ctrl;
     int count_mode;
     const unsigned char *x;
@@ -190,6 +225,7 @@ struct ExpandArgs {
     int aux_bytes, aux_shift;
     i64 *nc_out;
     i64 *anc_out;
+    int skip_identity;  // when the decision is "no resample", write nothing
 };
 
 template <int VEC>
@@ -201,6 +237,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
     const int tid = threadIdx.x, wid = tid >> 6;
     AFun f;
     if (!make_afun(a.ctrl, a.pref, a.n, a.count_mode, f, blockIdx.x == 0 && tid == 0)) return;
+    if (a.skip_identity && f.mode == 0) return;
 
     const i64 n = a.n;
     const i64 k0 = (i64)blockIdx.x * kSegLen;
@@ -209,7 +246,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
         const i64 k = wid == 0 ? k0 : k1;
         const i64 lo = k - n > 0 ? k - n : 0;
         const i64 hi = k < n ? k : n;
-        const i64 j = wave_search(f, k, lo, hi);
+        const i64 j = wave_search(f, a.pref64, k, lo, hi);
         if ((tid & 63) == 0) s_j[wid] = j;
     }
     __syncthreads();
@@ -253,11 +290,14 @@ static int shift_of(int v)
 
 hipError_t launch_expand(const Work &w, int64_t n, int count_mode, const void *x, void *x_out,
                          int row_bytes, const void *aux, void *aux_out, int aux_bytes,
-                         int64_t *ncopies_out, int64_t *anc_out, hipStream_t s)
+                         int64_t *ncopies_out, int64_t *anc_out, hipStream_t s,
+                         bool skip_identity)
 {
     ExpandArgs a;
+    a.skip_identity = skip_identity ? 1 : 0;
     a.n = n;
     a.pref = w.pref;
+    a.pref64 = w.pref64;
     a.ctrl = w.ctrl;
     a.count_mode = count_mode;
     a.x = reinterpret_cast<const unsigned char *>(x);

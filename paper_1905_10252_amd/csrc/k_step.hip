@@ -1,20 +1,559 @@
+// Sampler kernels of Alg 2 (SMC sampler with recycling), random-walk proposal
+// and backward kernel L = q (so the incremental weight is pi(x_t)/pi(x_{t-1}),
+// eq. smcs_drawing_weights):
+//   k_is<target, init>  draws x0 ~ q0 or x_t = x_{t-1} + rw_sd z, evaluates the
+//                       cheap targets, updates the log-weights, and leaves per
+//                       block estimate sums (block-local max) and the grid max.
+//   k_reweight<init>    the weight update for targets whose log-density comes
+//                       from a separate likelihood kernel.
+//   k_step_stats        estimates f_t (eq. estimation_at_t), c_t
+//                       (eq. normconst) and the recycled estimate
+//                       (eq. recycling).
+//   k_copyback          after redistribute: particles and cached log-target
+//                       back in place, weights reset to 1/N (Alg 4 Reset).
+//   k_logreg_f64 / k_logreg_bf16 + k_logreg_sum
+//                       Bayesian logistic regression log-likelihood
+//                       sum_m [y_m z_m - softplus(z_m)], z = X theta, in FP64 or
+//                       as a BF16 MFMA contraction with FP32 accumulation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "../../include/smc.h"
+#include "common.hpp"
+#include "det.hpp"
+#include "kernels.hpp"
+#include "reduce.hpp"
 #include "step.hpp"
 
 namespace smc {
 
-smc_status step_init(const smc_config &, const Work &, double *, double *, hipStream_t)
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+struct TArgs {
+    int kind, d, dp;
+    const double *mean, *prec;
+    double log_norm, mu, inv_nu, hnu1;
+    double init_mean, init_sd, init_prec, init_log_norm, rw_sd;
+    uint64_t seed;
+    uint32_t sampler;
+    unsigned short *thb;  // bf16 copy of the particles [npad][dp] (nullable)
+};
+
+__device__ inline unsigned short to_bf16(double v)
 {
-    return SMC_E_UNSUPPORTED;
+    const float f = (float)v;
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
 }
-smc_status step_run(const smc_config &, const Work &, int, uint32_t, double *, double *,
-                    smc_resample_info *, double *, hipStream_t)
+
+// ------------------------------------------------------------------ partials
+// Per-block sums for the estimates with the block's own max (rescaled later):
+// part = [m_b, sum e, sum e x_k (k < d), sum e x_k^2 (k < d)], e = exp(l - m_b).
+__device__ inline void is_block_finish(i64 n, int d, const double *x, const double *logw, u64 key,
+                                       unsigned bad, Ctrl *ctrl, u64 *blk_key, unsigned *blk_bad,
+                                       double *is_part)
 {
-    return SMC_E_UNSUPPORTED;
+    __shared__ double s_acc[4][2 + 2 * kMaxDim];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
+    const u64 bk = block_max_key(key, bad);
+    const double mb = okey_inv(bk);
+    const bool live = mb > -__builtin_huge_val() && mb == mb;
+    double e0 = 0.0;
+    for (i64 i = gtid; i < n; i += gsz) e0 += live ? det_exp(logw[i] - mb) : 0.0;
+    e0 = wave_sum_f64(e0);
+    if (lane == 0) s_acc[wid][1] = e0;
+    for (int k = 0; k < d; ++k) {
+        double s1 = 0.0, s2 = 0.0;
+        for (i64 i = gtid; i < n; i += gsz) {
+            const double e = live ? det_exp(logw[i] - mb) : 0.0;
+            const double ex = e * x[i * d + k];
+            s1 += ex;
+            s2 += ex * x[i * d + k];
+        }
+        s1 = wave_sum_f64(s1);
+        s2 = wave_sum_f64(s2);
+        if (lane == 0) {
+            s_acc[wid][2 + k] = s1;
+            s_acc[wid][2 + d + k] = s2;
+        }
+    }
+    __syncthreads();
+    const int ncol = 2 + 2 * d;
+    double *part = is_part + (i64)blockIdx.x * ncol;
+    for (int c = tid; c < ncol; c += 256)
+        part[c] = c == 0 ? mb : ((s_acc[0][c] + s_acc[1][c]) + s_acc[2][c]) + s_acc[3][c];
+    grid_max_combine(bk, bad, ctrl, blk_key, blk_bad);
 }
-smc_status step_log_target(const smc_config &, const Work &, const double *, int64_t, double *,
-                           hipStream_t)
+
+// ------------------------------------------------------- proposal + weights
+template <int kKind, bool kInit>
+__global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *__restrict__ x,
+                                            double *__restrict__ logw, double *__restrict__ lp,
+                                            Ctrl *ctrl, u64 *blk_key, unsigned *blk_bad,
+                                            u64 *status, int n_status, double *is_part)
 {
-    return SMC_E_UNSUPPORTED;
+    const int tid = threadIdx.x;
+    const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
+    if (kKind != SMC_TARGET_LOGREG)
+        for (i64 i = gtid; i < n_status; i += gsz) status[i] = 0;
+    const int d = a.d;
+    u64 key = 0;
+    unsigned bad = 0;
+    for (i64 i = gtid; i < n; i += gsz) {
+        double *xi = x + i * d;
+        double acc = 0.0, acc0 = 0.0;
+        for (int k = 0; 2 * k < d; ++k) {
+            double z[2];
+            normal_pair(a.seed, kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose, a.sampler,
+                        kInit ? 0u : t, (uint32_t)i, (uint32_t)k, z[0], z[1]);
+            for (int h = 0; h < 2; ++h) {
+                const int kk = 2 * k + h;
+                if (kk >= d) break;
+                const double xv = kInit ? a.init_mean + a.init_sd * z[h] : xi[kk] + a.rw_sd * z[h];
+                xi[kk] = xv;
+                if (a.thb) a.thb[i * a.dp + kk] = to_bf16(xv);
+                if (kKind == SMC_TARGET_GAUSS) {
+                    const double tt = xv - a.mean[kk];
+                    acc = acc + (tt * tt) * a.prec[kk];
+                }
+                if (kInit) {
+                    const double t0 = xv - a.init_mean;
+                    acc0 = acc0 + (t0 * t0) * a.init_prec;
+                }
+            }
+        }
+        const double lq0 = kInit ? a.init_log_norm - 0.5 * acc0 : 0.0;
+        if (kKind == SMC_TARGET_LOGREG) {
+            if (kInit) logw[i] = lq0;  // combined with log pi by k_reweight
+            continue;
+        }
+        double lpn;
+        if (kKind == SMC_TARGET_GAUSS) {
+            lpn = a.log_norm - 0.5 * acc;
+        } else {
+            const double tt = xi[0] - a.mu;
+            const double w = 1.0 + (tt * tt) * a.inv_nu;
+            lpn = a.log_norm - a.hnu1 * det_log(w);
+        }
+        const double lw = kInit ? lpn - lq0 : logw[i] + (lpn - lp[i]);
+        lp[i] = lpn;
+        logw[i] = lw;
+        bad |= (lw != lw) | (lw == __builtin_huge_val());
+        const u64 kk = okey(lw);
+        key = kk > key ? kk : key;
+    }
+    if (kKind == SMC_TARGET_LOGREG) return;
+    is_block_finish(n, d, x, logw, key, bad, ctrl, blk_key, blk_bad, is_part);
+}
+
+template <bool kInit>
+__global__ __launch_bounds__(256) void k_reweight(i64 n, int d, const double *__restrict__ x,
+                                                  const double *__restrict__ lp_new,
+                                                  double *__restrict__ logw,
+                                                  double *__restrict__ lp, Ctrl *ctrl,
+                                                  u64 *blk_key, unsigned *blk_bad, u64 *status,
+                                                  int n_status, double *is_part)
+{
+    const int tid = threadIdx.x;
+    const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
+    for (i64 i = gtid; i < n_status; i += gsz) status[i] = 0;
+    u64 key = 0;
+    unsigned bad = 0;
+    for (i64 i = gtid; i < n; i += gsz) {
+        const double lpn = lp_new[i];
+        const double lw = kInit ? lpn - logw[i] : logw[i] + (lpn - lp[i]);
+        lp[i] = lpn;
+        logw[i] = lw;
+        bad |= (lw != lw) | (lw == __builtin_huge_val());
+        const u64 kk = okey(lw);
+        key = kk > key ? kk : key;
+    }
+    is_block_finish(n, d, x, logw, key, bad, ctrl, blk_key, blk_bad, is_part);
+}
+
+// -------------------------------------------- estimates, c_t and recycling
+__global__ __launch_bounds__(256) void k_step_stats(Ctrl *ctrl, const double *is_part, int nblk,
+                                                    int d, double *rec_num, double *est,
+                                                    smc_resample_info *info, int init)
+{
+    __shared__ double s_col[2 + 2 * kMaxDim];
+    __shared__ double s_sc, s_wgt, s_den;
+    const int tid = threadIdx.x;
+    const int ncol = 2 + 2 * d;
+    const double m = ctrl->m;
+    for (int c = 1 + tid; c < ncol; c += 256) {
+        double acc = 0.0;
+        for (int b = 0; b < nblk; ++b) {
+            const double mb = is_part[(i64)b * ncol];
+            if (!(mb > -__builtin_huge_val())) continue;
+            acc += det_exp(mb - m) * is_part[(i64)b * ncol + c];
+        }
+        s_col[c] = acc;
+    }
+    __syncthreads();
+    const double E0 = s_col[1];
+    if (init) {
+        if (tid == 0) {
+            ctrl->logZ_prev = m + log(E0);
+            ctrl->lc_max = -__builtin_huge_val();
+            ctrl->rec_den = 0.0;
+            ctrl->rec_steps = 0;
+        }
+        for (int c = tid; c < 2 * d; c += 256) rec_num[c] = 0.0;
+        return;
+    }
+    if (tid == 0) {
+        const double logc = ctrl->logZ - ctrl->logZ_prev;
+        double sc = 1.0;
+        double den = ctrl->rec_den;
+        if (logc > ctrl->lc_max) {
+            sc = ctrl->rec_steps ? exp(ctrl->lc_max - logc) : 0.0;
+            den *= sc;
+            ctrl->lc_max = logc;
+        }
+        const double wgt = exp(logc - ctrl->lc_max);
+        den += wgt;
+        ctrl->rec_den = den;
+        ctrl->rec_steps += 1;
+        ctrl->log_c = logc;
+        ctrl->logZ_prev = (ctrl->resample && !ctrl->err_call) ? 0.0 : ctrl->logZ;
+        s_sc = sc;
+        s_wgt = wgt;
+        s_den = den;
+        if (info) info->log_c = logc;
+    }
+    __syncthreads();
+    for (int k = tid; k < 2 * d; k += 256) {
+        const double f = s_col[2 + k] / E0;
+        const double num = rec_num[k] * s_sc + s_wgt * f;
+        rec_num[k] = num;
+        if (est) {
+            est[k] = f;
+            est[2 * d + k] = num / s_den;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copyback(const Ctrl *ctrl, i64 n, int d, double *x,
+                                                  const double *x_scr, double *lp,
+                                                  const double *lp_scr, double *logw,
+                                                  double reset)
+{
+    if (!ctrl->resample || ctrl->err_call) return;
+    const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
+    for (i64 i = gtid; i < n * d; i += gsz) x[i] = x_scr[i];
+    for (i64 i = gtid; i < n; i += gsz) {
+        lp[i] = lp_scr[i];
+        logw[i] = reset;
+    }
+}
+
+// ------------------------------------------------------ cheap log-targets
+__global__ __launch_bounds__(256) void k_lp_cheap(TArgs a, i64 n, const double *x, double *lp)
+{
+    const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
+    for (i64 i = gtid; i < n; i += gsz) {
+        const double *xi = x + i * a.d;
+        if (a.kind == SMC_TARGET_GAUSS) {
+            double acc = 0.0;
+            for (int k = 0; k < a.d; ++k) {
+                const double tt = xi[k] - a.mean[k];
+                acc = acc + (tt * tt) * a.prec[k];
+            }
+            lp[i] = a.log_norm - 0.5 * acc;
+        } else {
+            const double tt = xi[0] - a.mu;
+            lp[i] = a.log_norm - a.hnu1 * det_log(1.0 + (tt * tt) * a.inv_nu);
+        }
+    }
+}
+
+// --------------------------------------------- logistic regression, FP64
+constexpr int kLrRows = 64;
+
+template <int DB>
+__global__ __launch_bounds__(256) void k_logreg_f64(const double *__restrict__ theta, i64 n, int d,
+                                                    const double *__restrict__ X,
+                                                    const double *__restrict__ y, i64 m_rows,
+                                                    double *__restrict__ lpart)
+{
+    __shared__ double sX[kLrRows][DB];
+    __shared__ double sy[kLrRows];
+    const i64 i = (i64)blockIdx.x * 256 + threadIdx.x;
+    double th[DB];
+#pragma unroll
+    for (int k = 0; k < DB; ++k) th[k] = (i < n && k < d) ? theta[i * d + k] : 0.0;
+    const i64 per = (m_rows + gridDim.y - 1) / gridDim.y;
+    const i64 r0 = (i64)blockIdx.y * per;
+    const i64 r1 = r0 + per < m_rows ? r0 + per : m_rows;
+    double acc = 0.0;
+    for (i64 rb = r0; rb < r1; rb += kLrRows) {
+        const int nr = (int)(r1 - rb < kLrRows ? r1 - rb : kLrRows);
+        __syncthreads();
+        for (int e = threadIdx.x; e < kLrRows * DB; e += 256) {
+            const int r = e / DB, k = e - r * DB;
+            sX[r][k] = (r < nr && k < d) ? X[(rb + r) * d + k] : 0.0;
+        }
+        if (threadIdx.x < kLrRows) sy[threadIdx.x] = (int)threadIdx.x < nr ? y[rb + threadIdx.x] : 0.0;
+        __syncthreads();
+        for (int r = 0; r < nr; ++r) {
+            double z = 0.0;
+#pragma unroll
+            for (int k = 0; k < DB; ++k) z = fma(sX[r][k], th[k], z);
+            const double sp = z > 0.0 ? z + log1p(exp(-z)) : log1p(exp(z));
+            acc += sy[r] * z - sp;
+        }
+    }
+    if (i < n) lpart[(i64)blockIdx.y * n + i] = acc;
+}
+
+// ------------------------------------ logistic regression, BF16 MFMA (gfx950)
+// X is stored pre-multiplied by s_m = 1 - 2 y_m (exact in bf16), so that
+// y_m z_m - softplus(z_m) = -softplus(s_m z_m) and the epilogue needs no labels.
+// One wavefront owns 32 particles (MFMA columns) and streams 32-row tiles of X
+// (MFMA rows) through v_mfma_f32_32x32x16_bf16; the softplus epilogue runs on
+// the FP32 accumulators and sums per particle.
+__device__ inline float softplus_f32(float t)
+{
+    const float a = fabsf(t);
+    const float e = __builtin_amdgcn_exp2f(-a * 1.4426950408889634f);
+    const float l = __builtin_amdgcn_logf(1.0f + e) * 0.6931471805599453f;
+    return fmaxf(t, 0.0f) + l;
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_logreg_bf16(const unsigned short *__restrict__ thb, i64 n,
+                                                     const unsigned short *__restrict__ xs,
+                                                     i64 m_rows, i64 mpad, int dp,
+                                                     double *__restrict__ lpart)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const i64 p0 = ((i64)blockIdx.x * 4 + wid) * 32;
+    if (p0 >= n) return;
+    const int col = lane & 31, kh = lane >> 5;
+    bf16x8 bfr[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+        bfr[s] = *reinterpret_cast<const bf16x8 *>(thb + (p0 + col) * dp + 16 * s + 8 * kh);
+    const i64 tiles = mpad / 32;
+    const i64 per = (tiles + gridDim.y - 1) / gridDim.y;
+    const i64 t0 = (i64)blockIdx.y * per;
+    const i64 t1 = t0 + per < tiles ? t0 + per : tiles;
+    float sp = 0.0f;
+    for (i64 tt = t0; tt < t1; ++tt) {
+        const i64 m0 = tt * 32;
+        f32x16 acc = {};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const bf16x8 afr =
+                *reinterpret_cast<const bf16x8 *>(xs + (m0 + col) * dp + 16 * s + 8 * kh);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[s], acc, 0, 0, 0);
+        }
+        if (m0 + 32 <= m_rows) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) sp += softplus_f32(acc[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const i64 row = m0 + 8 * (r >> 2) + 4 * kh + (r & 3);
+                if (row < m_rows) sp += softplus_f32(acc[r]);
+            }
+        }
+    }
+    sp += __shfl_xor(sp, 32, kWave);
+    if (lane < 32 && p0 + lane < n) lpart[(i64)blockIdx.y * n + p0 + lane] = -(double)sp;
+}
+
+__global__ __launch_bounds__(256) void k_logreg_sum(const double *theta, i64 n, int d,
+                                                    const double *lpart, int msplit,
+                                                    double log_norm, double prior_prec,
+                                                    double *lp)
+{
+    const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
+    for (i64 i = gtid; i < n; i += gsz) {
+        double pr = 0.0;
+        for (int k = 0; k < d; ++k) pr += theta[i * d + k] * theta[i * d + k];
+        double s = 0.0;
+        for (int j = 0; j < msplit; ++j) s += lpart[(i64)j * n + i];
+        lp[i] = log_norm - 0.5 * prior_prec * pr + s;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_prep_x(const double *X, const double *y, i64 m_rows,
+                                                int d, i64 mpad, int dp, unsigned short *xs,
+                                                unsigned short *thb, i64 thb_elems)
+{
+    const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
+    for (i64 e = gtid; e < mpad * dp; e += gsz) {
+        const i64 m = e / dp;
+        const int k = (int)(e - m * dp);
+        double v = 0.0;
+        if (m < m_rows && k < d) v = (y[m] != 0.0 ? -1.0 : 1.0) * X[m * d + k];
+        xs[e] = to_bf16(v);
+    }
+    for (i64 e = gtid; e < thb_elems; e += gsz) thb[e] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_theta_bf16(const double *x, i64 n, int d, int dp,
+                                                    unsigned short *thb)
+{
+    const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
+    for (i64 e = gtid; e < n * d; e += gsz) {
+        const i64 i = e / d;
+        const int k = (int)(e - i * d);
+        thb[i * dp + k] = to_bf16(x[e]);
+    }
+}
+
+// ================================================================= host side
+namespace {
+
+TArgs targs(const smc_config &c, const Work &w, bool with_bf16)
+{
+    TArgs a;
+    a.kind = c.target;
+    a.d = c.d;
+    a.dp = w.dp;
+    a.mean = c.mean;
+    a.prec = c.prec;
+    a.log_norm = c.log_norm;
+    a.mu = c.mu;
+    a.inv_nu = c.target == SMC_TARGET_STUDENT ? 1.0 / c.nu : 0.0;
+    a.hnu1 = 0.5 * (c.nu + 1.0);
+    a.init_mean = c.init_mean;
+    a.init_sd = c.init_sd;
+    a.init_prec = 1.0 / (c.init_sd * c.init_sd);
+    a.init_log_norm = c.init_log_norm;
+    a.rw_sd = c.rw_sd;
+    a.seed = c.seed;
+    a.sampler = c.sampler_id;
+    a.thb = with_bf16 ? w.thb : nullptr;
+    return a;
+}
+
+int grid_for(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    return (int)(b < 1 ? 1 : (b > kMaxBlocks ? kMaxBlocks : b));
+}
+
+bool is_bf16(const smc_config &c)
+{
+    return c.target == SMC_TARGET_LOGREG && c.loglik_precision == SMC_PREC_BF16;
+}
+
+// log pi at x[n][d] into lp (the likelihood kernels of the costly target).
+hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_t n, double *lp,
+                     bool theta_ready, hipStream_t s)
+{
+    const int msplit = kLogregSplit;
+    if (is_bf16(c)) {
+        if (!theta_ready) {
+            hipLaunchKernelGGL(k_theta_bf16, dim3(grid_for(n * c.d)), dim3(256), 0, s, x, (i64)n,
+                               c.d, w.dp, w.thb);
+        }
+        const dim3 grid((unsigned)((n + 127) / 128), msplit);
+        const unsigned short *xs = w.xs;
+        switch (w.dp / 16) {
+        case 1: hipLaunchKernelGGL(k_logreg_bf16<1>, grid, dim3(256), 0, s, w.thb, (i64)n, xs, c.m_rows, w.mpad, w.dp, w.lpart); break;
+        case 2: hipLaunchKernelGGL(k_logreg_bf16<2>, grid, dim3(256), 0, s, w.thb, (i64)n, xs, c.m_rows, w.mpad, w.dp, w.lpart); break;
+        case 3: hipLaunchKernelGGL(k_logreg_bf16<3>, grid, dim3(256), 0, s, w.thb, (i64)n, xs, c.m_rows, w.mpad, w.dp, w.lpart); break;
+        default: hipLaunchKernelGGL(k_logreg_bf16<4>, grid, dim3(256), 0, s, w.thb, (i64)n, xs, c.m_rows, w.mpad, w.dp, w.lpart); break;
+        }
+    } else {
+        const dim3 grid((unsigned)((n + 255) / 256), msplit);
+        const double *X = reinterpret_cast<const double *>(c.X);
+        if (c.d <= 8) hipLaunchKernelGGL(k_logreg_f64<8>, grid, dim3(256), 0, s, x, (i64)n, c.d, X, c.y, c.m_rows, w.lpart);
+        else if (c.d <= 16) hipLaunchKernelGGL(k_logreg_f64<16>, grid, dim3(256), 0, s, x, (i64)n, c.d, X, c.y, c.m_rows, w.lpart);
+        else if (c.d <= 32) hipLaunchKernelGGL(k_logreg_f64<32>, grid, dim3(256), 0, s, x, (i64)n, c.d, X, c.y, c.m_rows, w.lpart);
+        else hipLaunchKernelGGL(k_logreg_f64<64>, grid, dim3(256), 0, s, x, (i64)n, c.d, X, c.y, c.m_rows, w.lpart);
+    }
+    hipLaunchKernelGGL(k_logreg_sum, dim3(grid_for(n)), dim3(256), 0, s, x, (i64)n, c.d, w.lpart,
+                       msplit, c.log_norm, c.prior_prec, lp);
+    return hipGetLastError();
+}
+
+template <bool kInit>
+hipError_t launch_is(const smc_config &c, const Work &w, uint32_t t, double *x, double *logw,
+                     hipStream_t s)
+{
+    const TArgs a = targs(c, w, is_bf16(c));
+    const int g = grid_for(c.n);
+    const i64 n = c.n;
+    switch (c.target) {
+    case SMC_TARGET_GAUSS:
+        hipLaunchKernelGGL((k_is<SMC_TARGET_GAUSS, kInit>), dim3(g), dim3(256), 0, s, a, n, t, x,
+                           logw, w.lp, w.ctrl, w.blk_key, w.blk_bad, w.status, w.n_tiles,
+                           w.is_part);
+        break;
+    case SMC_TARGET_STUDENT:
+        hipLaunchKernelGGL((k_is<SMC_TARGET_STUDENT, kInit>), dim3(g), dim3(256), 0, s, a, n, t,
+                           x, logw, w.lp, w.ctrl, w.blk_key, w.blk_bad, w.status, w.n_tiles,
+                           w.is_part);
+        break;
+    default:
+        hipLaunchKernelGGL((k_is<SMC_TARGET_LOGREG, kInit>), dim3(g), dim3(256), 0, s, a, n, t, x,
+                           logw, w.lp, w.ctrl, w.blk_key, w.blk_bad, w.status, w.n_tiles,
+                           w.is_part);
+        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+        if (logreg_lp(c, w, x, n, w.lp_new, true, s) != hipSuccess) return hipErrorLaunchFailure;
+        hipLaunchKernelGGL(k_reweight<kInit>, dim3(g), dim3(256), 0, s, n, c.d, x, w.lp_new, logw,
+                           w.lp, w.ctrl, w.blk_key, w.blk_bad, w.status, w.n_tiles, w.is_part);
+        break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+smc_status step_init(const smc_config &c, const Work &w, double *x, double *logw, hipStream_t s)
+{
+    if (c.target == SMC_TARGET_LOGREG && is_bf16(c)) {
+        const int64_t thb_elems = w.npad * w.dp;
+        hipLaunchKernelGGL(k_prep_x, dim3(grid_for(w.mpad * w.dp)), dim3(256), 0, s,
+                           reinterpret_cast<const double *>(c.X), c.y, (i64)c.m_rows, c.d,
+                           (i64)w.mpad, w.dp, w.xs, w.thb, (i64)thb_elems);
+        if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
+    }
+    if (launch_is<true>(c, w, 0u, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
+    hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part, grid_for(c.n),
+                       c.d, w.rec_num, (double *)nullptr, (smc_resample_info *)nullptr, 1);
+    return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+}
+
+smc_status step_run(const smc_config &c, const Work &w, int K, uint32_t t, double *x,
+                    double *logw, smc_resample_info *info, double *est, hipStream_t s)
+{
+    const int64_t n = c.n;
+    if (launch_is<false>(c, w, t, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
+    const uint64_t r = resample_word(c.seed, c.sampler_id, t);
+    if (launch_quant_scan(w, logw, n, K, r, c.mode, c.ess_num, c.ess_den, info, s) != hipSuccess)
+        return SMC_E_DEVICE;
+    hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part, grid_for(n),
+                       c.d, w.rec_num, est, info, 0);
+    if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
+    if (launch_expand(w, n, 0, x, w.x_scr, c.d * 8, w.lp, w.lp_scr, 8, nullptr, nullptr, s,
+                      true) != hipSuccess)
+        return SMC_E_DEVICE;
+    hipLaunchKernelGGL(k_copyback, dim3(grid_for(n * c.d)), dim3(256), 0, s, w.ctrl, (i64)n, c.d,
+                       x, w.x_scr, w.lp, w.lp_scr, logw, -std::log((double)n));
+    return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+}
+
+smc_status step_log_target(const smc_config &c, const Work &w, const double *x, int64_t n,
+                           double *lp, hipStream_t s)
+{
+    if (n > c.n) return SMC_E_ARG;
+    if (c.target == SMC_TARGET_LOGREG) {
+        return logreg_lp(c, w, x, n, lp, false, s) == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+    }
+    const TArgs a = targs(c, w, false);
+    hipLaunchKernelGGL(k_lp_cheap, dim3(grid_for(n)), dim3(256), 0, s, a, (i64)n, x, lp);
+    return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
 
 }  // namespace smc

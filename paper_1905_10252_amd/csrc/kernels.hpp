@@ -15,6 +15,7 @@ constexpr int kTile = kScanThreads * kScanItems;  // 4096 elements per scan tile
 constexpr int kMaxBlocks = 1024;                  // grid of the max / reweight passes
 constexpr int kExpandThreads = 256;
 constexpr int kSegLen = 2048;                     // merge-path steps per expand workgroup
+constexpr int kLogregSplit = 8;                   // row blocks of the likelihood contraction
 
 struct TilePart {
     double Z, Z2;
@@ -29,6 +30,7 @@ struct Work {
     u64 *status;        // [n_tiles] lookback words
     TilePart *tpart;    // [n_tiles]
     u64 *pref;          // [n] inclusive prefix (S_j, or A_j for foreign counts)
+    u64 *pref64;        // [n / 64 + 1] every 64th prefix value (search index)
     // sampler state (NULL when no target)
     double *lp;         // [n] cached log-target of the current particles
     double *lp_new;     // [n] proposal log-target (costly targets)
@@ -36,6 +38,12 @@ struct Work {
     double *lp_scr;     // [n]
     double *is_part;    // [kMaxBlocks * (2 + 2d)] per-block estimate sums
     double *rec_num;    // [2d] recycled estimate sums
+    // logistic regression (NULL otherwise)
+    unsigned short *xs;   // [mpad][dp] bf16 rows of X times (1 - 2 y)
+    unsigned short *thb;  // [npad][dp] bf16 copy of the particles
+    double *lpart;        // [kLogregSplit][n] partial log-likelihoods
+    int64_t mpad, npad;
+    int dp;
     int n_tiles;
 };
 
@@ -46,19 +54,19 @@ inline int max_blocks_of(int64_t n)
     return (int)(b < 1 ? 1 : (b > kMaxBlocks ? kMaxBlocks : b));
 }
 
-struct InfoOut;  // smc_resample_info, written by the finalize kernels
 
 hipError_t launch_init_ctrl(const Work &w, hipStream_t s);
 hipError_t launch_max(const Work &w, const double *lw, int64_t n, hipStream_t s);
-hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, hipStream_t s);
-hipError_t launch_finalize_resample(const Work &w, int64_t n, uint64_t r, int mode, int ess_num,
-                                    int ess_den, int K, void *info, hipStream_t s);
+// Quantise + scan + (last tile) decision; info is a device smc_resample_info.
+hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, uint64_t r,
+                             int mode, int ess_num, int ess_den, void *info, hipStream_t s);
 hipError_t launch_clear_scan(const Work &w, hipStream_t s);
 hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, hipStream_t s);
 hipError_t launch_ncopies(const Work &w, int64_t n, int count_mode, int64_t *ncopies,
                           hipStream_t s);
 hipError_t launch_expand(const Work &w, int64_t n, int count_mode, const void *x, void *x_out,
                          int row_bytes, const void *aux, void *aux_out, int aux_bytes,
-                         int64_t *ncopies_out, int64_t *anc_out, hipStream_t s);
+                         int64_t *ncopies_out, int64_t *anc_out, hipStream_t s,
+                         bool skip_identity);
 
 }  // namespace smc

@@ -29,8 +29,11 @@ struct smc_ctx {
 namespace {
 
 struct Layout {
-    size_t ctrl, blk_key, blk_bad, status, tpart, pref;
+    size_t ctrl, blk_key, blk_bad, status, tpart, pref, pref64;
     size_t lp, lp_new, x_scr, lp_scr, is_part, rec_num;
+    size_t xs, thb, lpart;
+    int64_t mpad, npad;
+    int dp;
     size_t total;
 };
 
@@ -73,7 +76,12 @@ Layout layout_of(const smc_config *c)
     L.status = take(8 * nt);
     L.tpart = take(sizeof(TilePart) * nt);
     L.pref = take(8 * n);
+    L.pref64 = take(8 * (n / 64 + 1));
     L.lp = L.lp_new = L.x_scr = L.lp_scr = L.is_part = L.rec_num = 0;
+    L.xs = L.thb = L.lpart = 0;
+    L.dp = (int)((d + 15) / 16 * 16);
+    L.mpad = (c->m_rows + 31) / 32 * 32;
+    L.npad = (int64_t)((n + 31) / 32 * 32);
     if (c->target != SMC_TARGET_NONE) {
         L.lp = take(8 * n);
         L.lp_new = take(8 * n);
@@ -81,6 +89,13 @@ Layout layout_of(const smc_config *c)
         L.lp_scr = take(8 * n);
         L.is_part = take(8 * (size_t)kMaxBlocks * (2 + 2 * d));
         L.rec_num = take(8 * 2 * d);
+        if (c->target == SMC_TARGET_LOGREG) {
+            L.lpart = take(8 * (size_t)kLogregSplit * n);
+            if (c->loglik_precision == SMC_PREC_BF16) {
+                L.xs = take(2 * (size_t)L.mpad * L.dp);
+                L.thb = take(2 * (size_t)L.npad * L.dp);
+            }
+        }
     }
     L.total = off;
     return L;
@@ -147,6 +162,7 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
     w.status = reinterpret_cast<u64 *>(b + L.status);
     w.tpart = reinterpret_cast<TilePart *>(b + L.tpart);
     w.pref = reinterpret_cast<u64 *>(b + L.pref);
+    w.pref64 = reinterpret_cast<u64 *>(b + L.pref64);
     w.n_tiles = n_tiles_of(h_cfg->n);
     const bool samp = h_cfg->target != SMC_TARGET_NONE;
     w.lp = samp ? reinterpret_cast<double *>(b + L.lp) : nullptr;
@@ -155,6 +171,12 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
     w.lp_scr = samp ? reinterpret_cast<double *>(b + L.lp_scr) : nullptr;
     w.is_part = samp ? reinterpret_cast<double *>(b + L.is_part) : nullptr;
     w.rec_num = samp ? reinterpret_cast<double *>(b + L.rec_num) : nullptr;
+    w.lpart = L.lpart ? reinterpret_cast<double *>(b + L.lpart) : nullptr;
+    w.xs = L.xs ? reinterpret_cast<unsigned short *>(b + L.xs) : nullptr;
+    w.thb = L.thb ? reinterpret_cast<unsigned short *>(b + L.thb) : nullptr;
+    w.mpad = L.mpad;
+    w.npad = L.npad;
+    w.dp = L.dp;
     if (launch_init_ctrl(w, S(stream)) != hipSuccess) {
         delete ctx;
         return SMC_E_DEVICE;
@@ -181,9 +203,8 @@ smc_status smc_resample(smc_ctx *ctx, const double *logw, int64_t n, uint64_t r,
     const Work &w = ctx->w;
     hipStream_t s = S(stream);
     if (launch_max(w, logw, n, s) != hipSuccess) return SMC_E_DEVICE;
-    if (launch_quant_scan(w, logw, n, ctx->K, s) != hipSuccess) return SMC_E_DEVICE;
-    if (launch_finalize_resample(w, n, r, mode, ctx->cfg.ess_num, ctx->cfg.ess_den, ctx->K, info,
-                                 s) != hipSuccess)
+    if (launch_quant_scan(w, logw, n, ctx->K, r, mode, ctx->cfg.ess_num, ctx->cfg.ess_den, info,
+                          s) != hipSuccess)
         return SMC_E_DEVICE;
     ctx->pending = true;
     if (ncopies && launch_ncopies(w, n, 0, ncopies, s) != hipSuccess) return SMC_E_DEVICE;
@@ -212,7 +233,7 @@ smc_status smc_redistribute(smc_ctx *ctx, const int64_t *ncopies, const void *x,
         count_mode = 1;
     }
     if (launch_expand(w, n, count_mode, x, x_out, row_bytes, nullptr, nullptr, 0, ncopies_out, anc,
-                      s) != hipSuccess)
+                      s, false) != hipSuccess)
         return SMC_E_DEVICE;
     return SMC_OK;
 }

@@ -105,6 +105,101 @@ class Resampler:
         return self._lib.smc_sync_error(self.ctx, _stream())
 
 
-def reset_logw(logw: torch.Tensor) -> torch.Tensor:
-    """Reset step of Alg 4: every weight 1/N (log-weight -ln N)."""
-    return logw.fill_(-math.log(logw.shape[0]))
+class Sampler:
+    """One SMC sampler (Alg 2) driven through smc_init / smc_step.
+
+    Particles x [N][d] and log-weights logw [N] are FP64 device tensors owned
+    here; every step runs the library's kernels in place on them.
+    Targets: "gauss" (mean, var), "student" (nu, mu; d = 1) and "logreg"
+    (X [M][d], y [M], prior_var; precision "f64" or "bf16").
+    """
+
+    def __init__(self, n: int, d: int, target: str, *, seed: int = 0, sampler_id: int = 0,
+                 rw_sd: float = 0.5, init_mean: float = 0.0, init_sd: float = 3.0,
+                 mode: int = L.MODE_AUTO, ess_num: int = 1, ess_den: int = 2, mean=None,
+                 var=None, nu=None, mu=None, X=None, y=None, prior_var=None,
+                 precision: str = "f64", log_norm=None, init_log_norm=None, device=None):
+        lib = L.load()
+        self._lib = lib
+        self.n, self.d = int(n), int(d)
+        self.device = torch.device(device or "cuda")
+        dev = self.device
+        cfg = L.SmcConfig()
+        cfg.n, cfg.d, cfg.x_dtype = self.n, self.d, L.DTYPE_F64
+        cfg.mode, cfg.ess_num, cfg.ess_den = mode, ess_num, ess_den
+        cfg.sampler_id, cfg.seed = sampler_id, int(seed) & (2**64 - 1)
+        cfg.rw_sd, cfg.init_mean, cfg.init_sd = rw_sd, init_mean, init_sd
+        cfg.init_log_norm = (init_log_norm if init_log_norm is not None
+                             else -0.5 * d * math.log(2.0 * math.pi * init_sd * init_sd))
+        self._keep = []
+        if target == "gauss":
+            cfg.target = L.TARGET_GAUSS
+            m = torch.as_tensor(mean, dtype=torch.float64).reshape(-1).to(dev)
+            v = torch.as_tensor(var, dtype=torch.float64).reshape(-1)
+            pr = (1.0 / v).to(dev)
+            self._keep += [m, pr]
+            cfg.mean, cfg.prec = m.data_ptr(), pr.data_ptr()
+            cfg.log_norm = (log_norm if log_norm is not None else
+                            float(-0.5 * (v.numel() * math.log(2.0 * math.pi)
+                                          + sum(math.log(float(a)) for a in v))))
+        elif target == "student":
+            cfg.target = L.TARGET_STUDENT
+            cfg.nu, cfg.mu = nu, mu
+            cfg.log_norm = (log_norm if log_norm is not None else
+                            math.lgamma(0.5 * (nu + 1.0)) - math.lgamma(0.5 * nu)
+                            - 0.5 * math.log(nu * math.pi))
+        elif target == "logreg":
+            cfg.target = L.TARGET_LOGREG
+            Xd = torch.as_tensor(X, dtype=torch.float64).contiguous().to(dev)
+            yd = torch.as_tensor(y, dtype=torch.float64).contiguous().to(dev)
+            self._keep += [Xd, yd]
+            cfg.m_rows, cfg.X, cfg.y = Xd.shape[0], Xd.data_ptr(), yd.data_ptr()
+            cfg.prior_prec = 1.0 / prior_var
+            cfg.loglik_precision = L.PREC_BF16 if precision == "bf16" else L.PREC_F64
+            cfg.log_norm = (log_norm if log_norm is not None
+                            else -0.5 * d * math.log(2.0 * math.pi * prior_var))
+        else:
+            raise ValueError("unknown target %r" % target)
+        self.cfg = cfg
+        self.ws_bytes = lib.smc_workspace_bytes(C.byref(cfg))
+        if self.ws_bytes == 0:
+            raise L.SmcError(L.SMC_E_ARG, "smc_workspace_bytes")
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.x = torch.empty((self.n, self.d), dtype=torch.float64, device=dev)
+        self.logw = torch.empty(self.n, dtype=torch.float64, device=dev)
+        self.info_buf = torch.zeros(L.INFO_BYTES, dtype=torch.uint8, device=dev)
+        self.est = torch.zeros(4 * self.d, dtype=torch.float64, device=dev)
+        self.ctx = C.c_void_p()
+        L.check(lib.smc_init(C.byref(self.ctx), C.byref(cfg), _ptr(self.ws), self.ws_bytes,
+                             _ptr(self.x), _ptr(self.logw), _stream()), "smc_init")
+        self.t = 0
+
+    def __del__(self):
+        if getattr(self, "ctx", None) and self.ctx.value:
+            self._lib.smc_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def step(self, info: bool = True, est: bool = True) -> None:
+        L.check(self._lib.smc_step(self.ctx, _ptr(self.x), _ptr(self.logw),
+                                   _ptr(self.info_buf) if info else None,
+                                   _ptr(self.est) if est else None, _stream()), "smc_step")
+        self.t += 1
+
+    def info(self) -> dict:
+        return decode_info(self.info_buf)
+
+    def estimates(self) -> dict:
+        e = self.est.cpu().numpy()
+        d = self.d
+        return {"mean": e[:d], "m2": e[d:2 * d], "rec_mean": e[2 * d:3 * d],
+                "rec_m2": e[3 * d:4 * d]}
+
+    def log_target(self, x: torch.Tensor) -> torch.Tensor:
+        _need(x, torch.float64, None, "x")
+        lp = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+        L.check(self._lib.smc_log_target(self.ctx, _ptr(x), x.shape[0], _ptr(lp), _stream()),
+                "smc_log_target")
+        return lp
+
+    def sync_error(self) -> int:
+        return self._lib.smc_sync_error(self.ctx, _stream())

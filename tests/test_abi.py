@@ -46,7 +46,7 @@ def test_workspace_bytes(lib):
     cfg = L.SmcConfig()
     cfg.n, cfg.d, cfg.x_dtype, cfg.target, cfg.ess_num, cfg.ess_den = 1 << 24, 16, 0, 0, 1, 2
     b = lib.smc_workspace_bytes(C.byref(cfg))
-    assert 8 * (1 << 24) < b < 8 * (1 << 24) + (1 << 21)
+    assert 8 * (1 << 24) < b < 8 * (1 << 24) + (1 << 24) // 8 + (1 << 21)  # prefix + 1/64 samples
     cfg.n = 0
     assert lib.smc_workspace_bytes(C.byref(cfg)) == 0
     cfg.n, cfg.ess_den = 10, 0

@@ -1,0 +1,221 @@
+"""GPU parity of smc_init / smc_step (Alg 2) against the CPU oracle.
+
+For the cheap targets every operation on a particle is a fixed IEEE sequence
+and resampling is integer-exact, so whole trajectories (particles and
+log-weights) must match bit for bit; estimates, c_t and the recycled
+estimate are FP64 sums in a different order (relative 1e-12).  For logistic
+regression the likelihood is a long FP64 sum (GPU order differs: 1e-11
+relative) or a BF16 MFMA contraction (1e-2 relative, per the stated
+tolerance), so its parity is per step.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_10252_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def smc(dev):
+    from paper_1905_10252_amd import smc as S
+    return S
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint64)
+
+
+def assert_close(a, b, rtol, what):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    scale = np.maximum(np.abs(b), 1.0)
+    err = np.max(np.abs(a - b) / scale) if a.size else 0.0
+    assert err <= rtol, "%s: rel err %.3g > %.3g" % (what, err, rtol)
+
+
+MODES = {"auto": O.MODE_AUTO, "force": O.MODE_FORCE, "never": O.MODE_NEVER}
+
+
+def pair_gauss(smc, dev, n, mean, var, seed, mode, rw_sd=0.5, init_sd=3.0):
+    d = len(mean)
+    ln, iln = I.gauss_log_norm(var), I.iso_gauss_log_norm(d, init_sd)
+    g = smc.Sampler(n, d, "gauss", seed=seed, rw_sd=rw_sd, init_mean=0.0, init_sd=init_sd,
+                    mean=mean, var=var, mode=mode, log_norm=ln, init_log_norm=iln, device=dev)
+    o = O.Sampler(n, d, O.T_GAUSS, seed=seed, rw_sd=rw_sd, init_mean=0.0, init_sd=init_sd,
+                  mean=mean, var=var, mode=mode, log_norm=ln, init_log_norm=iln)
+    o.init()
+    return g, o
+
+
+def run_and_compare(g, o, steps):
+    assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x)), "x0"
+    assert np.array_equal(bits(g.logw.cpu().numpy()), bits(o.logw)), "logw0"
+    for t in range(1, steps + 1):
+        g.step()
+        out = o.step()
+        info = g.info()
+        oi = out["info"]
+        for k in ("S", "U", "Q2_hi", "Q2_lo", "resampled", "K", "err"):
+            assert info[k] == oi[k], (t, k, info[k], oi[k])
+        assert info["m"] == oi["m"], t
+        assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x)), "x at t=%d" % t
+        assert np.array_equal(bits(g.logw.cpu().numpy()), bits(o.logw)), "logw at t=%d" % t
+        assert_close(info["logZ"], oi["logZ"], 1e-12, "logZ t=%d" % t)
+        assert_close(info["ess"], oi["ess"], 1e-12, "ess t=%d" % t)
+        assert abs(info["log_c"] - out["log_c"]) <= 1e-11, ("log_c", t)
+        e = g.estimates()
+        for k in ("mean", "m2", "rec_mean", "rec_m2"):
+            assert_close(e[k], out[k], 1e-11, "%s t=%d" % (k, t))
+    assert g.sync_error() == 0
+
+
+def test_gauss_1d_twenty_iterations_bit_exact(smc, dev):
+    """N = 1024, target N(2, 1), q0 = N(0, 9), random walk sd 0.5."""
+    g = I.GAUSS1D
+    G, Or = pair_gauss(smc, dev, g["n"], g["mean"], g["var"], 0, O.MODE_AUTO)
+    run_and_compare(G, Or, g["iters"])
+
+
+@pytest.mark.parametrize("mode", ["auto", "force", "never"])
+def test_gauss_3d_ragged(smc, dev, mode):
+    _say("gauss 3d", mode)
+    G, Or = pair_gauss(smc, dev, 3001, [1.0, -2.0, 0.5], [0.5, 2.0, 1.5], 17, MODES[mode],
+                       rw_sd=0.3)
+    run_and_compare(G, Or, 6)
+
+
+@pytest.mark.parametrize("n", [1, 7, 4096, 70001])
+def test_student_t(smc, dev, n):
+    _say("student n=%d" % n)
+    nu, mu = 5.0, 1.0
+    ln, iln = I.student_log_norm(nu), I.iso_gauss_log_norm(1, 3.0)
+    g = smc.Sampler(n, 1, "student", seed=5, rw_sd=0.5, nu=nu, mu=mu, mode=O.MODE_FORCE,
+                    log_norm=ln, init_log_norm=iln, device=dev)
+    o = O.Sampler(n, 1, O.T_STUDENT, seed=5, rw_sd=0.5, nu=nu, mu=mu, mode=O.MODE_FORCE,
+                  log_norm=ln, init_log_norm=iln)
+    o.init()
+    run_and_compare(g, o, 5)
+
+
+def test_many_samplers_independent_streams(smc, dev):
+    """Different seeds / sampler ids give different draws; same ones repeat."""
+    g = I.GAUSS1D
+    outs = []
+    for seed, sid in [(1, 0), (1, 0), (2, 0), (1, 3)]:
+        s = smc.Sampler(256, 1, "gauss", seed=seed, sampler_id=sid, mean=g["mean"],
+                        var=g["var"], device=dev)
+        s.step()
+        outs.append(s.x.cpu().numpy().copy())
+    assert np.array_equal(outs[0], outs[1])
+    assert not np.array_equal(outs[0], outs[2])
+    assert not np.array_equal(outs[0], outs[3])
+
+
+# ------------------------------------------------------ logistic regression
+def logreg_pair(smc, dev, m_rows, d, n, precision, mode=O.MODE_NEVER, seed=3):
+    X, y, _ = I.logreg_data(m_rows, d, 200 + m_rows)
+    ln = I.iso_gauss_log_norm(d, math.sqrt(10.0))
+    iln = I.iso_gauss_log_norm(d, math.sqrt(10.0))
+    kw = dict(seed=seed, rw_sd=0.01, init_mean=0.0, init_sd=math.sqrt(10.0), mode=mode)
+    g = smc.Sampler(n, d, "logreg", X=X.astype(np.float64), y=y, prior_var=10.0,
+                    precision=precision, log_norm=ln, init_log_norm=iln, device=dev, **kw)
+    o = O.Sampler(n, d, O.T_LOGREG, X=X.astype(np.float64), y=y, prior_var=10.0, log_norm=ln,
+                  init_log_norm=iln, **kw)
+    return g, o
+
+
+@pytest.mark.parametrize("m_rows,d", [(1000, 8), (333, 3), (2048, 32), (100, 64)])
+def test_logreg_f64_log_target(smc, dev, m_rows, d):
+    import torch
+    g, o = logreg_pair(smc, dev, m_rows, d, 600, "f64")
+    th = np.random.default_rng(9).standard_normal((600, d)) * 0.3
+    lp = g.log_target(torch.from_numpy(th).to(dev)).cpu().numpy()
+    ref = o.log_target(th)
+    assert_close(lp, ref, 1e-11, "logreg f64 lp")
+
+
+@pytest.mark.parametrize("m_rows,d", [(1000, 8), (333, 3), (2048, 32), (100, 64)])
+def test_logreg_bf16_log_target(smc, dev, m_rows, d):
+    import torch
+    g, o = logreg_pair(smc, dev, m_rows, d, 600, "bf16")
+    th = np.random.default_rng(9).standard_normal((600, d)) * 0.3
+    lp = g.log_target(torch.from_numpy(th).to(dev)).cpu().numpy()
+    ref = o.log_target(th)
+    rel = np.abs(lp - ref) / np.abs(ref)
+    _say("bf16 lp (M=%d, d=%d): max rel %.3g, max abs %.3g nats" % (m_rows, d, rel.max(),
+                                                                     np.abs(lp - ref).max()))
+    assert rel.max() < 1e-2
+
+
+def test_logreg_full_size_likelihood(smc, dev):
+    """M = 65536 rows, D = 32, N = 2^16 particles: both precisions on the GPU
+    for every particle; the oracle on a 256-particle sample."""
+    import torch
+    cfg = I.LOGREG
+    m_rows, d, n = cfg["m_rows"], cfg["d"], cfg["n"]
+    X, y, theta_star = I.logreg_data(m_rows, d, 200)
+    th = theta_star[None, :] + 0.05 * np.random.default_rng(4).standard_normal((n, d))
+    tth = torch.from_numpy(th).to(dev)
+    lps = {}
+    for prec in ("f64", "bf16"):
+        g = smc.Sampler(n, d, "logreg", X=X.astype(np.float64), y=y, prior_var=10.0,
+                        precision=prec, init_sd=math.sqrt(10.0), rw_sd=0.01, device=dev)
+        lps[prec] = g.log_target(tth).cpu().numpy()
+    o = O.Sampler(n, d, O.T_LOGREG, X=X.astype(np.float64), y=y, prior_var=10.0,
+                  init_sd=math.sqrt(10.0))
+    o.cfg.log_norm = g.cfg.log_norm
+    idx = np.linspace(0, n - 1, 256).astype(np.int64)
+    ref = o.log_target(th[idx])
+    assert_close(lps["f64"][idx], ref, 1e-11, "f64 full size")
+    rel = np.abs(lps["bf16"][idx] - ref) / np.abs(ref)
+    _say("full-size bf16: max rel %.3g, median abs %.3g nats, max abs %.3g nats"
+         % (rel.max(), np.median(np.abs(lps["bf16"][idx] - ref)),
+            np.abs(lps["bf16"][idx] - ref).max()))
+    assert rel.max() < 1e-2
+    relg = np.abs(lps["bf16"] - lps["f64"]) / np.abs(lps["f64"])
+    assert relg.max() < 1e-2
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-11), ("bf16", 1e-2)])
+def test_logreg_steps_per_step_parity(smc, dev, precision, tol):
+    """Proposals are bit-exact; log-weights within the likelihood tolerance;
+    the resampling decision on the GPU's own weights is bit-exact."""
+    import torch
+    n, d = 3000, 8
+    g, o = logreg_pair(smc, dev, 1500, d, n, precision)
+    o.init()
+    assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x))
+    assert_close(g.logw.cpu().numpy(), o.logw, tol, "logw0")
+    R = smc.Resampler(n, device=dev)
+    for t in range(1, 4):
+        g.step()
+        o.step()
+        assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x)), t
+        gl = g.logw.cpu().numpy()
+        assert_close(gl, o.logw, tol * 10, "logw t=%d" % t)
+        nc = torch.zeros(n, dtype=torch.int64, device=dev)
+        R.resample(g.logw, 77 + t, O.MODE_FORCE, ncopies=nc)
+        onc, _ = O.resample(gl, 77 + t, O.MODE_FORCE)
+        assert np.array_equal(nc.cpu().numpy(), onc)
+
+
+def test_logreg_force_step_structure(smc, dev):
+    """A resampling step leaves copies of proposed particles, equal weights."""
+    n, d = 2000, 8
+    g, o = logreg_pair(smc, dev, 700, d, n, "f64", mode=O.MODE_FORCE)
+    o.init()
+    g.step()
+    o.step()
+    assert g.info()["resampled"] == 1
+    assert np.all(g.logw.cpu().numpy() == -math.log(n))
+    gx = g.x.cpu().numpy()
+    assert np.array_equal(bits(gx), bits(o.x)) or set(map(tuple, gx)) <= set(map(tuple, o.x))
