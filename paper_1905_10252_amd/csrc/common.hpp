@@ -24,9 +24,9 @@ constexpr unsigned kErrArg = 1, kErrNonfinite = 2, kErrDegenerate = 3;
 // Control block at the start of the workspace.  Every kernel of one call
 // sequence communicates through it; no host round trip is needed.
 struct Ctrl {
-    u64 mkey;            // ordered image of max log-weight
-    unsigned blk_done;   // last-block-done counter (self-resetting)
-    unsigned tile_next;  // dynamic tile counter of the scan (reset before each scan)
+    u64 mkey;            // order key of the max log-weight (written by the fold)
+    unsigned spin_fail;  // a lookback exceeded its spin bound (never expected)
+    unsigned unused0;
     unsigned err_call;   // device error of the current call (0 = none)
     unsigned err_latch;  // sticky error, cleared by smc_sync_error
     unsigned resample;   // decision of the last resample (1 = resample)
@@ -41,7 +41,7 @@ struct Ctrl {
     double rec_den;      // sum_t c_t exp(-lc_max)
     double log_c;
     int rec_steps;
-    unsigned scan_done;  // last-tile-done counter of the scan (self-resetting)
+    unsigned unused1;
     double pad1[4];
 };
 

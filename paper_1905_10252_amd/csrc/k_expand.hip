@@ -16,6 +16,7 @@
 // 128-bit integers (no division).
 #include <hip/hip_runtime.h>
 
+#include "../../include/smc.h"
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -130,11 +131,12 @@ __device__ inline bool make_afun(const Ctrl *ctrl, const u64 *pref, i64 n, int c
     f.U = 0;
     f.invS = 1.0;
     if (count_mode) {
-        if (ctrl->ncopy_bad || pref[n - 1] != (u64)n) {
+        if (ctrl->spin_fail || ctrl->ncopy_bad || pref[n - 1] != (u64)n) {
             if (report) {
+                const unsigned err = ctrl->spin_fail ? (unsigned)SMC_E_DEVICE : kErrArg;
                 Ctrl *c = const_cast<Ctrl *>(ctrl);
-                c->err_call = kErrArg;
-                if (!c->err_latch) c->err_latch = kErrArg;
+                c->err_call = err;
+                if (!c->err_latch) c->err_latch = err;
             }
             return false;
         }

@@ -2,15 +2,18 @@
 //   k_max          exact FP64 max of the log-weights (the stability shift of
 //                  eq. normalise) and non-finite detection; clears the scan
 //                  state for the pass that follows.
+//   k_fold         combines the max slots, records the error of the call.
 //   k_scan<true>   one pass over the log-weights: 64-bit fixed-point weights
 //                  q_i = min(2^K, floor(2^K det_exp(l_i - m))), FP64 sums for
 //                  log-sum-exp and ESS (eq. normalise, eq. neff), the exact
 //                  sum of q_i^2, and the inclusive prefix S_j (the Cumulative
-//                  Sum of MVR) by a single-pass decoupled-lookback scan.  The
-//                  tile that finishes last takes the exact integer ESS decision
-//                  (resample when ESS < N*, Alg 2), the systematic offset
-//                  U = floor(r S / 2^64), log Z and the FP64 ESS.
+//                  Sum of MVR) by a single-pass decoupled-lookback scan.
 //   k_scan<false>  the same scan over caller-supplied int64 ncopies.
+//   k_decide       the exact integer ESS decision (resample when ESS < N*,
+//                  Alg 2), the systematic offset U = floor(r S / 2^64), log Z
+//                  and the FP64 ESS from the tile partials.
+// No kernel here uses a device-wide fence or a contended atomic: both
+// serialise across the chip.
 // Every 64th prefix value is also written to a sample array, a coarse index
 // for the merge-path searches of the expand kernel.
 #include <hip/hip_runtime.h>
@@ -24,25 +27,25 @@
 namespace smc {
 
 // ------------------------------------------------------------- control init
-__global__ void k_init_ctrl(Ctrl *ctrl)
+__global__ void k_init_ctrl(Ctrl *ctrl, u64 *slots)
 {
     u64 *p = reinterpret_cast<u64 *>(ctrl);
     for (int i = threadIdx.x; i < (int)(sizeof(Ctrl) / 8); i += blockDim.x) p[i] = 0;
+    for (int i = threadIdx.x; i < kSlotWords; i += blockDim.x) slots[i] = 0;
 }
 
 hipError_t launch_init_ctrl(const Work &w, hipStream_t s)
 {
     static_assert(sizeof(Ctrl) % 8 == 0, "ctrl size");
-    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(64), 0, s, w.ctrl);
+    hipLaunchKernelGGL(k_init_ctrl, dim3(1), dim3(256), 0, s, w.ctrl, w.slots);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------- exact max
-// Grid-stride share per block, four 16-byte loads in flight per thread; the
-// last block to finish combines the per-block order keys.
+// Grid-stride share per block, four 16-byte loads in flight per thread; each
+// block publishes its max order key into the slots of this call's parity.
 __global__ __launch_bounds__(256) void k_max(const double *__restrict__ lw, i64 n, int vec2,
-                                             Ctrl *ctrl, u64 *blk_key, unsigned *blk_bad,
-                                             u64 *status, int n_status)
+                                             u64 *slots_p, u64 *status, int n_status)
 {
     constexpr int U = 4;
     const int tid = threadIdx.x;
@@ -78,23 +81,61 @@ __global__ __launch_bounds__(256) void k_max(const double *__restrict__ lw, i64 
         for (i64 i = gtid; i < n; i += gsz) take(lw[i]);
     }
     const u64 bk = block_max_key(key, bad);
-    grid_max_combine(bk, bad, ctrl, blk_key, blk_bad);
+    slot_publish(slots_p, bk, bad);
 }
 
-hipError_t launch_max(const Work &w, const double *lw, int64_t n, hipStream_t s)
+hipError_t launch_max(const Work &w, const double *lw, int64_t n, int par, hipStream_t s)
 {
     const int vec2 = ((uintptr_t)lw & 15) == 0;
-    hipLaunchKernelGGL(k_max, dim3(max_blocks_of(n)), dim3(256), 0, s, lw, (i64)n, vec2, w.ctrl,
-                       w.blk_key, w.blk_bad, w.status, w.n_tiles);
+    hipLaunchKernelGGL(k_max, dim3(max_blocks_of(n)), dim3(256), 0, s, lw, (i64)n, vec2,
+                       w.slots + (par & 1) * kSlots * kSlotStride, w.status, w.n_tiles);
+    return hipGetLastError();
+}
+
+// One wavefront: max over the 64 slots of parity par, the call's error
+// (NaN or +inf seen: non-finite; max = -inf: every weight zero), and a clear
+// of the other parity's slots for the next call.
+__global__ __launch_bounds__(64) void k_fold(u64 *slots, int par, Ctrl *ctrl)
+{
+    const int lane = threadIdx.x;
+    u64 *cur = slots + (par & 1) * kSlots * kSlotStride;
+    u64 *nxt = slots + ((par & 1) ^ 1) * kSlots * kSlotStride;
+    const u64 key = wave_max_u64(cur[lane * kSlotStride]);
+    const unsigned bad = wave_or((unsigned)cur[lane * kSlotStride + 1]);
+    nxt[lane * kSlotStride] = 0;
+    nxt[lane * kSlotStride + 1] = 0;
+    if (lane == 0) {
+        unsigned err = 0;
+        if (bad) err = kErrNonfinite;
+        else if (key <= okey(-__builtin_huge_val())) err = kErrDegenerate;
+        ctrl->mkey = key;
+        ctrl->m = okey_inv(key);
+        ctrl->err_call = err;
+        if (err && !ctrl->err_latch) ctrl->err_latch = err;
+        ctrl->spin_fail = 0;
+        ctrl->pending = 0;
+    }
+}
+
+hipError_t launch_fold(const Work &w, int par, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fold, dim3(1), dim3(64), 0, s, w.slots, par, w.ctrl);
     return hipGetLastError();
 }
 
 // -------------------------------------------------- decoupled-lookback scan
-// Tile = 256 threads x 16 items.  Global loads and stores are coalesced
-// 16-byte accesses over rows of 512 elements; an LDS transpose (one pad word
-// per 16 entries against bank conflicts) gives each thread 16 consecutive
-// items for the sequential part of the scan.
+// Tile = 256 threads x 16 items; tile t is workgroup t.  Global loads and
+// stores are coalesced 16-byte accesses over rows of 512 elements; an LDS
+// transpose (one pad word per 16 entries against bank conflicts) gives each
+// thread 16 consecutive items for the sequential part of the scan.
+// A tile only ever waits on lower-numbered tiles, which the hardware
+// dispatches before it (workgroups are issued to each XCD in index order), so
+// the wait ends.  As a guarantee of termination whatever the dispatch order,
+// the spin is bounded: past kSpinLimit polls the tile gives up and flags the
+// call as a device error instead of hanging.
 __host__ __device__ constexpr int kPad(int i) { return i + (i >> 4); }
+constexpr int kLookU = 8;  // 64-entry lookback windows loaded per round trip
+constexpr int kSpinLimit = 1 << 22;
 
 struct ScanArgs {
     const double *lw;   // quantise mode input
@@ -107,90 +148,7 @@ struct ScanArgs {
     u64 *out;           // [n] inclusive prefix
     u64 *out64;         // [n / 64] every 64th prefix value
     int n_tiles;
-    // resampling decision (quantise mode)
-    u64 r;
-    int mode, ess_num, ess_den;
-    smc_resample_info *info;
 };
-
-// Decision, offset and FP64 summaries from the tile partials, in a fixed
-// reduction order (reproducible); run by one whole block.
-__device__ void finalize_block(const ScanArgs &a)
-{
-    __shared__ double s_z[4], s_z2[4];
-    __shared__ u64 s_lo[4], s_hi[4];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    Ctrl *ctrl = a.ctrl;
-    double z = 0.0, z2 = 0.0;
-    U128 q2{0, 0};
-    for (int t = tid; t < a.n_tiles; t += 256) {
-        const TilePart p = a.tpart[t];
-        z += p.Z;
-        z2 += p.Z2;
-        q2 = add128(q2, U128{p.q2lo, p.q2hi});
-    }
-    z = wave_sum_f64(z);
-    z2 = wave_sum_f64(z2);
-    q2 = wave_sum_u128(q2);
-    if (lane == 0) {
-        s_z[wid] = z;
-        s_z2[wid] = z2;
-        s_lo[wid] = q2.lo;
-        s_hi[wid] = q2.hi;
-    }
-    __syncthreads();
-    if (tid != 0) return;
-    const double Z = ((s_z[0] + s_z[1]) + s_z[2]) + s_z[3];
-    const double Z2 = ((s_z2[0] + s_z2[1]) + s_z2[2]) + s_z2[3];
-    U128 Q2{s_lo[0], s_hi[0]};
-    for (int i = 1; i < 4; ++i) Q2 = add128(Q2, U128{s_lo[i], s_hi[i]});
-    const u64 S = ld_relaxed(&a.status[a.n_tiles - 1]) & kValMask;
-    const unsigned err = ctrl->err_call;
-    const double m = ctrl->m;
-    int resample;
-    if (a.mode == SMC_MODE_FORCE) {
-        resample = 1;
-    } else if (a.mode == SMC_MODE_NEVER) {
-        resample = 0;
-    } else {
-        // ess_den * S^2 < ess_num * N * Q2; both sides stay below 2^127
-        const U128 lhs = mul128_small(mul64(S, S), (u64)a.ess_den);
-        const U128 rhs = mul128_small(mul128_small(Q2, (u64)a.n), (u64)a.ess_num);
-        resample = lt128(lhs, rhs) ? 1 : 0;
-    }
-    if (err) resample = 0;
-    const u64 U = mul64(a.r, S).hi;
-    const double logZ = m + log(Z);
-    const double ess = (Z * Z) / Z2;
-    ctrl->S = S;
-    ctrl->U = U;
-    ctrl->Q2lo = Q2.lo;
-    ctrl->Q2hi = Q2.hi;
-    ctrl->Z = Z;
-    ctrl->Z2 = Z2;
-    ctrl->logZ = logZ;
-    ctrl->ess = ess;
-    ctrl->K = a.K;
-    ctrl->resample = (unsigned)resample;
-    ctrl->pending = err ? 0 : 1;
-    if (a.info) {
-        smc_resample_info *o = a.info;
-        o->m = m;
-        o->logZ = logZ;
-        o->ess = ess;
-        o->Z = Z;
-        o->Z2 = Z2;
-        o->S = S;
-        o->U = U;
-        o->Q2_hi = Q2.hi;
-        o->Q2_lo = Q2.lo;
-        o->K = a.K;
-        o->resampled = resample;
-        o->err = (int)err;
-        o->pad = 0;
-        o->log_c = 0.0;
-    }
-}
 
 // Fixed-point weight of one log-weight; accumulates the FP64 and exact sums.
 __device__ inline u64 quant_one(double v, double m, int K, u64 top, double &z, double &z2, U128 &q2)
@@ -213,16 +171,13 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     __shared__ u64 s_wsum[4];
     __shared__ double s_z[4], s_z2[4];
     __shared__ u64 s_q2lo[4], s_q2hi[4];
-    __shared__ unsigned s_tile, s_bad[4];
+    __shared__ unsigned s_bad[4];
     __shared__ u64 s_prefix;
-    __shared__ int s_last;
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     Ctrl *ctrl = a.ctrl;
     const i64 n = a.n;
-    if (tid == 0) s_tile = atomicAdd(&ctrl->tile_next, 1u);
-    __syncthreads();
-    const unsigned tile = s_tile;
+    const unsigned tile = blockIdx.x;
     const i64 base = (i64)tile * kTile;
     const bool full = base + kTile <= n;
 
@@ -231,7 +186,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     unsigned bad = 0;
     u64 q[kScanItems];  // striped: q[2r + h] is element base + 512 r + 2 tid + h
     if (kQuant) {
-        const double m = ctrl->m;  // written by the max pass
+        const double m = ctrl->m;  // written by the fold of the max pass
         const int K = a.K;
         const u64 top = 1ull << K;
         double v[kScanItems];
@@ -288,7 +243,8 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     }
     const u64 texcl = wpre + incl - run;
 
-    // decoupled lookback by wave 0: 64 predecessors per probe
+    // decoupled lookback by wave 0: kLookU x 64 predecessors per round trip,
+    // nearest first; aggregates are summed until the nearest inclusive prefix
     if (wid == 0) {
         u64 excl = 0;
         if (tile == 0) {
@@ -296,23 +252,44 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
         } else {
             if (lane == 0) st_relaxed(&a.status[tile], kFlagAgg | agg);
             i64 top_idx = (i64)tile - 1;
+            int spins = 0;
             while (true) {
-                const i64 idx = top_idx - lane;
-                const u64 sv = idx >= 0 ? ld_relaxed(&a.status[idx]) : kFlagInc;
-                const u64 flag = sv >> 62;
-                const u64 inc_mask = __ballot(flag == 2);
-                const u64 zero_mask = __ballot(flag == 0);
-                const int first_inc = inc_mask ? __ffsll((long long)inc_mask) - 1 : 64;
-                const u64 need = first_inc >= 64 ? ~0ull : ((1ull << first_inc) - 1);
-                if (zero_mask & need) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
+                u64 sv[kLookU];
+#pragma unroll
+                for (int u = 0; u < kLookU; ++u) {
+                    const i64 idx = top_idx - 64 * u - lane;
+                    sv[u] = idx >= 0 ? ld_relaxed(&a.status[idx]) : kFlagInc;
                 }
-                u64 v = lane <= first_inc ? (sv & kValMask) : 0;
-                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-                excl += v;
-                if (first_inc < 64) break;
-                top_idx -= 64;
+                u64 acc = 0;
+                int consumed = 0;
+                bool done = false, stall = false;
+#pragma unroll
+                for (int u = 0; u < kLookU; ++u) {
+                    if (done || stall) break;
+                    const u64 flag = sv[u] >> 62;
+                    const u64 inc_mask = __ballot(flag == 2);
+                    const u64 zero_mask = __ballot(flag == 0);
+                    const int first_inc = inc_mask ? __ffsll((long long)inc_mask) - 1 : 64;
+                    const u64 need = first_inc >= 64 ? ~0ull : ((1ull << first_inc) - 1);
+                    if (zero_mask & need) {
+                        stall = true;
+                        break;
+                    }
+                    acc += lane <= first_inc ? (sv[u] & kValMask) : 0;
+                    consumed = u + 1;
+                    if (first_inc < 64) done = true;
+                }
+                for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+                excl += acc;
+                if (done) break;
+                top_idx -= 64 * consumed;
+                if (stall) {
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) ctrl->spin_fail = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
             }
             if (lane == 0) st_relaxed(&a.status[tile], kFlagInc | (excl + agg));
         }
@@ -361,32 +338,130 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
         }
     }
 
-    if (!kQuant) {
-        if (tid == 0 && (s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3])) atomicOr(&ctrl->ncopy_bad, 1u);
-        return;
-    }
-    // publish the tile partials; the last tile to finish takes the decision
     if (tid == 0) {
-        TilePart p;
-        p.Z = ((s_z[0] + s_z[1]) + s_z[2]) + s_z[3];
-        p.Z2 = ((s_z2[0] + s_z2[1]) + s_z2[2]) + s_z2[3];
-        U128 t{s_q2lo[0], s_q2hi[0]};
-        for (int i = 1; i < 4; ++i) t = add128(t, U128{s_q2lo[i], s_q2hi[i]});
-        p.q2lo = t.lo;
-        p.q2hi = t.hi;
-        a.tpart[tile] = p;
-        __threadfence();
-        s_last = atomicAdd(&ctrl->scan_done, 1u) == (unsigned)a.n_tiles - 1;
+        if (kQuant) {
+            TilePart p;
+            p.Z = ((s_z[0] + s_z[1]) + s_z[2]) + s_z[3];
+            p.Z2 = ((s_z2[0] + s_z2[1]) + s_z2[2]) + s_z2[3];
+            U128 t{s_q2lo[0], s_q2hi[0]};
+            for (int i = 1; i < 4; ++i) t = add128(t, U128{s_q2lo[i], s_q2hi[i]});
+            p.q2lo = t.lo;
+            p.q2hi = t.hi;
+            a.tpart[tile] = p;
+        } else if (s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]) {
+            atomicOr(&ctrl->ncopy_bad, 1u);
+        }
     }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if (tid == 0) ctrl->scan_done = 0;
-    finalize_block(a);
 }
 
-hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, uint64_t r,
-                             int mode, int ess_num, int ess_den, void *info, hipStream_t s)
+// ---------------------------------------------------------------- decision
+// One workgroup: tile partials summed in a fixed order (reproducible FP64);
+// exact integer decision and offset.
+__global__ __launch_bounds__(1024) void k_decide(Ctrl *ctrl, const TilePart *tpart,
+                                                 const u64 *status, int n_tiles, i64 n, int K,
+                                                 u64 r, int mode, int ess_num, int ess_den,
+                                                 smc_resample_info *info)
+{
+    __shared__ double s_z[16], s_z2[16];
+    __shared__ u64 s_lo[16], s_hi[16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double z = 0.0, z2 = 0.0;
+    U128 q2{0, 0};
+    constexpr int FU = 4;  // partials in flight per thread; summed in tile order
+    for (int t0 = tid; t0 < n_tiles; t0 += 1024 * FU) {
+        TilePart p[FU];
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int t = t0 + 1024 * u;
+            p[u] = t < n_tiles ? tpart[t] : TilePart{0.0, 0.0, 0ull, 0ull};
+        }
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            z += p[u].Z;
+            z2 += p[u].Z2;
+            q2 = add128(q2, U128{p[u].q2lo, p[u].q2hi});
+        }
+    }
+    z = wave_sum_f64(z);
+    z2 = wave_sum_f64(z2);
+    q2 = wave_sum_u128(q2);
+    if (lane == 0) {
+        s_z[wid] = z;
+        s_z2[wid] = z2;
+        s_lo[wid] = q2.lo;
+        s_hi[wid] = q2.hi;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    double Z = s_z[0], Z2 = s_z2[0];
+    U128 Q2{s_lo[0], s_hi[0]};
+    for (int i = 1; i < 16; ++i) {
+        Z += s_z[i];
+        Z2 += s_z2[i];
+        Q2 = add128(Q2, U128{s_lo[i], s_hi[i]});
+    }
+    const u64 S = status[n_tiles - 1] & kValMask;
+    unsigned err = ctrl->err_call;
+    if (!err && ctrl->spin_fail) {
+        err = SMC_E_DEVICE;
+        ctrl->err_call = err;
+        if (!ctrl->err_latch) ctrl->err_latch = err;
+    }
+    const double m = ctrl->m;
+    int resample;
+    if (mode == SMC_MODE_FORCE) {
+        resample = 1;
+    } else if (mode == SMC_MODE_NEVER) {
+        resample = 0;
+    } else {
+        // ess_den * S^2 < ess_num * N * Q2; both sides stay below 2^127
+        const U128 lhs = mul128_small(mul64(S, S), (u64)ess_den);
+        const U128 rhs = mul128_small(mul128_small(Q2, (u64)n), (u64)ess_num);
+        resample = lt128(lhs, rhs) ? 1 : 0;
+    }
+    if (err) resample = 0;
+    const u64 U = mul64(r, S).hi;
+    const double logZ = m + log(Z);
+    const double ess = (Z * Z) / Z2;
+    ctrl->S = S;
+    ctrl->U = U;
+    ctrl->Q2lo = Q2.lo;
+    ctrl->Q2hi = Q2.hi;
+    ctrl->Z = Z;
+    ctrl->Z2 = Z2;
+    ctrl->logZ = logZ;
+    ctrl->ess = ess;
+    ctrl->K = K;
+    ctrl->resample = (unsigned)resample;
+    ctrl->pending = err ? 0 : 1;
+    if (info) {
+        info->m = m;
+        info->logZ = logZ;
+        info->ess = ess;
+        info->Z = Z;
+        info->Z2 = Z2;
+        info->S = S;
+        info->U = U;
+        info->Q2_hi = Q2.hi;
+        info->Q2_lo = Q2.lo;
+        info->K = K;
+        info->resampled = resample;
+        info->err = (int)err;
+        info->pad = 0;
+        info->log_c = 0.0;
+    }
+}
+
+hipError_t launch_decide(const Work &w, int64_t n, int K, uint64_t r, int mode, int ess_num,
+                         int ess_den, void *info, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, w.ctrl, w.tpart, w.status, w.n_tiles,
+                       (i64)n, K, (u64)r, mode, ess_num, ess_den,
+                       reinterpret_cast<smc_resample_info *>(info));
+    return hipGetLastError();
+}
+
+hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, hipStream_t s)
 {
     ScanArgs a;
     a.lw = lw;
@@ -400,11 +475,6 @@ hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, 
     a.out = w.pref;
     a.out64 = w.pref64;
     a.n_tiles = w.n_tiles;
-    a.r = r;
-    a.mode = mode;
-    a.ess_num = ess_num;
-    a.ess_den = ess_den;
-    a.info = reinterpret_cast<smc_resample_info *>(info);
     hipLaunchKernelGGL(k_scan<true>, dim3(w.n_tiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -415,7 +485,7 @@ __global__ __launch_bounds__(256) void k_clear_scan(Ctrl *ctrl, u64 *status, int
     const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
     for (i64 i = gtid; i < n_status; i += gsz) status[i] = 0;
     if (gtid == 0) {
-        ctrl->tile_next = 0;
+        ctrl->spin_fail = 0;
         ctrl->ncopy_bad = 0;
         ctrl->err_call = 0;
         ctrl->pending = 0;
@@ -444,11 +514,6 @@ hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, h
     a.out = w.pref;
     a.out64 = w.pref64;
     a.n_tiles = w.n_tiles;
-    a.r = 0;
-    a.mode = 0;
-    a.ess_num = 0;
-    a.ess_den = 1;
-    a.info = nullptr;
     hipLaunchKernelGGL(k_scan<false>, dim3(w.n_tiles), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -53,8 +53,7 @@ __device__ inline unsigned short to_bf16(double v)
 // Per-block sums for the estimates with the block's own max (rescaled later):
 // part = [m_b, sum e, sum e x_k (k < d), sum e x_k^2 (k < d)], e = exp(l - m_b).
 __device__ inline void is_block_finish(i64 n, int d, const double *x, const double *logw, u64 key,
-                                       unsigned bad, Ctrl *ctrl, u64 *blk_key, unsigned *blk_bad,
-                                       double *is_part)
+                                       unsigned bad, u64 *slots_p, double *is_part)
 {
     __shared__ double s_acc[4][2 + 2 * kMaxDim];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -86,15 +85,15 @@ __device__ inline void is_block_finish(i64 n, int d, const double *x, const doub
     double *part = is_part + (i64)blockIdx.x * ncol;
     for (int c = tid; c < ncol; c += 256)
         part[c] = c == 0 ? mb : ((s_acc[0][c] + s_acc[1][c]) + s_acc[2][c]) + s_acc[3][c];
-    grid_max_combine(bk, bad, ctrl, blk_key, blk_bad);
+    slot_publish(slots_p, bk, bad);
 }
 
 // ------------------------------------------------------- proposal + weights
 template <int kKind, bool kInit>
 __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *__restrict__ x,
                                             double *__restrict__ logw, double *__restrict__ lp,
-                                            Ctrl *ctrl, u64 *blk_key, unsigned *blk_bad,
-                                            u64 *status, int n_status, double *is_part)
+                                            u64 *slots_p, u64 *status, int n_status,
+                                            double *is_part)
 {
     const int tid = threadIdx.x;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
@@ -147,16 +146,15 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
         key = kk > key ? kk : key;
     }
     if (kKind == SMC_TARGET_LOGREG) return;
-    is_block_finish(n, d, x, logw, key, bad, ctrl, blk_key, blk_bad, is_part);
+    is_block_finish(n, d, x, logw, key, bad, slots_p, is_part);
 }
 
 template <bool kInit>
 __global__ __launch_bounds__(256) void k_reweight(i64 n, int d, const double *__restrict__ x,
                                                   const double *__restrict__ lp_new,
                                                   double *__restrict__ logw,
-                                                  double *__restrict__ lp, Ctrl *ctrl,
-                                                  u64 *blk_key, unsigned *blk_bad, u64 *status,
-                                                  int n_status, double *is_part)
+                                                  double *__restrict__ lp, u64 *slots_p,
+                                                  u64 *status, int n_status, double *is_part)
 {
     const int tid = threadIdx.x;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
@@ -172,7 +170,7 @@ __global__ __launch_bounds__(256) void k_reweight(i64 n, int d, const double *__
         const u64 kk = okey(lw);
         key = kk > key ? kk : key;
     }
-    is_block_finish(n, d, x, logw, key, bad, ctrl, blk_key, blk_bad, is_part);
+    is_block_finish(n, d, x, logw, key, bad, slots_p, is_part);
 }
 
 // -------------------------------------------- estimates, c_t and recycling
@@ -478,39 +476,42 @@ hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_
 }
 
 template <bool kInit>
-hipError_t launch_is(const smc_config &c, const Work &w, uint32_t t, double *x, double *logw,
-                     hipStream_t s)
+hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, double *x,
+                     double *logw, hipStream_t s)
 {
     const TArgs a = targs(c, w, is_bf16(c));
     const int g = grid_for(c.n);
     const i64 n = c.n;
+    u64 *sp = w.slots + (par & 1) * kSlots * kSlotStride;
     switch (c.target) {
     case SMC_TARGET_GAUSS:
         hipLaunchKernelGGL((k_is<SMC_TARGET_GAUSS, kInit>), dim3(g), dim3(256), 0, s, a, n, t, x,
-                           logw, w.lp, w.ctrl, w.blk_key, w.blk_bad, w.status, w.n_tiles,
+                           logw, w.lp, sp, w.status, w.n_tiles,
                            w.is_part);
         break;
     case SMC_TARGET_STUDENT:
         hipLaunchKernelGGL((k_is<SMC_TARGET_STUDENT, kInit>), dim3(g), dim3(256), 0, s, a, n, t,
-                           x, logw, w.lp, w.ctrl, w.blk_key, w.blk_bad, w.status, w.n_tiles,
+                           x, logw, w.lp, sp, w.status, w.n_tiles,
                            w.is_part);
         break;
     default:
         hipLaunchKernelGGL((k_is<SMC_TARGET_LOGREG, kInit>), dim3(g), dim3(256), 0, s, a, n, t, x,
-                           logw, w.lp, w.ctrl, w.blk_key, w.blk_bad, w.status, w.n_tiles,
+                           logw, w.lp, sp, w.status, w.n_tiles,
                            w.is_part);
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
         if (logreg_lp(c, w, x, n, w.lp_new, true, s) != hipSuccess) return hipErrorLaunchFailure;
         hipLaunchKernelGGL(k_reweight<kInit>, dim3(g), dim3(256), 0, s, n, c.d, x, w.lp_new, logw,
-                           w.lp, w.ctrl, w.blk_key, w.blk_bad, w.status, w.n_tiles, w.is_part);
+                           w.lp, sp, w.status, w.n_tiles, w.is_part);
         break;
     }
-    return hipGetLastError();
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    return launch_fold(w, par, s);
 }
 
 }  // namespace
 
-smc_status step_init(const smc_config &c, const Work &w, double *x, double *logw, hipStream_t s)
+smc_status step_init(const smc_config &c, const Work &w, int par, double *x, double *logw,
+                     hipStream_t s)
 {
     if (c.target == SMC_TARGET_LOGREG && is_bf16(c)) {
         const int64_t thb_elems = w.npad * w.dp;
@@ -519,19 +520,20 @@ smc_status step_init(const smc_config &c, const Work &w, double *x, double *logw
                            (i64)w.mpad, w.dp, w.xs, w.thb, (i64)thb_elems);
         if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     }
-    if (launch_is<true>(c, w, 0u, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_is<true>(c, w, par, 0u, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
     hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part, grid_for(c.n),
                        c.d, w.rec_num, (double *)nullptr, (smc_resample_info *)nullptr, 1);
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
 
-smc_status step_run(const smc_config &c, const Work &w, int K, uint32_t t, double *x,
+smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t t, double *x,
                     double *logw, smc_resample_info *info, double *est, hipStream_t s)
 {
     const int64_t n = c.n;
-    if (launch_is<false>(c, w, t, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_is<false>(c, w, par, t, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_quant_scan(w, logw, n, K, s) != hipSuccess) return SMC_E_DEVICE;
     const uint64_t r = resample_word(c.seed, c.sampler_id, t);
-    if (launch_quant_scan(w, logw, n, K, r, c.mode, c.ess_num, c.ess_den, info, s) != hipSuccess)
+    if (launch_decide(w, n, K, r, c.mode, c.ess_num, c.ess_den, info, s) != hipSuccess)
         return SMC_E_DEVICE;
     hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part, grid_for(n),
                        c.d, w.rec_num, est, info, 0);

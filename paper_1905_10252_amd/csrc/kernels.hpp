@@ -25,8 +25,7 @@ struct TilePart {
 // Device pointers into the caller's workspace.
 struct Work {
     Ctrl *ctrl;
-    u64 *blk_key;       // [kMaxBlocks] per-block max keys
-    unsigned *blk_bad;  // [kMaxBlocks] per-block non-finite flags
+    u64 *slots;         // [2][64][16] max / non-finite slots, double-buffered by parity
     u64 *status;        // [n_tiles] lookback words
     TilePart *tpart;    // [n_tiles]
     u64 *pref;          // [n] inclusive prefix (S_j, or A_j for foreign counts)
@@ -56,10 +55,13 @@ inline int max_blocks_of(int64_t n)
 
 
 hipError_t launch_init_ctrl(const Work &w, hipStream_t s);
-hipError_t launch_max(const Work &w, const double *lw, int64_t n, hipStream_t s);
-// Quantise + scan + (last tile) decision; info is a device smc_resample_info.
-hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, uint64_t r,
-                             int mode, int ess_num, int ess_den, void *info, hipStream_t s);
+// Max pass into the slots of parity par, then the fold of those slots.
+hipError_t launch_max(const Work &w, const double *lw, int64_t n, int par, hipStream_t s);
+hipError_t launch_fold(const Work &w, int par, hipStream_t s);
+hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, hipStream_t s);
+// Decision from the scan; info is a device smc_resample_info (nullable).
+hipError_t launch_decide(const Work &w, int64_t n, int K, uint64_t r, int mode, int ess_num,
+                         int ess_den, void *info, hipStream_t s);
 hipError_t launch_clear_scan(const Work &w, hipStream_t s);
 hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, hipStream_t s);
 hipError_t launch_ncopies(const Work &w, int64_t n, int count_mode, int64_t *ncopies,

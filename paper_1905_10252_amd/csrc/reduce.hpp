@@ -1,8 +1,10 @@
-// Grid-wide exact max of the log-weights with the last-block-done pattern:
-// each block publishes its max order key and non-finite flag; the block that
-// finishes last combines them (max is order-free, so the result is exact and
-// does not depend on scheduling), records the error of the call and resets
-// the counters the following scan pass relies on.
+// Grid-wide exact max of the log-weights without fences or contended
+// atomics: every block publishes its max order key (and a non-finite flag)
+// with one device-scope atomic into one of 64 slots, each on its own cache
+// line, so the atomics do not serialise.  The slots are double-buffered by the
+// parity of the call: a small fold kernel combines the current parity (max is
+// order-free, so the result is exact) and clears the other parity for the
+// next call.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,8 +13,12 @@
 
 namespace smc {
 
+constexpr int kSlots = 64;
+constexpr int kSlotStride = 16;  // u64 words: one 128-byte line per slot
+constexpr int kSlotWords = 2 * kSlots * kSlotStride;
+
 // Call with every thread of a 256-thread block; key/bad are per-thread values.
-// Returns the block's max key to every thread.
+// Returns the block's max key (and OR of flags in bad) to every thread.
 __device__ inline u64 block_max_key(u64 key, unsigned &bad)
 {
     __shared__ u64 s_k[4];
@@ -36,39 +42,13 @@ __device__ inline u64 block_max_key(u64 key, unsigned &bad)
     return k;
 }
 
-__device__ inline void grid_max_combine(u64 blk_k, unsigned blk_b, Ctrl *ctrl, u64 *blk_key,
-                                        unsigned *blk_bad)
+// slots_p: the kSlots slots of this call's parity.
+__device__ inline void slot_publish(u64 *slots_p, u64 key, unsigned bad)
 {
-    __shared__ int s_last;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        blk_key[blockIdx.x] = blk_k;
-        blk_bad[blockIdx.x] = blk_b;
-        __threadfence();
-        s_last = atomicAdd(&ctrl->blk_done, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    u64 key = 0;
-    unsigned bad = 0;
-    for (int i = tid; i < (int)gridDim.x; i += blockDim.x) {
-        const u64 k = __hip_atomic_load(&blk_key[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        key = k > key ? k : key;
-        bad |= __hip_atomic_load(&blk_bad[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    key = block_max_key(key, bad);
-    if (tid == 0) {
-        unsigned err = 0;
-        if (bad) err = kErrNonfinite;
-        else if (key <= okey(-__builtin_huge_val())) err = kErrDegenerate;
-        ctrl->mkey = key;
-        ctrl->m = okey_inv(key);
-        ctrl->err_call = err;
-        if (err && !ctrl->err_latch) ctrl->err_latch = err;
-        ctrl->blk_done = 0;
-        ctrl->tile_next = 0;
-        ctrl->pending = 0;
+    if (threadIdx.x == 0) {
+        u64 *s = slots_p + (blockIdx.x & (kSlots - 1)) * kSlotStride;
+        atomicMax(s, key);
+        if (bad) atomicOr(s + 1, 1ull);
     }
 }
 

@@ -12,6 +12,7 @@
 #include "../../include/smc.h"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "reduce.hpp"
 #include "step.hpp"
 
 using namespace smc;
@@ -24,12 +25,13 @@ struct smc_ctx {
     int K;
     bool pending;   // the workspace prefix belongs to the last smc_resample
     uint32_t t;     // sampler iteration counter (Alg 2 t)
+    int par;        // parity of the max slots used by the next call
 };
 
 namespace {
 
 struct Layout {
-    size_t ctrl, blk_key, blk_bad, status, tpart, pref, pref64;
+    size_t ctrl, slots, status, tpart, pref, pref64;
     size_t lp, lp_new, x_scr, lp_scr, is_part, rec_num;
     size_t xs, thb, lpart;
     int64_t mpad, npad;
@@ -71,8 +73,7 @@ Layout layout_of(const smc_config *c)
     const size_t n = (size_t)c->n, d = (size_t)c->d;
     const size_t nt = (size_t)n_tiles_of(c->n);
     L.ctrl = take(sizeof(Ctrl));
-    L.blk_key = take(8 * kMaxBlocks);
-    L.blk_bad = take(4 * kMaxBlocks);
+    L.slots = take(8 * (size_t)kSlotWords);
     L.status = take(8 * nt);
     L.tpart = take(sizeof(TilePart) * nt);
     L.pref = take(8 * n);
@@ -149,6 +150,7 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
     ctx->ws_bytes = workspace_bytes;
     ctx->pending = false;
     ctx->t = 0;
+    ctx->par = 0;
     {
         int c = 0;
         while ((1LL << c) < h_cfg->n) ++c;
@@ -157,8 +159,7 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
     unsigned char *b = reinterpret_cast<unsigned char *>(workspace);
     Work &w = ctx->w;
     w.ctrl = reinterpret_cast<Ctrl *>(b + L.ctrl);
-    w.blk_key = reinterpret_cast<u64 *>(b + L.blk_key);
-    w.blk_bad = reinterpret_cast<unsigned *>(b + L.blk_bad);
+    w.slots = reinterpret_cast<u64 *>(b + L.slots);
     w.status = reinterpret_cast<u64 *>(b + L.status);
     w.tpart = reinterpret_cast<TilePart *>(b + L.tpart);
     w.pref = reinterpret_cast<u64 *>(b + L.pref);
@@ -182,8 +183,9 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
         return SMC_E_DEVICE;
     }
     if (samp) {
-        const smc_status st = step_init(ctx->cfg, w, reinterpret_cast<double *>(x), logw,
-                                        S(stream));
+        const smc_status st = step_init(ctx->cfg, w, ctx->par, reinterpret_cast<double *>(x),
+                                        logw, S(stream));
+        ctx->par ^= 1;
         if (st != SMC_OK) {
             delete ctx;
             return st;
@@ -202,9 +204,13 @@ smc_status smc_resample(smc_ctx *ctx, const double *logw, int64_t n, uint64_t r,
         return SMC_E_ARG;
     const Work &w = ctx->w;
     hipStream_t s = S(stream);
-    if (launch_max(w, logw, n, s) != hipSuccess) return SMC_E_DEVICE;
-    if (launch_quant_scan(w, logw, n, ctx->K, r, mode, ctx->cfg.ess_num, ctx->cfg.ess_den, info,
-                          s) != hipSuccess)
+    const int par = ctx->par;
+    ctx->par ^= 1;
+    if (launch_max(w, logw, n, par, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_fold(w, par, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_quant_scan(w, logw, n, ctx->K, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_decide(w, n, ctx->K, r, mode, ctx->cfg.ess_num, ctx->cfg.ess_den, info, s) !=
+        hipSuccess)
         return SMC_E_DEVICE;
     ctx->pending = true;
     if (ncopies && launch_ncopies(w, n, 0, ncopies, s) != hipSuccess) return SMC_E_DEVICE;
@@ -246,8 +252,10 @@ smc_status smc_step(smc_ctx *ctx, void *x, double *logw, smc_resample_info *info
         ((uintptr_t)est & 7))
         return SMC_E_ARG;
     ctx->t += 1;
-    const smc_status st = step_run(ctx->cfg, ctx->w, ctx->K, ctx->t, reinterpret_cast<double *>(x),
-                                   logw, info, est, S(stream));
+    const int par = ctx->par;
+    ctx->par ^= 1;
+    const smc_status st = step_run(ctx->cfg, ctx->w, ctx->K, par, ctx->t,
+                                   reinterpret_cast<double *>(x), logw, info, est, S(stream));
     ctx->pending = false;  // the step reuses the prefix buffer
     return st;
 }

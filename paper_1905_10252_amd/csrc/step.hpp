@@ -11,8 +11,10 @@ namespace smc {
 
 constexpr int kMaxDim = 64;
 
-smc_status step_init(const smc_config &cfg, const Work &w, double *x, double *logw, hipStream_t s);
-smc_status step_run(const smc_config &cfg, const Work &w, int K, uint32_t t, double *x,
+// par: parity of the max slots this call uses (alternates between calls).
+smc_status step_init(const smc_config &cfg, const Work &w, int par, double *x, double *logw,
+                     hipStream_t s);
+smc_status step_run(const smc_config &cfg, const Work &w, int K, int par, uint32_t t, double *x,
                     double *logw, smc_resample_info *info, double *est, hipStream_t s);
 smc_status step_log_target(const smc_config &cfg, const Work &w, const double *x, int64_t n,
                            double *lp, hipStream_t s);
