@@ -154,6 +154,7 @@ def main():
                                "s cycled over 0.5/2/8, systematic, forced",
                    "n": n, "d": d, "scales": list(scales)},
         "p50_ms": round(pctl(step_ms, 50), 4), "p99_ms": round(pctl(step_ms, 99), 4),
+        "max_ms": round(max(step_ms), 4),
         "per_scale": per_s,
         "path_hbm_frac": round(path_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "wall_s": round(t_wall, 3),

@@ -151,15 +151,18 @@ __device__ inline bool make_afun(const Ctrl *ctrl, const u64 *pref, i64 n, int c
     return true;
 }
 
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
 template <int VEC>
 struct VecT;
 template <>
 struct VecT<16> {
-    typedef uint4 T;
+    typedef u32x4 T;
 };
 template <>
 struct VecT<8> {
-    typedef uint2 T;
+    typedef u32x2 T;
 };
 template <>
 struct VecT<4> {

@@ -2,16 +2,18 @@
 //   k_max          exact FP64 max of the log-weights (the stability shift of
 //                  eq. normalise) and non-finite detection; clears the scan
 //                  state for the pass that follows.
-//   k_fold         combines the max slots, records the error of the call.
+//   k_fold         combines the max slots, records the error of the call
+//                  (used where no scan follows the max pass).
 //   k_scan<true>   one pass over the log-weights: 64-bit fixed-point weights
 //                  q_i = min(2^K, floor(2^K det_exp(l_i - m))), FP64 sums for
 //                  log-sum-exp and ESS (eq. normalise, eq. neff), the exact
 //                  sum of q_i^2, and the inclusive prefix S_j (the Cumulative
 //                  Sum of MVR) by a single-pass decoupled-lookback scan.
 //   k_scan<false>  the same scan over caller-supplied int64 ncopies.
-//   k_decide       the exact integer ESS decision (resample when ESS < N*,
-//                  Alg 2), the systematic offset U = floor(r S / 2^64), log Z
-//                  and the FP64 ESS from the tile partials.
+//   k_decide       the error of the call, the exact integer ESS decision
+//                  (resample when ESS < N*, Alg 2), the systematic offset
+//                  U = floor(r S / 2^64), log Z and the FP64 ESS from the tile
+//                  partials; clears the other parity's max slots.
 // No kernel here uses a device-wide fence or a contended atomic: both
 // serialise across the chip.
 // Every 64th prefix value is also written to a sample array, a coarse index
@@ -134,7 +136,7 @@ hipError_t launch_fold(const Work &w, int par, hipStream_t s)
 // the spin is bounded: past kSpinLimit polls the tile gives up and flags the
 // call as a device error instead of hanging.
 __host__ __device__ constexpr int kPad(int i) { return i + (i >> 4); }
-constexpr int kLookU = 8;  // 64-entry lookback windows loaded per round trip
+constexpr int kLookU = 1;  // 64-entry lookback windows loaded per round trip
 constexpr int kSpinLimit = 1 << 22;
 
 struct ScanArgs {
@@ -147,6 +149,7 @@ struct ScanArgs {
     TilePart *tpart;
     u64 *out;           // [n] inclusive prefix
     u64 *out64;         // [n / 64] every 64th prefix value
+    const u64 *slots_p; // max slots of this call's parity (quantise mode)
     int n_tiles;
 };
 
@@ -186,7 +189,8 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     unsigned bad = 0;
     u64 q[kScanItems];  // striped: q[2r + h] is element base + 512 r + 2 tid + h
     if (kQuant) {
-        const double m = ctrl->m;  // written by the fold of the max pass
+        // every wave folds the 64 max slots itself (cached lines; no barrier)
+        const double m = okey_inv(wave_max_u64(a.slots_p[lane * kSlotStride]));
         const int K = a.K;
         const u64 top = 1ull << K;
         double v[kScanItems];
@@ -357,14 +361,29 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
 // ---------------------------------------------------------------- decision
 // One workgroup: tile partials summed in a fixed order (reproducible FP64);
 // exact integer decision and offset.
-__global__ __launch_bounds__(1024) void k_decide(Ctrl *ctrl, const TilePart *tpart,
-                                                 const u64 *status, int n_tiles, i64 n, int K,
-                                                 u64 r, int mode, int ess_num, int ess_den,
+__global__ __launch_bounds__(1024) void k_decide(Ctrl *ctrl, u64 *slots, int par,
+                                                 const TilePart *tpart, const u64 *status,
+                                                 int n_tiles, i64 n, int K, u64 r, int mode,
+                                                 int ess_num, int ess_den,
                                                  smc_resample_info *info)
 {
     __shared__ double s_z[16], s_z2[16];
     __shared__ u64 s_lo[16], s_hi[16];
+    __shared__ u64 s_key;
+    __shared__ unsigned s_badf;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (wid == 0) {
+        u64 *cur = slots + (par & 1) * kSlots * kSlotStride;
+        u64 *nxt = slots + ((par & 1) ^ 1) * kSlots * kSlotStride;
+        const u64 key = wave_max_u64(cur[lane * kSlotStride]);
+        const unsigned bad = wave_or((unsigned)cur[lane * kSlotStride + 1]);
+        nxt[lane * kSlotStride] = 0;
+        nxt[lane * kSlotStride + 1] = 0;
+        if (lane == 0) {
+            s_key = key;
+            s_badf = bad;
+        }
+    }
     double z = 0.0, z2 = 0.0;
     U128 q2{0, 0};
     constexpr int FU = 4;  // partials in flight per thread; summed in tile order
@@ -401,13 +420,17 @@ __global__ __launch_bounds__(1024) void k_decide(Ctrl *ctrl, const TilePart *tpa
         Q2 = add128(Q2, U128{s_lo[i], s_hi[i]});
     }
     const u64 S = status[n_tiles - 1] & kValMask;
-    unsigned err = ctrl->err_call;
-    if (!err && ctrl->spin_fail) {
-        err = SMC_E_DEVICE;
-        ctrl->err_call = err;
-        if (!ctrl->err_latch) ctrl->err_latch = err;
-    }
-    const double m = ctrl->m;
+    const u64 key = s_key;
+    const double m = okey_inv(key);
+    unsigned err = 0;
+    if (s_badf) err = kErrNonfinite;
+    else if (key <= okey(-__builtin_huge_val())) err = kErrDegenerate;
+    else if (ctrl->spin_fail) err = SMC_E_DEVICE;
+    ctrl->mkey = key;
+    ctrl->m = m;
+    ctrl->err_call = err;
+    ctrl->spin_fail = 0;
+    if (err && !ctrl->err_latch) ctrl->err_latch = err;
     int resample;
     if (mode == SMC_MODE_FORCE) {
         resample = 1;
@@ -452,16 +475,17 @@ __global__ __launch_bounds__(1024) void k_decide(Ctrl *ctrl, const TilePart *tpa
     }
 }
 
-hipError_t launch_decide(const Work &w, int64_t n, int K, uint64_t r, int mode, int ess_num,
-                         int ess_den, void *info, hipStream_t s)
+hipError_t launch_decide(const Work &w, int par, int64_t n, int K, uint64_t r, int mode,
+                         int ess_num, int ess_den, void *info, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, w.ctrl, w.tpart, w.status, w.n_tiles,
-                       (i64)n, K, (u64)r, mode, ess_num, ess_den,
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, w.ctrl, w.slots, par, w.tpart,
+                       w.status, w.n_tiles, (i64)n, K, (u64)r, mode, ess_num, ess_den,
                        reinterpret_cast<smc_resample_info *>(info));
     return hipGetLastError();
 }
 
-hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, hipStream_t s)
+hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, int par,
+                             hipStream_t s)
 {
     ScanArgs a;
     a.lw = lw;
@@ -474,6 +498,7 @@ hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, 
     a.tpart = w.tpart;
     a.out = w.pref;
     a.out64 = w.pref64;
+    a.slots_p = w.slots + (par & 1) * kSlots * kSlotStride;
     a.n_tiles = w.n_tiles;
     hipLaunchKernelGGL(k_scan<true>, dim3(w.n_tiles), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -513,6 +538,7 @@ hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, h
     a.tpart = w.tpart;
     a.out = w.pref;
     a.out64 = w.pref64;
+    a.slots_p = nullptr;
     a.n_tiles = w.n_tiles;
     hipLaunchKernelGGL(k_scan<false>, dim3(w.n_tiles), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -505,7 +505,8 @@ hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, do
         break;
     }
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-    return launch_fold(w, par, s);
+    // initialisation has no scan; its max is folded on its own
+    return kInit ? launch_fold(w, par, s) : hipSuccess;
 }
 
 }  // namespace
@@ -531,9 +532,9 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
 {
     const int64_t n = c.n;
     if (launch_is<false>(c, w, par, t, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
-    if (launch_quant_scan(w, logw, n, K, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_quant_scan(w, logw, n, K, par, s) != hipSuccess) return SMC_E_DEVICE;
     const uint64_t r = resample_word(c.seed, c.sampler_id, t);
-    if (launch_decide(w, n, K, r, c.mode, c.ess_num, c.ess_den, info, s) != hipSuccess)
+    if (launch_decide(w, par, n, K, r, c.mode, c.ess_num, c.ess_den, info, s) != hipSuccess)
         return SMC_E_DEVICE;
     hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part, grid_for(n),
                        c.d, w.rec_num, est, info, 0);

@@ -58,10 +58,13 @@ hipError_t launch_init_ctrl(const Work &w, hipStream_t s);
 // Max pass into the slots of parity par, then the fold of those slots.
 hipError_t launch_max(const Work &w, const double *lw, int64_t n, int par, hipStream_t s);
 hipError_t launch_fold(const Work &w, int par, hipStream_t s);
-hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, hipStream_t s);
-// Decision from the scan; info is a device smc_resample_info (nullable).
-hipError_t launch_decide(const Work &w, int64_t n, int K, uint64_t r, int mode, int ess_num,
-                         int ess_den, void *info, hipStream_t s);
+// Quantise + scan; reads the max slots of parity par.
+hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, int par,
+                             hipStream_t s);
+// Error and decision of the call from the max slots of parity par and the
+// scan; info is a device smc_resample_info (nullable).
+hipError_t launch_decide(const Work &w, int par, int64_t n, int K, uint64_t r, int mode,
+                         int ess_num, int ess_den, void *info, hipStream_t s);
 hipError_t launch_clear_scan(const Work &w, hipStream_t s);
 hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, hipStream_t s);
 hipError_t launch_ncopies(const Work &w, int64_t n, int count_mode, int64_t *ncopies,

@@ -207,9 +207,8 @@ smc_status smc_resample(smc_ctx *ctx, const double *logw, int64_t n, uint64_t r,
     const int par = ctx->par;
     ctx->par ^= 1;
     if (launch_max(w, logw, n, par, s) != hipSuccess) return SMC_E_DEVICE;
-    if (launch_fold(w, par, s) != hipSuccess) return SMC_E_DEVICE;
-    if (launch_quant_scan(w, logw, n, ctx->K, s) != hipSuccess) return SMC_E_DEVICE;
-    if (launch_decide(w, n, ctx->K, r, mode, ctx->cfg.ess_num, ctx->cfg.ess_den, info, s) !=
+    if (launch_quant_scan(w, logw, n, ctx->K, par, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_decide(w, par, n, ctx->K, r, mode, ctx->cfg.ess_num, ctx->cfg.ess_den, info, s) !=
         hipSuccess)
         return SMC_E_DEVICE;
     ctx->pending = true;
