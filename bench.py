@@ -20,6 +20,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+EXPAND_SRC = os.path.join(ROOT, "paper_1905_10252_amd", "csrc", "k_expand.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "k_expand_N2e24_hbm_counters.md")
+
+
+def expand_traffic():
+    """HBM bytes per expand launch from the committed rocprofv3 counter summary,
+    or None when that summary was taken on another version of the kernel."""
+    import hashlib
+    if not os.path.exists(COUNTERS):
+        return None
+    digest = hashlib.sha256(open(EXPAND_SRC, "rb").read()).hexdigest()
+    text = open(COUNTERS).read()
+    src = [l.split("`")[1] for l in text.splitlines() if l.startswith("- source sha256:")]
+    tot = [l.split("`")[1] for l in text.splitlines() if l.startswith("- traffic bytes per launch:")]
+    if not src or not tot or src[0] != digest:
+        return None
+    return int(tot[0])
 
 
 def pctl(v, q):
@@ -124,6 +141,20 @@ def main():
     if args.calib_copy:
         x_out.copy_(x)
         torch.cuda.synchronize()
+    # measured stream-copy bandwidth (1 GiB device copy, outside the timed region)
+    ce0, ce1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    x_out.copy_(x)
+    ce0.record()
+    for _ in range(5):
+        x_out.copy_(x)
+    ce1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * x.numel() * x.element_size() * 5 / (ce0.elapsed_time(ce1) / 1e3) / 1e9
+    # sources that receive a copy, per scale (the strict read bound)
+    uniq = []
+    for i in range(len(scales)):
+        step(i)
+        uniq.append(int((ncopies > 0).sum().item()))
 
     per_s = {}
     for i, s in enumerate(scales):
@@ -140,9 +171,19 @@ def main():
     exp_avg_s = float(np.mean(exp_ms)) / 1e3
     bytes_expand = (8 * d + 8) * n  # read row + write row (4d each) + ncopies write (8)
     achieved = bytes_expand / exp_avg_s / 1e9
+    # strict bound: only sources with ncopies > 0 need their row read
+    u_mean = float(np.mean(uniq))
+    bytes_strict = (8 + 4 * d) * n + 4 * d * u_mean
+    achieved_strict = bytes_strict / exp_avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_expand", "algorithmic_bytes_per_launch": bytes_expand}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": expand_traffic(),
+                "kernel": "k_expand", "algorithmic_bytes_per_launch": bytes_expand,
+                "strict_bytes_per_launch": int(bytes_strict),
+                "achieved_strict": round(achieved_strict, 1),
+                "frac_strict": round(achieved_strict / HBM_PEAK_GBS, 4),
+                "unique_sources": {"s=%g" % s: u for s, u in zip(scales, uniq)},
+                "avg_launch_us": round(exp_avg_s * 1e6, 2)}
     path_bytes = (16 + 8 * d) * n  # logw read, ncopies write, row read + write
     out = {
         "metric": "resampled particles/s (resample+redistribute) @N=2^24",
@@ -157,6 +198,8 @@ def main():
         "max_ms": round(max(step_ms), 4),
         "per_scale": per_s,
         "path_hbm_frac": round(path_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "copy_GBs_measured": round(copy_gbs, 1),
+        "path_frac_of_copy": round(path_bytes / (ms_per_step / 1e3) / 1e9 / copy_gbs, 4),
         "wall_s": round(t_wall, 3),
         "roofline": roofline,
     }
