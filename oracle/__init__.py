@@ -67,6 +67,19 @@ class StepOut(C.Structure):
                 ("est", C.c_double * (2 * DMAX)), ("rec", C.c_double * (2 * DMAX))]
 
 
+class PfCfg(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mode", C.c_int32), ("ess_num", C.c_int32),
+                ("ess_den", C.c_int32), ("sampler_id", C.c_uint32), ("seed", C.c_uint64),
+                ("delta", C.c_double), ("obs_var", C.c_double), ("obs_log_norm", C.c_double),
+                ("init_mean", C.c_double * 4), ("init_sd", C.c_double),
+                ("y", C.POINTER(C.c_double)), ("T", C.c_int32), ("pad", C.c_int32)]
+
+
+class PfOut(C.Structure):
+    _fields_ = [("info", ResampleInfo), ("log_c", C.c_double), ("mean", C.c_double * 4),
+                ("m2", C.c_double * 4)]
+
+
 _lib = None
 
 
@@ -80,6 +93,15 @@ def lib():
         L.orc_det_exp.restype = C.c_double
         L.orc_det_log.argtypes = [C.c_double]
         L.orc_det_log.restype = C.c_double
+        L.orc_det_atan.argtypes = [C.c_double]
+        L.orc_det_atan.restype = C.c_double
+        L.orc_pf_init.argtypes = [P(PfCfg), P(C.c_double), P(C.c_double), P(C.c_double)]
+        L.orc_pf_init.restype = C.c_int
+        L.orc_pf_step.argtypes = [P(PfCfg), C.c_uint32, P(C.c_double), P(C.c_double),
+                                  P(C.c_double), P(PfOut)]
+        L.orc_pf_step.restype = C.c_int
+        L.orc_pf_loglik.argtypes = [P(PfCfg), P(C.c_double), C.c_double]
+        L.orc_pf_loglik.restype = C.c_double
         L.orc_normals.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                   C.c_int32, P(C.c_double)]
         L.orc_resample_draw.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32]
@@ -125,6 +147,10 @@ def det_exp(x: float) -> float:
 
 def det_log(x: float) -> float:
     return lib().orc_det_log(float(x))
+
+
+def det_atan(x: float) -> float:
+    return lib().orc_det_atan(float(x))
 
 
 def normals(seed, tag, sampler_id, t, idx, d):
@@ -264,3 +290,46 @@ def gauss_log_norm(var) -> float:
 def student_log_norm(nu: float) -> float:
     import math
     return math.lgamma(0.5 * (nu + 1.0)) - math.lgamma(0.5 * nu) - 0.5 * math.log(nu * math.pi)
+
+
+class ParticleFilter:
+    """Alg 1 (SIR) on the bearing-only tracking model, host arrays x [N][4]."""
+
+    def __init__(self, n, y, *, seed=0, sampler_id=0, mode=MODE_AUTO, ess_num=1, ess_den=2,
+                 delta=1.0, obs_var=1e-4, init_mean=(0.0, 0.0, 0.0, 0.0), init_sd=1.0,
+                 obs_log_norm=None):
+        import math
+        self.y = np.ascontiguousarray(y, dtype=np.float64)
+        c = self.cfg = PfCfg()
+        c.n, c.mode, c.ess_num, c.ess_den = n, mode, ess_num, ess_den
+        c.sampler_id, c.seed, c.delta, c.obs_var = sampler_id, seed, delta, obs_var
+        c.obs_log_norm = (obs_log_norm if obs_log_norm is not None
+                          else -0.5 * math.log(2.0 * math.pi * obs_var))
+        for k in range(4):
+            c.init_mean[k] = init_mean[k]
+        c.init_sd, c.y, c.T = init_sd, _p(self.y, C.c_double), self.y.size
+        self.x = np.zeros((n, 4), dtype=np.float64)
+        self.logw = np.zeros(n, dtype=np.float64)
+        self.logZ_prev = C.c_double(0.0)
+        self.t = 0
+
+    def init(self):
+        if lib().orc_pf_init(C.byref(self.cfg), _p(self.x, C.c_double), _p(self.logw, C.c_double),
+                             C.byref(self.logZ_prev)) != E_OK:
+            raise ValueError("pf init failed")
+        self.t = 0
+
+    def step(self):
+        self.t += 1
+        out = PfOut()
+        rc = lib().orc_pf_step(C.byref(self.cfg), self.t, _p(self.x, C.c_double),
+                               _p(self.logw, C.c_double), C.byref(self.logZ_prev),
+                               C.byref(out))
+        if rc != E_OK:
+            raise ValueError("pf step failed: %d" % rc)
+        return {"info": out.info.as_dict(), "log_c": out.log_c, "mean": np.array(out.mean[:]),
+                "m2": np.array(out.m2[:])}
+
+    def loglik(self, x, y):
+        xa = np.ascontiguousarray(x, dtype=np.float64)
+        return lib().orc_pf_loglik(C.byref(self.cfg), _p(xa, C.c_double), float(y))

@@ -38,7 +38,15 @@
  *     polynomial of degree 13 by Horner with fused multiply-add, ldexp.
  *   - det_log: reduction to m in [sqrt(1/2), sqrt(2)), log m = 2 atanh(f),
  *     f = (m-1)/(m+1), odd series to f^23 by Horner in f^2 with FMA.
+ *   - det_atan: atan(1/a) = pi/2 - atan(a) folds |z| to [0, 1]; two argument
+ *     halvings a <- a / (1 + sqrt(1 + a^2)) bring it below tan(pi/16); odd
+ *     Taylor series to a^25; times 4.
  *   - normals: Marsaglia-Bray polar method on Philox uniforms.
+ *
+ * SIR particle filter (Alg 1) on the bearing-only tracking model of Sec. 5.2.2:
+ * constant-velocity state [x, vx, y, vy], process noise with the paper's block
+ * covariance, bearing measurement arctan(y / x) plus Gaussian noise; the
+ * proposal is the transition, so the weight update is the likelihood.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fno-fast-math -shared -fPIC.
  */
@@ -132,6 +140,30 @@ double orc_det_log(double x)
     double lm = f * p;
     double E = (double)e;
     return fma(E, ORC_LN2_HI, fma(E, ORC_LN2_LO, lm));
+}
+
+static const double ORC_PI_2_HI = 1.57079632679489655800e+00; /* pi/2 rounded */
+static const double ORC_PI_2_LO = 6.12323399573676603587e-17; /* pi/2 - PI_2_HI */
+
+double orc_det_atan(double z)
+{
+    if (z != z) return z;
+    int neg = z < 0.0;
+    double a = neg ? -z : z;
+    int inv = a > 1.0;
+    if (inv) a = 1.0 / a;
+    a = a / (1.0 + sqrt(fma(a, a, 1.0)));
+    a = a / (1.0 + sqrt(fma(a, a, 1.0)));
+    double s = a * a;
+    /* atan(a) / a = sum_k (-1)^k s^k / (2k + 1), k = 0..12 */
+    double p = 1.0 / 25.0;
+    for (int k = 11; k >= 0; --k) {
+        double c = 1.0 / (double)(2 * k + 1);
+        p = fma(p, -s, c);
+    }
+    double r = 4.0 * (a * p);
+    if (inv) r = (ORC_PI_2_HI - r) + ORC_PI_2_LO;
+    return neg ? -r : r;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -512,5 +544,124 @@ int orc_smc_step(const orc_smc_cfg *c, uint32_t t, double *x, double *logw, doub
         rec->logZ_prev = out->info.logZ;
     }
     free(nc);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* SIR particle filter (Alg 1), bearing-only tracking (Sec. 5.2.2).          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    int32_t mode, ess_num, ess_den;
+    uint32_t sampler_id;
+    uint64_t seed;
+    double delta;         /* sampling period */
+    double obs_var;       /* variance of the bearing noise */
+    double obs_log_norm;  /* -0.5 log(2 pi obs_var) */
+    double init_mean[4];  /* X0 ~ N(init_mean, init_sd^2 I) */
+    double init_sd;
+    const double *y;      /* measurements y[t-1] for t = 1..T */
+    int32_t T;
+    int32_t pad;
+} orc_pf_cfg;
+
+typedef struct {
+    orc_resample_info info;
+    double log_c;       /* log of sum w_t / sum w_{t-1}: evidence increment */
+    double mean[4];     /* weighted mean after resampling (Alg 1 order) */
+    double m2[4];
+} orc_pf_out;
+
+/* Cholesky factor of the 2x2 process-noise block [[5 D^3/3, 5 D^2/2], [5 D^2/2, 5 D]]. */
+static void orc_pf_chol(double D, double *l11, double *l21, double *l22)
+{
+    double s11 = 5.0 * D * D * D / 3.0, s21 = 5.0 * D * D / 2.0, s22 = 5.0 * D;
+    *l11 = sqrt(s11);
+    *l21 = s21 / *l11;
+    *l22 = sqrt(s22 - *l21 * *l21);
+}
+
+int orc_pf_init(const orc_pf_cfg *c, double *x, double *logw, double *logZ_prev)
+{
+    if (c->n < 1) return ORC_E_ARG;
+    double z[4];
+    double reset = -log((double)c->n);
+    for (int64_t i = 0; i < c->n; ++i) {
+        orc_normals(c->seed, ORC_TAG_INIT, c->sampler_id, 0u, (uint32_t)i, 4, z);
+        for (int k = 0; k < 4; ++k) x[i * 4 + k] = c->init_mean[k] + c->init_sd * z[k];
+        logw[i] = reset;
+    }
+    *logZ_prev = 0.0;
+    return ORC_OK;
+}
+
+/* Bearing log-likelihood of one particle: log N(y; atan(x2 / x0), obs_var). */
+double orc_pf_loglik(const orc_pf_cfg *c, const double *xi, double y)
+{
+    double h = orc_det_atan(xi[2] / xi[0]);
+    double e = y - h;
+    double prec = 1.0 / c->obs_var;
+    return c->obs_log_norm - 0.5 * ((e * e) * prec);
+}
+
+int orc_pf_step(const orc_pf_cfg *c, uint32_t t, double *x, double *logw, double *logZ_prev,
+                orc_pf_out *out)
+{
+    if (t < 1 || (int32_t)t > c->T) return ORC_E_ARG;
+    int64_t n = c->n;
+    double l11, l21, l22, z[4];
+    orc_pf_chol(c->delta, &l11, &l21, &l22);
+    double y = c->y[t - 1];
+    memset(out, 0, sizeof(*out));
+    /* importance sampling with the transition as proposal */
+    for (int64_t i = 0; i < n; ++i) {
+        double *xi = x + i * 4;
+        orc_normals(c->seed, ORC_TAG_PROPOSE, c->sampler_id, t, (uint32_t)i, 4, z);
+        double v0 = l11 * z[0];
+        double v1 = l21 * z[0] + l22 * z[1];
+        double v2 = l11 * z[2];
+        double v3 = l21 * z[2] + l22 * z[3];
+        double n0 = (xi[0] + c->delta * xi[1]) + v0;
+        double n1 = xi[1] + v1;
+        double n2 = (xi[2] + c->delta * xi[3]) + v2;
+        double n3 = xi[3] + v3;
+        xi[0] = n0; xi[1] = n1; xi[2] = n2; xi[3] = n3;
+        logw[i] = logw[i] + orc_pf_loglik(c, xi, y);
+    }
+    int64_t *nc = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!nc) return ORC_E_ARG;
+    uint64_t r = orc_resample_draw(c->seed, c->sampler_id, t);
+    int rc = orc_resample(logw, n, r, c->mode, c->ess_num, c->ess_den, nc, &out->info);
+    if (rc != ORC_OK) { free(nc); return rc; }
+    out->log_c = out->info.logZ - *logZ_prev;
+    if (out->info.resampled) {
+        double *xn = (double *)malloc(sizeof(double) * (size_t)(n * 4));
+        if (!xn) { free(nc); return ORC_E_ARG; }
+        orc_redistribute(n, nc, x, 32, xn, NULL);
+        memcpy(x, xn, sizeof(double) * (size_t)(n * 4));
+        free(xn);
+        double reset = -log((double)n);
+        for (int64_t i = 0; i < n; ++i) logw[i] = reset;
+        *logZ_prev = 0.0;
+    } else {
+        *logZ_prev = out->info.logZ;
+    }
+    free(nc);
+    /* weighted mean of the particles after resampling */
+    double m = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) if (logw[i] > m) m = logw[i];
+    double Z = 0.0, cz = 0.0;
+    for (int64_t i = 0; i < n; ++i) neu_add(&Z, &cz, exp(logw[i] - m));
+    Z += cz;
+    for (int k = 0; k < 4; ++k) {
+        double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double e = exp(logw[i] - m), xv = x[i * 4 + k];
+            neu_add(&s1, &c1, e * xv);
+            neu_add(&s2, &c2, e * xv * xv);
+        }
+        out->mean[k] = (s1 + c1) / Z;
+        out->m2[k] = (s2 + c2) / Z;
+    }
     return ORC_OK;
 }

@@ -83,3 +83,27 @@ def logreg_data(m_rows: int, d: int, seed: int):
     p = 1.0 / (1.0 + np.exp(-z))
     y = (rng.random(m_rows) < p).astype(np.float64)
     return X, y, theta
+
+
+# Bearing-only tracking (SIR particle filter): constant-velocity state
+# [x, vx, y, vy], sampling period 1 s, process noise covariance per axis
+# [[5/3, 5/2], [5/2, 5]], bearing noise variance 1e-4, X0 ~ N(true X0, I).
+BEARING = dict(delta=1.0, obs_var=1e-4, x0=(10.0, -1.0, 10.0, 1.0), init_sd=1.0, T=100)
+
+
+def bearing_track(T: int, seed: int, x0=BEARING["x0"], delta=BEARING["delta"],
+                  obs_var=BEARING["obs_var"]):
+    """Simulated true states [T+1][4] and bearings y[T] = arctan(x2/x0) + noise."""
+    rng = np.random.default_rng(seed)
+    A = np.array([[1, delta, 0, 0], [0, 1, 0, 0], [0, 0, 1, delta], [0, 0, 0, 1]], float)
+    blk = np.array([[5 * delta**3 / 3, 5 * delta**2 / 2], [5 * delta**2 / 2, 5 * delta]])
+    Q = np.zeros((4, 4))
+    Q[:2, :2] = blk
+    Q[2:, 2:] = blk
+    L = np.linalg.cholesky(Q)
+    xs = [np.asarray(x0, float)]
+    ys = []
+    for _ in range(T):
+        xs.append(A @ xs[-1] + L @ rng.standard_normal(4))
+        ys.append(np.arctan(xs[-1][2] / xs[-1][0]) + np.sqrt(obs_var) * rng.standard_normal())
+    return np.array(xs), np.array(ys)

@@ -433,3 +433,77 @@ def test_logreg_log_target_bruteforce():
         ll = np.sum(y.astype(L) * z - np.log1p(np.exp(z)))
         pr = -L(0.5) * np.sum(th[i].astype(L) ** 2) / L(10) - L(1.5) * np.log(L(2 * math.pi * 10))
         assert abs(float(ll + pr) - got[i]) < 1e-12 * max(1.0, abs(got[i]))
+
+
+# ------------------------------------------------------ det_atan and the PF
+def test_det_atan_against_long_double():
+    xs = np.concatenate([np.linspace(-50, 50, 4001), np.exp(np.linspace(-30, 30, 801)),
+                         -np.exp(np.linspace(-30, 30, 801)), [1e-300, 1e300, 1.0, -1.0]])
+    ref = np.arctan(xs.astype(np.longdouble))
+    for x, r in zip(xs, ref):
+        got, rr = O.det_atan(float(x)), float(r)
+        assert ulps(got, rr) <= 4.0, (x, got, rr)
+    assert O.det_atan(0.0) == 0.0
+    assert O.det_atan(math.inf) == math.pi / 2 and O.det_atan(-math.inf) == -math.pi / 2
+    assert abs(4 * O.det_atan(1.0) - math.pi) <= 2 * math.ulp(math.pi)
+    for x in (0.3, 2.0, 17.0):
+        assert O.det_atan(-x) == -O.det_atan(x)
+
+
+def pf(n, T=5, seed=1, **kw):
+    B = I.BEARING
+    xs, ys = I.bearing_track(T, 7)
+    args = dict(seed=seed, delta=B["delta"], obs_var=B["obs_var"], init_mean=B["x0"],
+                init_sd=B["init_sd"])
+    args.update(kw)
+    f = O.ParticleFilter(n, ys, **args)
+    f.init()
+    return f, xs, ys
+
+
+def test_pf_transition_moments_closed_form():
+    """With a flat likelihood and no resampling, one step moves the cloud to
+    A mu0 with covariance A A^T + Q (the paper's process noise)."""
+    f, _, _ = pf(1 << 16, obs_var=1e12, mode=O.MODE_NEVER)
+    f.step()
+    A = np.array([[1, 1, 0, 0], [0, 1, 0, 0], [0, 0, 1, 1], [0, 0, 0, 1]], float)
+    Q = np.zeros((4, 4))
+    Q[:2, :2] = Q[2:, 2:] = [[5 / 3, 5 / 2], [5 / 2, 5]]
+    mu = A @ np.array(I.BEARING["x0"])
+    cov = A @ A.T + Q
+    emp_mu = f.x.mean(0)
+    emp_cov = np.cov(f.x.T)
+    se = np.sqrt(np.diag(cov) / f.x.shape[0])
+    assert np.all(np.abs(emp_mu - mu) < 5 * se)
+    assert np.all(np.abs(emp_cov - cov) < 0.05 * np.sqrt(np.outer(np.diag(cov), np.diag(cov))))
+
+
+def test_pf_likelihood_is_bearing_gaussian():
+    f, _, ys = pf(16)
+    rng = np.random.default_rng(3)
+    L = np.longdouble
+    for _ in range(50):
+        x = rng.normal(0, 10, 4)
+        y = float(ys[0])
+        e = L(y) - np.arctan(L(x[2]) / L(x[0]))
+        ref = -L(0.5) * e * e / L(1e-4) - L(0.5) * np.log(L(2) * L(math.pi) * L(1e-4))
+        assert abs(f.loglik(x, y) - float(ref)) < 1e-9 * max(1.0, abs(float(ref)))
+
+
+def test_pf_weighted_bearing_matches_measurement():
+    """After each update the weighted mean bearing of the particles sits within
+    a few noise standard deviations (0.01 rad) of the measured bearing."""
+    f, xs, ys = pf(20000, T=10)
+    for t in range(10):
+        f.step()
+        h = np.arctan(f.x[:, 2] / f.x[:, 0])
+        w = np.exp(f.logw - f.logw.max())
+        w /= w.sum()
+        assert abs(np.sum(w * h) - ys[t]) < 0.05, t
+
+
+def test_pf_evidence_increment_is_ratio_of_weight_sums():
+    f, _, _ = pf(3000, mode=O.MODE_NEVER)
+    before = special.logsumexp(f.logw)
+    out = f.step()
+    assert abs(out["log_c"] - (special.logsumexp(f.logw) - before)) < 1e-10
