@@ -72,12 +72,88 @@ def cpu_baseline(budget_s: float = 12.0):
                                                                          ", ".join(calls), spent)}
 
 
+def sampler_metrics(dev):
+    """SMC iterations per second of whole smc_step iterations (Alg 2) on three
+    workloads; each timed with events around whole runs after warm-up."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1905_10252_amd import inputs as I
+    from paper_1905_10252_amd import smc
+    out = {}
+
+    def timed_steps(S, k):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+        ev[0].record()
+        for i in range(k):
+            S.step(info=False, est=False)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        per = [ev[i].elapsed_time(ev[i + 1]) for i in range(k)]
+        return ev[0].elapsed_time(ev[k]), per
+
+    # 1-D Gaussian N(2,1), N = 1024, 20 iterations per run
+    g = I.GAUSS1D
+    runs, tot, lat = 10, 0.0, []
+    for rep in range(runs + 2):
+        S = smc.Sampler(g["n"], 1, "gauss", seed=rep, rw_sd=g["rw_sd"], init_sd=g["init_sd"],
+                        mean=g["mean"], var=g["var"], device=dev)
+        torch.cuda.synchronize()
+        ms, per = timed_steps(S, g["iters"])
+        if rep >= 2:
+            tot += ms
+            lat += per
+    out["gauss1d_N1024"] = {"iters_per_s": round(runs * g["iters"] / (tot / 1e3), 1),
+                            "us_per_iter": round(1e3 * tot / (runs * g["iters"]), 2),
+                            "p50_us": round(1e3 * pctl(lat, 50), 2),
+                            "p99_us": round(1e3 * pctl(lat, 99), 2)}
+    # Student-t (nu = 5, mu = 1), N = 2^24, resampling every iteration, 100 iterations
+    n = 1 << 24
+    S = smc.Sampler(n, 1, "student", seed=1, rw_sd=0.5, nu=5.0, mu=1.0, mode=smc.L.MODE_FORCE,
+                    device=dev)
+    timed_steps(S, 3)
+    ms, per = timed_steps(S, 100)
+    out["student_t_N2e24_force"] = {"iters_per_s": round(100 / (ms / 1e3), 2),
+                                    "ms_per_iter": round(ms / 100, 4),
+                                    "particles_per_s": round(100 * n / (ms / 1e3), 1),
+                                    "p50_ms": round(pctl(per, 50), 4),
+                                    "p99_ms": round(pctl(per, 99), 4)}
+    del S
+    # SIR particle filter (Alg 1), bearing-only tracking, N = 2^24, 50 updates
+    B = I.BEARING
+    _, ys = I.bearing_track(60, 7)
+    S = smc.Sampler(n, 4, "bearing", seed=2, mean=B["x0"], init_sd=B["init_sd"], obs=ys,
+                    delta=B["delta"], obs_var=B["obs_var"], device=dev)
+    timed_steps(S, 3)
+    ms, per = timed_steps(S, 50)
+    out["bearing_pf_N2e24"] = {"iters_per_s": round(50 / (ms / 1e3), 2),
+                               "ms_per_iter": round(ms / 50, 4),
+                               "particles_per_s": round(50 * n / (ms / 1e3), 1),
+                               "p50_ms": round(pctl(per, 50), 4),
+                               "p99_ms": round(pctl(per, 99), 4)}
+    del S
+    # Bayesian logistic regression: M = 65536, D = 32, N = 2^16
+    c = I.LOGREG
+    X, y, _ = I.logreg_data(c["m_rows"], c["d"], 200)
+    for prec, k in (("bf16", 6), ("f64", 2)):
+        S = smc.Sampler(c["n"], c["d"], "logreg", X=X.astype(np.float64), y=y,
+                        prior_var=c["prior_var"], precision=prec, rw_sd=c["rw_sd"],
+                        init_sd=math.sqrt(c["prior_var"]), device=dev)
+        timed_steps(S, 1)
+        ms, per = timed_steps(S, k)
+        out["logreg_%s" % prec] = {"iters_per_s": round(k / (ms / 1e3), 2),
+                                   "ms_per_iter": round(ms / k, 3)}
+        del S
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-samplers", action="store_true", help="skip the smc_step workloads")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one plain device copy of the 1 GiB particle array "
                          "(reference for hardware byte counters)")
@@ -203,6 +279,8 @@ def main():
         "wall_s": round(t_wall, 3),
         "roofline": roofline,
     }
+    if not args.no_samplers:
+        out["smc_iters"] = sampler_metrics(dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -47,7 +47,11 @@ typedef enum smc_status {
 } smc_status;
 
 enum { SMC_DTYPE_F32 = 0, SMC_DTYPE_F64 = 1 };
-enum { SMC_TARGET_NONE = 0, SMC_TARGET_GAUSS = 1, SMC_TARGET_STUDENT = 2, SMC_TARGET_LOGREG = 3 };
+/* Targets of smc_step: the SMC sampler of Alg 2 on a Gaussian, Student-t or
+ * logistic-regression posterior (random-walk proposal, L = q), or the SIR
+ * particle filter of Alg 1 on the bearing-only tracking model (Sec. 5.2.2). */
+enum { SMC_TARGET_NONE = 0, SMC_TARGET_GAUSS = 1, SMC_TARGET_STUDENT = 2, SMC_TARGET_LOGREG = 3,
+       SMC_TARGET_BEARING = 4 };
 /* Resampling trigger: the ESS rule of Alg 2 (resample when ESS < N*), always,
  * or never. */
 enum { SMC_MODE_AUTO = 0, SMC_MODE_FORCE = 1, SMC_MODE_NEVER = 2 };
@@ -74,13 +78,19 @@ typedef struct smc_config {
     double init_sd;
     double init_log_norm;    /* additive constant of log q0                            */
     double log_norm;         /* additive constant of log pi                            */
-    const double *mean;      /* GAUSS: [d] target mean                                 */
+    const double *mean;      /* GAUSS: [d] target mean; BEARING: [4] mean of X0        */
     const double *prec;      /* GAUSS: [d] target precision (1 / variance)             */
     double nu, mu;           /* STUDENT (d = 1): degrees of freedom, location          */
     int64_t m_rows;          /* LOGREG: data rows M                                    */
     const void *X;           /* LOGREG: [M][d] row-major, FP64 or BF16 (precision)     */
     const double *y;         /* LOGREG: [M] labels in {0, 1}                           */
     double prior_prec;       /* LOGREG: prior N(0, I / prior_prec)                     */
+    const double *obs;       /* BEARING: [n_obs] bearings, y_t used at iteration t     */
+    int32_t n_obs;           /* BEARING: number of measurements (iterations allowed)   */
+    int32_t pad0;
+    double delta;            /* BEARING: sampling period                               */
+    double obs_var;          /* BEARING: bearing noise variance                        */
+    double obs_log_norm;     /* BEARING: -0.5 log(2 pi obs_var)                        */
 } smc_config;
 
 /* Per-call summary written on the device (nullable everywhere). */
@@ -115,7 +125,11 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
  * estimate, ESS, and resampling when the configured trigger fires (then x
  * holds the redistributed particles and logw = -ln N).  est (nullable, [4d])
  * receives f_t (eq. estimation_at_t), sum w~ x^2, and the recycled estimates
- * of both (eq. recycling). */
+ * of both (eq. recycling).  For SMC_TARGET_BEARING it is one iteration of
+ * Alg 1 instead: transition proposal, likelihood weight, normalise, ESS,
+ * resampling, then the weighted mean (est[0..d)) and second moment
+ * (est[d..2d)) of the resampled population; info->log_c is then the log
+ * evidence increment.  Returns SMC_E_ARG past the last measurement. */
 smc_status smc_step(smc_ctx *ctx, void *x, double *logw, smc_resample_info *info, double *est,
                     void *stream);
 

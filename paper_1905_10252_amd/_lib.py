@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(PKG, "libsmc.so")
 SMC_OK, SMC_E_ARG, SMC_E_NONFINITE, SMC_E_DEGENERATE = 0, 1, 2, 3
 SMC_E_NOMEM, SMC_E_DEVICE, SMC_E_UNSUPPORTED = 4, 5, 6
 DTYPE_F32, DTYPE_F64 = 0, 1
-TARGET_NONE, TARGET_GAUSS, TARGET_STUDENT, TARGET_LOGREG = 0, 1, 2, 3
+TARGET_NONE, TARGET_GAUSS, TARGET_STUDENT, TARGET_LOGREG, TARGET_BEARING = 0, 1, 2, 3, 4
 MODE_AUTO, MODE_FORCE, MODE_NEVER = 0, 1, 2
 PREC_F64, PREC_BF16 = 0, 1
 
@@ -35,6 +35,8 @@ class SmcConfig(C.Structure):
         ("init_log_norm", C.c_double), ("log_norm", C.c_double),
         ("mean", C.c_void_p), ("prec", C.c_void_p), ("nu", C.c_double), ("mu", C.c_double),
         ("m_rows", C.c_int64), ("X", C.c_void_p), ("y", C.c_void_p), ("prior_prec", C.c_double),
+        ("obs", C.c_void_p), ("n_obs", C.c_int32), ("pad0", C.c_int32), ("delta", C.c_double),
+        ("obs_var", C.c_double), ("obs_log_norm", C.c_double),
     ]
 
 

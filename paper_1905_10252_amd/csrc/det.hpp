@@ -10,6 +10,10 @@
 //   det_log : x = m 2^e with m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(f),
 //             f = (m - 1)/(m + 1), odd series through f^23 (Horner in f^2,
 //             fma); result e ln2_hi + (e ln2_lo + log m) with fma.
+//   det_atan: |z| > 1 folded by atan z = pi/2 - atan(1/z); two halvings
+//             a <- a / (1 + sqrt(1 + a^2)) (atan a = 2 atan of the result);
+//             odd Taylor series of atan to a^25 by Horner in a^2 with fma;
+//             times 4; pi/2 as a two-part constant.
 //   Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and standard normals by
 //   the Marsaglia-Bray polar method on its 53-bit uniforms.
 #pragma once
@@ -73,6 +77,43 @@ __host__ __device__ inline double det_log(double x)
     return fma(E, 0x1.62e42fee00000p-1, fma(E, 0x1.a39ef35793c76p-33, lm));
 }
 
+__host__ __device__ inline double det_sqrt(double v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __dsqrt_rn(v);
+#else
+    return __builtin_sqrt(v);
+#endif
+}
+
+__host__ __device__ inline double det_atan(double z)
+{
+    if (z != z) return z;
+    const bool neg = z < 0.0;
+    double a = neg ? -z : z;
+    const bool inv = a > 1.0;
+    if (inv) a = 1.0 / a;
+    a = a / (1.0 + det_sqrt(fma(a, a, 1.0)));
+    a = a / (1.0 + det_sqrt(fma(a, a, 1.0)));
+    const double s = a * a;
+    double p = 0x1.47ae147ae147bp-5;      // 1/25
+    p = fma(p, -s, 0x1.642c8590b2164p-5);  // 1/23
+    p = fma(p, -s, 0x1.8618618618618p-5);  // 1/21
+    p = fma(p, -s, 0x1.af286bca1af28p-5);  // 1/19
+    p = fma(p, -s, 0x1.e1e1e1e1e1e1ep-5);  // 1/17
+    p = fma(p, -s, 0x1.1111111111111p-4);  // 1/15
+    p = fma(p, -s, 0x1.3b13b13b13b14p-4);  // 1/13
+    p = fma(p, -s, 0x1.745d1745d1746p-4);  // 1/11
+    p = fma(p, -s, 0x1.c71c71c71c71cp-4);  // 1/9
+    p = fma(p, -s, 0x1.2492492492492p-3);  // 1/7
+    p = fma(p, -s, 0x1.999999999999ap-3);  // 1/5
+    p = fma(p, -s, 0x1.5555555555555p-2);  // 1/3
+    p = fma(p, -s, 1.0);                   // 1/1
+    double r = 4.0 * (a * p);
+    if (inv) r = (0x1.921fb54442d18p+0 - r) + 0x1.1a62633145c07p-54;
+    return neg ? -r : r;
+}
+
 // ------------------------------------------------------------- Philox4x32-10
 struct Philox4 {
     uint32_t v[4];
@@ -130,11 +171,7 @@ __host__ __device__ inline void normal_pair(uint64_t seed, uint32_t tag, uint32_
         const double s = v1 * v1 + v2 * v2;
         if (s > 0.0 && s < 1.0) {
             const double c = (-2.0 * det_log(s)) / s;
-#if defined(__HIP_DEVICE_COMPILE__)
-            const double f = __dsqrt_rn(c);
-#else
-            const double f = __builtin_sqrt(c);
-#endif
+            const double f = det_sqrt(c);
             z1 = v1 * f;
             z2 = v2 * f;
             return;

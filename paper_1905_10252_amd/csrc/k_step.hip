@@ -11,6 +11,10 @@
 //                       (eq. recycling).
 //   k_copyback          after redistribute: particles and cached log-target
 //                       back in place, weights reset to 1/N (Alg 4 Reset).
+//   k_is<BEARING>       one SIR particle-filter update (Alg 1, Sec. 5.2.2):
+//                       constant-velocity transition as proposal, bearing
+//                       likelihood as weight; k_post_est then forms the
+//                       weighted mean of the resampled population.
 //   k_logreg_f64 / k_logreg_bf16 + k_logreg_sum
 //                       Bayesian logistic regression log-likelihood
 //                       sum_m [y_m z_m - softplus(z_m)], z = X theta, in FP64 or
@@ -39,6 +43,9 @@ struct TArgs {
     uint64_t seed;
     uint32_t sampler;
     unsigned short *thb;  // bf16 copy of the particles [npad][dp] (nullable)
+    // bearing-only particle filter
+    const double *obs;    // measurements, y_t = obs[t - 1]
+    double delta, l11, l21, l22, obs_prec, obs_log_norm, reset;
 };
 
 __device__ inline unsigned short to_bf16(double v)
@@ -104,6 +111,39 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
     unsigned bad = 0;
     for (i64 i = gtid; i < n; i += gsz) {
         double *xi = x + i * d;
+        if (kKind == SMC_TARGET_BEARING) {
+            double z[4];
+            normal_pair(a.seed, kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose, a.sampler,
+                        kInit ? 0u : t, (uint32_t)i, 0u, z[0], z[1]);
+            normal_pair(a.seed, kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose, a.sampler,
+                        kInit ? 0u : t, (uint32_t)i, 1u, z[2], z[3]);
+            double lw;
+            if (kInit) {
+                for (int k = 0; k < 4; ++k) xi[k] = a.mean[k] + a.init_sd * z[k];
+                lw = a.reset;
+                lp[i] = 0.0;
+            } else {
+                const double v0 = a.l11 * z[0];
+                const double v1 = a.l21 * z[0] + a.l22 * z[1];
+                const double v2 = a.l11 * z[2];
+                const double v3 = a.l21 * z[2] + a.l22 * z[3];
+                const double n0 = (xi[0] + a.delta * xi[1]) + v0;
+                const double n1 = xi[1] + v1;
+                const double n2 = (xi[2] + a.delta * xi[3]) + v2;
+                const double n3 = xi[3] + v3;
+                xi[0] = n0;
+                xi[1] = n1;
+                xi[2] = n2;
+                xi[3] = n3;
+                const double e = a.obs[t - 1] - det_atan(n2 / n0);
+                lw = logw[i] + (a.obs_log_norm - 0.5 * ((e * e) * a.obs_prec));
+            }
+            logw[i] = lw;
+            bad |= (lw != lw) | (lw == __builtin_huge_val());
+            const u64 kk = okey(lw);
+            key = kk > key ? kk : key;
+            continue;
+        }
         double acc = 0.0, acc0 = 0.0;
         for (int k = 0; 2 * k < d; ++k) {
             double z[2];
@@ -180,9 +220,21 @@ __global__ __launch_bounds__(256) void k_step_stats(Ctrl *ctrl, const double *is
 {
     __shared__ double s_col[2 + 2 * kMaxDim];
     __shared__ double s_sc, s_wgt, s_den;
+    __shared__ u64 s_mk[4];
     const int tid = threadIdx.x;
     const int ncol = 2 + 2 * d;
-    const double m = ctrl->m;
+    // reference: the largest block reference (blocks with no weight carry -inf)
+    u64 mk = 0;
+    for (int b = tid; b < nblk; b += 256) {
+        const u64 k = okey(is_part[(i64)b * ncol]);
+        mk = k > mk ? k : mk;
+    }
+    mk = wave_max_u64(mk);
+    if ((tid & 63) == 0) s_mk[tid >> 6] = mk;
+    __syncthreads();
+    for (int i = 1; i < 4; ++i) mk = s_mk[i] > mk ? s_mk[i] : mk;
+    mk = s_mk[0] > mk ? s_mk[0] : mk;
+    const double m = okey_inv(mk);
     for (int c = 1 + tid; c < ncol; c += 256) {
         double acc = 0.0;
         for (int b = 0; b < nblk; ++b) {
@@ -248,6 +300,43 @@ __global__ __launch_bounds__(256) void k_copyback(const Ctrl *ctrl, i64 n, int d
         lp[i] = lp_scr[i];
         logw[i] = reset;
     }
+}
+
+// Weighted sums of the population after resampling (Alg 1 takes its mean
+// after the resampling step), in the block-partial layout of is_block_finish
+// with one common reference weight.
+__global__ __launch_bounds__(256) void k_post_est(const Ctrl *ctrl, i64 n, int d,
+                                                  const double *__restrict__ x,
+                                                  const double *__restrict__ logw, double reset,
+                                                  double *is_part)
+{
+    __shared__ double s_acc[4][2 + 2 * kMaxDim];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
+    const double m = (ctrl->resample && !ctrl->err_call) ? reset : ctrl->m;
+    double e0 = 0.0;
+    for (i64 i = gtid; i < n; i += gsz) e0 += det_exp(logw[i] - m);
+    e0 = wave_sum_f64(e0);
+    if (lane == 0) s_acc[wid][1] = e0;
+    for (int k = 0; k < d; ++k) {
+        double s1 = 0.0, s2 = 0.0;
+        for (i64 i = gtid; i < n; i += gsz) {
+            const double ex = det_exp(logw[i] - m) * x[i * d + k];
+            s1 += ex;
+            s2 += ex * x[i * d + k];
+        }
+        s1 = wave_sum_f64(s1);
+        s2 = wave_sum_f64(s2);
+        if (lane == 0) {
+            s_acc[wid][2 + k] = s1;
+            s_acc[wid][2 + d + k] = s2;
+        }
+    }
+    __syncthreads();
+    const int ncol = 2 + 2 * d;
+    double *part = is_part + (i64)blockIdx.x * ncol;
+    for (int c = tid; c < ncol; c += 256)
+        part[c] = c == 0 ? m : ((s_acc[0][c] + s_acc[1][c]) + s_acc[2][c]) + s_acc[3][c];
 }
 
 // ------------------------------------------------------ cheap log-targets
@@ -430,6 +519,17 @@ TArgs targs(const smc_config &c, const Work &w, bool with_bf16)
     a.seed = c.seed;
     a.sampler = c.sampler_id;
     a.thb = with_bf16 ? w.thb : nullptr;
+    a.obs = c.obs;
+    a.delta = c.delta;
+    const double s11 = 5.0 * c.delta * c.delta * c.delta / 3.0;
+    const double s21 = 5.0 * c.delta * c.delta / 2.0;
+    const double s22 = 5.0 * c.delta;
+    a.l11 = std::sqrt(s11);
+    a.l21 = s21 / a.l11;
+    a.l22 = std::sqrt(s22 - a.l21 * a.l21);
+    a.obs_prec = c.target == SMC_TARGET_BEARING ? 1.0 / c.obs_var : 0.0;
+    a.obs_log_norm = c.obs_log_norm;
+    a.reset = -std::log((double)c.n);
     return a;
 }
 
@@ -448,6 +548,8 @@ bool is_bf16(const smc_config &c)
 hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_t n, double *lp,
                      bool theta_ready, hipStream_t s)
 {
+    if (c.target != SMC_TARGET_LOGREG || !w.lpart || (is_bf16(c) && (!w.xs || !w.thb)))
+        return hipErrorInvalidValue;
     const int msplit = kLogregSplit;
     if (is_bf16(c)) {
         if (!theta_ready) {
@@ -494,7 +596,11 @@ hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, do
                            x, logw, w.lp, sp, w.status, w.n_tiles,
                            w.is_part);
         break;
-    default:
+    case SMC_TARGET_BEARING:
+        hipLaunchKernelGGL((k_is<SMC_TARGET_BEARING, kInit>), dim3(g), dim3(256), 0, s, a, n, t,
+                           x, logw, w.lp, sp, w.status, w.n_tiles, w.is_part);
+        break;
+    case SMC_TARGET_LOGREG:
         hipLaunchKernelGGL((k_is<SMC_TARGET_LOGREG, kInit>), dim3(g), dim3(256), 0, s, a, n, t, x,
                            logw, w.lp, sp, w.status, w.n_tiles,
                            w.is_part);
@@ -503,6 +609,8 @@ hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, do
         hipLaunchKernelGGL(k_reweight<kInit>, dim3(g), dim3(256), 0, s, n, c.d, x, w.lp_new, logw,
                            w.lp, sp, w.status, w.n_tiles, w.is_part);
         break;
+    default:
+        return hipErrorInvalidValue;
     }
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     // initialisation has no scan; its max is folded on its own
@@ -536,14 +644,24 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
     const uint64_t r = resample_word(c.seed, c.sampler_id, t);
     if (launch_decide(w, par, n, K, r, c.mode, c.ess_num, c.ess_den, info, s) != hipSuccess)
         return SMC_E_DEVICE;
-    hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part, grid_for(n),
-                       c.d, w.rec_num, est, info, 0);
-    if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
+    const bool pf = c.target == SMC_TARGET_BEARING;
+    if (!pf) {  // Alg 2 estimates come before resampling
+        hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
+                           grid_for(n), c.d, w.rec_num, est, info, 0);
+        if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
+    }
     if (launch_expand(w, n, 0, x, w.x_scr, c.d * 8, w.lp, w.lp_scr, 8, nullptr, nullptr, s,
                       true) != hipSuccess)
         return SMC_E_DEVICE;
+    const double reset = -std::log((double)n);
     hipLaunchKernelGGL(k_copyback, dim3(grid_for(n * c.d)), dim3(256), 0, s, w.ctrl, (i64)n, c.d,
-                       x, w.x_scr, w.lp, w.lp_scr, logw, -std::log((double)n));
+                       x, w.x_scr, w.lp, w.lp_scr, logw, reset);
+    if (pf) {  // Alg 1 takes the mean after resampling
+        hipLaunchKernelGGL(k_post_est, dim3(grid_for(n)), dim3(256), 0, s, w.ctrl, (i64)n, c.d, x,
+                           logw, reset, w.is_part);
+        hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
+                           grid_for(n), c.d, w.rec_num, est, info, 0);
+    }
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
 

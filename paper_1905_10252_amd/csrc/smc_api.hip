@@ -47,12 +47,16 @@ bool config_ok(const smc_config *c)
     if (c->x_dtype != SMC_DTYPE_F32 && c->x_dtype != SMC_DTYPE_F64) return false;
     if (c->ess_num < 0 || c->ess_num > 16 || c->ess_den < 1 || c->ess_den > 16) return false;
     if (c->mode < SMC_MODE_AUTO || c->mode > SMC_MODE_NEVER) return false;
-    if (c->target < SMC_TARGET_NONE || c->target > SMC_TARGET_LOGREG) return false;
+    if (c->target < SMC_TARGET_NONE || c->target > SMC_TARGET_BEARING) return false;
     if (c->target != SMC_TARGET_NONE) {
         if (c->d > kMaxDim || c->x_dtype != SMC_DTYPE_F64) return false;
         if (!(c->rw_sd >= 0.0) || !(c->init_sd > 0.0)) return false;
         if (c->target == SMC_TARGET_GAUSS && (!c->mean || !c->prec)) return false;
         if (c->target == SMC_TARGET_STUDENT && (c->d != 1 || !(c->nu > 0.0))) return false;
+        if (c->target == SMC_TARGET_BEARING &&
+            (c->d != 4 || !c->mean || !c->obs || c->n_obs < 1 || !(c->delta > 0.0) ||
+             !(c->obs_var > 0.0)))
+            return false;
         if (c->target == SMC_TARGET_LOGREG &&
             (!c->X || !c->y || c->m_rows < 1 || !(c->prior_prec > 0.0) ||
              (c->loglik_precision != SMC_PREC_F64 && c->loglik_precision != SMC_PREC_BF16)))
@@ -250,6 +254,8 @@ smc_status smc_step(smc_ctx *ctx, void *x, double *logw, smc_resample_info *info
     if (((uintptr_t)x & 7) || ((uintptr_t)logw & 7) || ((uintptr_t)info & 7) ||
         ((uintptr_t)est & 7))
         return SMC_E_ARG;
+    if (ctx->cfg.target == SMC_TARGET_BEARING && (int64_t)ctx->t >= (int64_t)ctx->cfg.n_obs)
+        return SMC_E_ARG;  // no measurement left
     ctx->t += 1;
     const int par = ctx->par;
     ctx->par ^= 1;
@@ -261,7 +267,9 @@ smc_status smc_step(smc_ctx *ctx, void *x, double *logw, smc_resample_info *info
 
 smc_status smc_log_target(smc_ctx *ctx, const double *x, int64_t n, double *lp, void *stream)
 {
-    if (!ctx || !x || !lp || n < 1 || ctx->cfg.target == SMC_TARGET_NONE) return SMC_E_ARG;
+    if (!ctx || !x || !lp || n < 1 || ctx->cfg.target == SMC_TARGET_NONE ||
+        ctx->cfg.target == SMC_TARGET_BEARING)
+        return SMC_E_ARG;
     return step_log_target(ctx->cfg, ctx->w, x, n, lp, S(stream));
 }
 

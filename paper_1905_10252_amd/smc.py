@@ -110,15 +110,18 @@ class Sampler:
 
     Particles x [N][d] and log-weights logw [N] are FP64 device tensors owned
     here; every step runs the library's kernels in place on them.
-    Targets: "gauss" (mean, var), "student" (nu, mu; d = 1) and "logreg"
-    (X [M][d], y [M], prior_var; precision "f64" or "bf16").
+    Targets: "gauss" (mean, var), "student" (nu, mu; d = 1), "logreg"
+    (X [M][d], y [M], prior_var; precision "f64" or "bf16"), and "bearing",
+    the SIR particle filter of Alg 1 (mean = X0 mean, obs = bearings, delta,
+    obs_var; d = 4).
     """
 
     def __init__(self, n: int, d: int, target: str, *, seed: int = 0, sampler_id: int = 0,
                  rw_sd: float = 0.5, init_mean: float = 0.0, init_sd: float = 3.0,
                  mode: int = L.MODE_AUTO, ess_num: int = 1, ess_den: int = 2, mean=None,
                  var=None, nu=None, mu=None, X=None, y=None, prior_var=None,
-                 precision: str = "f64", log_norm=None, init_log_norm=None, device=None):
+                 precision: str = "f64", log_norm=None, init_log_norm=None, obs=None,
+                 delta: float = 1.0, obs_var: float = 1e-4, device=None):
         lib = L.load()
         self._lib = lib
         self.n, self.d = int(n), int(d)
@@ -158,6 +161,18 @@ class Sampler:
             cfg.loglik_precision = L.PREC_BF16 if precision == "bf16" else L.PREC_F64
             cfg.log_norm = (log_norm if log_norm is not None
                             else -0.5 * d * math.log(2.0 * math.pi * prior_var))
+        elif target == "bearing":
+            # SIR particle filter (Alg 1): mean = X0 mean [4], obs = bearings
+            if d != 4:
+                raise ValueError("the bearing-only model has d = 4")
+            cfg.target = L.TARGET_BEARING
+            m = torch.as_tensor(mean, dtype=torch.float64).reshape(-1).to(dev)
+            ob = torch.as_tensor(obs, dtype=torch.float64).reshape(-1).to(dev)
+            self._keep += [m, ob]
+            cfg.mean, cfg.obs, cfg.n_obs = m.data_ptr(), ob.data_ptr(), ob.numel()
+            cfg.delta, cfg.obs_var = delta, obs_var
+            cfg.obs_log_norm = (log_norm if log_norm is not None
+                                else -0.5 * math.log(2.0 * math.pi * obs_var))
         else:
             raise ValueError("unknown target %r" % target)
         self.cfg = cfg

@@ -68,4 +68,4 @@ def test_status_strings(lib):
 def test_struct_sizes_match_header():
     from paper_1905_10252_amd import _lib as L
     assert C.sizeof(L.SmcInfo) == 96
-    assert C.sizeof(L.SmcConfig) == 152  # sizeof(smc_config) on x86-64 (gcc)
+    assert C.sizeof(L.SmcConfig) == 192  # sizeof(smc_config) on x86-64 (gcc)

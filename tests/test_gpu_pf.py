@@ -1,0 +1,85 @@
+"""GPU parity of the SIR particle filter (Alg 1, bearing-only tracking) run
+through smc_init / smc_step, against the CPU oracle.
+
+The transition, the deterministic arctan and the likelihood are fixed IEEE
+sequences and resampling is integer-exact, so particle trajectories and
+log-weights must match bit for bit; the post-resampling mean and the log
+evidence increment are FP64 sums in another order (1e-11 relative).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_10252_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smc(dev):
+    from paper_1905_10252_amd import smc as S
+    return S
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint64)
+
+
+def pair(smc, dev, n, T, mode, seed=3, track_seed=7):
+    B = I.BEARING
+    _, ys = I.bearing_track(T, track_seed)
+    g = smc.Sampler(n, 4, "bearing", seed=seed, mean=B["x0"], init_sd=B["init_sd"], obs=ys,
+                    delta=B["delta"], obs_var=B["obs_var"], mode=mode, device=dev)
+    o = O.ParticleFilter(n, ys, seed=seed, delta=B["delta"], obs_var=B["obs_var"],
+                         init_mean=B["x0"], init_sd=B["init_sd"], mode=mode,
+                         obs_log_norm=g.cfg.obs_log_norm)
+    o.init()
+    return g, o
+
+
+def close(a, b, rtol):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.max(np.abs(a - b) / np.maximum(np.abs(b), 1.0)) <= rtol
+
+
+@pytest.mark.parametrize("n,mode", [(1, O.MODE_AUTO), (1000, O.MODE_AUTO), (4097, O.MODE_FORCE),
+                                    (100003, O.MODE_AUTO), (30000, O.MODE_NEVER)])
+def test_pf_trajectory_bit_exact(smc, dev, n, mode):
+    print("pf n=%d mode=%d" % (n, mode), flush=True)
+    T = 12
+    g, o = pair(smc, dev, n, T, mode)
+    assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x))
+    assert np.array_equal(bits(g.logw.cpu().numpy()), bits(o.logw))
+    for t in range(1, T + 1):
+        g.step()
+        out = o.step()
+        info = g.info()
+        for k in ("S", "U", "Q2_hi", "Q2_lo", "resampled", "err"):
+            assert info[k] == out["info"][k], (t, k)
+        assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x)), t
+        assert np.array_equal(bits(g.logw.cpu().numpy()), bits(o.logw)), t
+        e = g.estimates()
+        assert close(e["mean"], out["mean"], 1e-11), (t, e["mean"], out["mean"])
+        assert close(e["m2"], out["m2"], 1e-11), t
+        assert abs(info["log_c"] - out["log_c"]) <= 1e-10 * max(1.0, abs(out["log_c"])), t
+    assert g.sync_error() == 0
+
+
+def test_pf_stops_after_last_measurement(smc, dev):
+    g, _ = pair(smc, dev, 100, 3, O.MODE_AUTO)
+    for _ in range(3):
+        g.step()
+    with pytest.raises(smc.L.SmcError):
+        g.step()
+
+
+def test_pf_large_population(smc, dev):
+    print("pf n=2^20", flush=True)
+    g, o = pair(smc, dev, 1 << 20, 4, O.MODE_AUTO, seed=11)
+    for t in range(4):
+        g.step()
+        o.step()
+    assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x))
+    assert np.array_equal(bits(g.logw.cpu().numpy()), bits(o.logw))
