@@ -95,13 +95,91 @@ __device__ inline void is_block_finish(i64 n, int d, const double *x, const doub
     slot_publish(slots_p, bk, bad);
 }
 
+// One-pass variant for small d (the row stays in registers): each thread keeps
+// a running reference max and rescales its sums when the max grows, so the
+// rows are read once; blocks combine the thread references with exact
+// power-free rescaling by det_exp.
+template <int DT>
+struct Online {
+    double m, e0, e1[DT], e2[DT];
+    __device__ void init()
+    {
+        m = -__builtin_huge_val();
+        e0 = 0.0;
+        for (int k = 0; k < DT; ++k) e1[k] = e2[k] = 0.0;
+    }
+    __device__ void add(double lw, const double *xv)
+    {
+        if (!(lw > -__builtin_huge_val())) return;  // zero weight, or NaN (flagged elsewhere)
+        if (lw > m) {
+            if (m > -__builtin_huge_val()) {
+                const double sc = det_exp(m - lw);
+                e0 *= sc;
+                for (int k = 0; k < DT; ++k) {
+                    e1[k] *= sc;
+                    e2[k] *= sc;
+                }
+            }
+            m = lw;
+        }
+        const double e = det_exp(lw - m);
+        e0 += e;
+        for (int k = 0; k < DT; ++k) {
+            const double ex = e * xv[k];
+            e1[k] += ex;
+            e2[k] += ex * xv[k];
+        }
+    }
+    // Block combine into part = [m_b, sum e, sum e x_k, sum e x_k^2].
+    __device__ void finish(double *part)
+    {
+        __shared__ double s_m[4], s_acc[4][1 + 2 * DT];
+        const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+        const double mw = wave_max_f64(m);
+        const double sc = m > -__builtin_huge_val() ? det_exp(m - mw) : 0.0;
+        const double a0 = wave_sum_f64(e0 * sc);
+        double a1[DT], a2[DT];
+        for (int k = 0; k < DT; ++k) {
+            a1[k] = wave_sum_f64(e1[k] * sc);
+            a2[k] = wave_sum_f64(e2[k] * sc);
+        }
+        if (lane == 0) {
+            s_m[wid] = mw;
+            s_acc[wid][0] = a0;
+            for (int k = 0; k < DT; ++k) {
+                s_acc[wid][1 + k] = a1[k];
+                s_acc[wid][1 + DT + k] = a2[k];
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double mb = s_m[0];
+            for (int w = 1; w < 4; ++w) mb = fmax(mb, s_m[w]);
+            double scw[4];
+            for (int w = 0; w < 4; ++w)
+                scw[w] = s_m[w] > -__builtin_huge_val() ? det_exp(s_m[w] - mb) : 0.0;
+            part[0] = mb;
+            for (int c = 0; c < 1 + 2 * DT; ++c) {
+                double v = 0.0;
+                for (int w = 0; w < 4; ++w) v += scw[w] * s_acc[w][c];
+                part[1 + c] = v;
+            }
+        }
+    }
+};
+
 // ------------------------------------------------------- proposal + weights
-template <int kKind, bool kInit>
+// DT > 0: d == DT and the estimate sums are accumulated in one pass; DT == 0:
+// any d, sums in a second pass over the block's particles.  The particle filter
+// takes its estimate after resampling, so its update kernel skips them.
+template <int kKind, bool kInit, int DT>
 __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *__restrict__ x,
                                             double *__restrict__ logw, double *__restrict__ lp,
                                             u64 *slots_p, u64 *status, int n_status,
                                             double *is_part)
 {
+    constexpr bool kEst = kKind != SMC_TARGET_BEARING;
+    constexpr int DA = DT > 0 ? DT : 1;
     const int tid = threadIdx.x;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
     if (kKind != SMC_TARGET_LOGREG)
@@ -109,6 +187,9 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
     const int d = a.d;
     u64 key = 0;
     unsigned bad = 0;
+    Online<DA> on;
+    on.init();
+    double xv[DA];
     for (i64 i = gtid; i < n; i += gsz) {
         double *xi = x + i * d;
         if (kKind == SMC_TARGET_BEARING) {
@@ -152,15 +233,16 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
             for (int h = 0; h < 2; ++h) {
                 const int kk = 2 * k + h;
                 if (kk >= d) break;
-                const double xv = kInit ? a.init_mean + a.init_sd * z[h] : xi[kk] + a.rw_sd * z[h];
-                xi[kk] = xv;
-                if (a.thb) a.thb[i * a.dp + kk] = to_bf16(xv);
+                const double xk = kInit ? a.init_mean + a.init_sd * z[h] : xi[kk] + a.rw_sd * z[h];
+                xi[kk] = xk;
+                if (DT > 0 && kk < DT) xv[kk] = xk;
+                if (a.thb) a.thb[i * a.dp + kk] = to_bf16(xk);
                 if (kKind == SMC_TARGET_GAUSS) {
-                    const double tt = xv - a.mean[kk];
+                    const double tt = xk - a.mean[kk];
                     acc = acc + (tt * tt) * a.prec[kk];
                 }
                 if (kInit) {
-                    const double t0 = xv - a.init_mean;
+                    const double t0 = xk - a.init_mean;
                     acc0 = acc0 + (t0 * t0) * a.init_prec;
                 }
             }
@@ -184,8 +266,15 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
         bad |= (lw != lw) | (lw == __builtin_huge_val());
         const u64 kk = okey(lw);
         key = kk > key ? kk : key;
+        if (DT > 0) on.add(lw, xv);
     }
     if (kKind == SMC_TARGET_LOGREG) return;
+    if (!kEst || DT > 0) {
+        const u64 bk = block_max_key(key, bad);
+        if (kEst) on.finish(is_part + (i64)blockIdx.x * (2 + 2 * DA));
+        slot_publish(slots_p, bk, bad);
+        return;
+    }
     is_block_finish(n, d, x, logw, key, bad, slots_p, is_part);
 }
 
@@ -305,38 +394,45 @@ __global__ __launch_bounds__(256) void k_copyback(const Ctrl *ctrl, i64 n, int d
 // Weighted sums of the population after resampling (Alg 1 takes its mean
 // after the resampling step), in the block-partial layout of is_block_finish
 // with one common reference weight.
+template <int DT>
 __global__ __launch_bounds__(256) void k_post_est(const Ctrl *ctrl, i64 n, int d,
                                                   const double *__restrict__ x,
                                                   const double *__restrict__ logw, double reset,
                                                   double *is_part)
 {
-    __shared__ double s_acc[4][2 + 2 * kMaxDim];
+    __shared__ double s_acc[4][1 + 2 * DT];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
     const double m = (ctrl->resample && !ctrl->err_call) ? reset : ctrl->m;
-    double e0 = 0.0;
-    for (i64 i = gtid; i < n; i += gsz) e0 += det_exp(logw[i] - m);
-    e0 = wave_sum_f64(e0);
-    if (lane == 0) s_acc[wid][1] = e0;
-    for (int k = 0; k < d; ++k) {
-        double s1 = 0.0, s2 = 0.0;
-        for (i64 i = gtid; i < n; i += gsz) {
-            const double ex = det_exp(logw[i] - m) * x[i * d + k];
-            s1 += ex;
-            s2 += ex * x[i * d + k];
+    double e0 = 0.0, e1[DT], e2[DT];
+    for (int k = 0; k < DT; ++k) e1[k] = e2[k] = 0.0;
+    for (i64 i = gtid; i < n; i += gsz) {
+        const double e = det_exp(logw[i] - m);
+        e0 += e;
+        for (int k = 0; k < DT; ++k) {
+            const double xk = x[i * DT + k];
+            const double ex = e * xk;
+            e1[k] += ex;
+            e2[k] += ex * xk;
         }
-        s1 = wave_sum_f64(s1);
-        s2 = wave_sum_f64(s2);
-        if (lane == 0) {
-            s_acc[wid][2 + k] = s1;
-            s_acc[wid][2 + d + k] = s2;
+    }
+    e0 = wave_sum_f64(e0);
+    for (int k = 0; k < DT; ++k) {
+        e1[k] = wave_sum_f64(e1[k]);
+        e2[k] = wave_sum_f64(e2[k]);
+    }
+    if (lane == 0) {
+        s_acc[wid][0] = e0;
+        for (int k = 0; k < DT; ++k) {
+            s_acc[wid][1 + k] = e1[k];
+            s_acc[wid][1 + DT + k] = e2[k];
         }
     }
     __syncthreads();
-    const int ncol = 2 + 2 * d;
-    double *part = is_part + (i64)blockIdx.x * ncol;
-    for (int c = tid; c < ncol; c += 256)
-        part[c] = c == 0 ? m : ((s_acc[0][c] + s_acc[1][c]) + s_acc[2][c]) + s_acc[3][c];
+    double *part = is_part + (i64)blockIdx.x * (2 + 2 * DT);
+    for (int c = tid; c < 2 + 2 * DT; c += 256)
+        part[c] = c == 0 ? m : ((s_acc[0][c - 1] + s_acc[1][c - 1]) + s_acc[2][c - 1]) +
+                                   s_acc[3][c - 1];
 }
 
 // ------------------------------------------------------ cheap log-targets
@@ -577,36 +673,39 @@ hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_
     return hipGetLastError();
 }
 
+template <int kKind, bool kInit, int DT>
+void launch_is_k(dim3 g, hipStream_t s, const TArgs &a, i64 n, uint32_t t, double *x, double *logw,
+                 const Work &w, u64 *sp)
+{
+    hipLaunchKernelGGL((k_is<kKind, kInit, DT>), g, dim3(256), 0, s, a, n, t, x, logw, w.lp, sp,
+                       w.status, w.n_tiles, w.is_part);
+}
+
 template <bool kInit>
 hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, double *x,
                      double *logw, hipStream_t s)
 {
     const TArgs a = targs(c, w, is_bf16(c));
-    const int g = grid_for(c.n);
+    const dim3 g(grid_for(c.n));
     const i64 n = c.n;
     u64 *sp = w.slots + (par & 1) * kSlots * kSlotStride;
     switch (c.target) {
     case SMC_TARGET_GAUSS:
-        hipLaunchKernelGGL((k_is<SMC_TARGET_GAUSS, kInit>), dim3(g), dim3(256), 0, s, a, n, t, x,
-                           logw, w.lp, sp, w.status, w.n_tiles,
-                           w.is_part);
+        if (c.d == 1) launch_is_k<SMC_TARGET_GAUSS, kInit, 1>(g, s, a, n, t, x, logw, w, sp);
+        else if (c.d == 4) launch_is_k<SMC_TARGET_GAUSS, kInit, 4>(g, s, a, n, t, x, logw, w, sp);
+        else launch_is_k<SMC_TARGET_GAUSS, kInit, 0>(g, s, a, n, t, x, logw, w, sp);
         break;
     case SMC_TARGET_STUDENT:
-        hipLaunchKernelGGL((k_is<SMC_TARGET_STUDENT, kInit>), dim3(g), dim3(256), 0, s, a, n, t,
-                           x, logw, w.lp, sp, w.status, w.n_tiles,
-                           w.is_part);
+        launch_is_k<SMC_TARGET_STUDENT, kInit, 1>(g, s, a, n, t, x, logw, w, sp);
         break;
     case SMC_TARGET_BEARING:
-        hipLaunchKernelGGL((k_is<SMC_TARGET_BEARING, kInit>), dim3(g), dim3(256), 0, s, a, n, t,
-                           x, logw, w.lp, sp, w.status, w.n_tiles, w.is_part);
+        launch_is_k<SMC_TARGET_BEARING, kInit, 4>(g, s, a, n, t, x, logw, w, sp);
         break;
     case SMC_TARGET_LOGREG:
-        hipLaunchKernelGGL((k_is<SMC_TARGET_LOGREG, kInit>), dim3(g), dim3(256), 0, s, a, n, t, x,
-                           logw, w.lp, sp, w.status, w.n_tiles,
-                           w.is_part);
+        launch_is_k<SMC_TARGET_LOGREG, kInit, 0>(g, s, a, n, t, x, logw, w, sp);
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
         if (logreg_lp(c, w, x, n, w.lp_new, true, s) != hipSuccess) return hipErrorLaunchFailure;
-        hipLaunchKernelGGL(k_reweight<kInit>, dim3(g), dim3(256), 0, s, n, c.d, x, w.lp_new, logw,
+        hipLaunchKernelGGL(k_reweight<kInit>, g, dim3(256), 0, s, n, c.d, x, w.lp_new, logw,
                            w.lp, sp, w.status, w.n_tiles, w.is_part);
         break;
     default:
@@ -630,6 +729,9 @@ smc_status step_init(const smc_config &c, const Work &w, int par, double *x, dou
         if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     }
     if (launch_is<true>(c, w, par, 0u, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
+    if (c.target == SMC_TARGET_BEARING)  // equal initial weights: sums from the common reference
+        hipLaunchKernelGGL(k_post_est<4>, dim3(grid_for(c.n)), dim3(256), 0, s, w.ctrl, (i64)c.n,
+                           c.d, x, logw, -std::log((double)c.n), w.is_part);
     hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part, grid_for(c.n),
                        c.d, w.rec_num, (double *)nullptr, (smc_resample_info *)nullptr, 1);
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
@@ -657,8 +759,8 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
     hipLaunchKernelGGL(k_copyback, dim3(grid_for(n * c.d)), dim3(256), 0, s, w.ctrl, (i64)n, c.d,
                        x, w.x_scr, w.lp, w.lp_scr, logw, reset);
     if (pf) {  // Alg 1 takes the mean after resampling
-        hipLaunchKernelGGL(k_post_est, dim3(grid_for(n)), dim3(256), 0, s, w.ctrl, (i64)n, c.d, x,
-                           logw, reset, w.is_part);
+        hipLaunchKernelGGL(k_post_est<4>, dim3(grid_for(n)), dim3(256), 0, s, w.ctrl, (i64)n,
+                           c.d, x, logw, reset, w.is_part);
         hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
                            grid_for(n), c.d, w.rec_num, est, info, 0);
     }
