@@ -13,7 +13,7 @@
 //                       back in place, weights reset to 1/N (Alg 4 Reset).
 //   k_is<BEARING>       one SIR particle-filter update (Alg 1, Sec. 5.2.2):
 //                       constant-velocity transition as proposal, bearing
-//                       likelihood as weight; k_post_est then forms the
+//                       likelihood as weight; k_copyback_est then forms the
 //                       weighted mean of the resampled population.
 //   k_logreg_f64 / k_logreg_bf16 + k_logreg_sum
 //                       Bayesian logistic regression log-likelihood
@@ -28,6 +28,7 @@
 #include "det.hpp"
 #include "kernels.hpp"
 #include "reduce.hpp"
+#include "rng_wave.hpp"
 #include "step.hpp"
 
 namespace smc {
@@ -185,19 +186,23 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
     if (kKind != SMC_TARGET_LOGREG)
         for (i64 i = gtid; i < n_status; i += gsz) status[i] = 0;
     const int d = a.d;
+    const uint32_t tag = kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose;
+    const uint32_t tt_ = kInit ? 0u : t;
     u64 key = 0;
     unsigned bad = 0;
     Online<DA> on;
     on.init();
     double xv[DA];
-    for (i64 i = gtid; i < n; i += gsz) {
+    // wave-uniform trip count: the normal generator is wave-cooperative
+    for (i64 base = gtid - (tid & 63); base < n; base += gsz) {
+        const i64 i = base + (tid & 63);
+        const bool act = i < n;
         double *xi = x + i * d;
         if (kKind == SMC_TARGET_BEARING) {
             double z[4];
-            normal_pair(a.seed, kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose, a.sampler,
-                        kInit ? 0u : t, (uint32_t)i, 0u, z[0], z[1]);
-            normal_pair(a.seed, kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose, a.sampler,
-                        kInit ? 0u : t, (uint32_t)i, 1u, z[2], z[3]);
+            normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, 0u, act, z[0], z[1]);
+            normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, 1u, act, z[2], z[3]);
+            if (!act) continue;
             double lw;
             if (kInit) {
                 for (int k = 0; k < 4; ++k) xi[k] = a.mean[k] + a.init_sd * z[k];
@@ -228,8 +233,9 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
         double acc = 0.0, acc0 = 0.0;
         for (int k = 0; 2 * k < d; ++k) {
             double z[2];
-            normal_pair(a.seed, kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose, a.sampler,
-                        kInit ? 0u : t, (uint32_t)i, (uint32_t)k, z[0], z[1]);
+            normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, (uint32_t)k, act, z[0],
+                             z[1]);
+            if (!act) continue;
             for (int h = 0; h < 2; ++h) {
                 const int kk = 2 * k + h;
                 if (kk >= d) break;
@@ -247,6 +253,7 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
                 }
             }
         }
+        if (!act) continue;
         const double lq0 = kInit ? a.init_log_norm - 0.5 * acc0 : 0.0;
         if (kKind == SMC_TARGET_LOGREG) {
             if (kInit) logw[i] = lq0;  // combined with log pi by k_reweight
@@ -308,9 +315,10 @@ __global__ __launch_bounds__(256) void k_step_stats(Ctrl *ctrl, const double *is
                                                     smc_resample_info *info, int init)
 {
     __shared__ double s_col[2 + 2 * kMaxDim];
+    __shared__ double s_red[4][2 + 2 * kMaxDim];
     __shared__ double s_sc, s_wgt, s_den;
     __shared__ u64 s_mk[4];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int ncol = 2 + 2 * d;
     // reference: the largest block reference (blocks with no weight carry -inf)
     u64 mk = 0;
@@ -324,15 +332,27 @@ __global__ __launch_bounds__(256) void k_step_stats(Ctrl *ctrl, const double *is
     for (int i = 1; i < 4; ++i) mk = s_mk[i] > mk ? s_mk[i] : mk;
     mk = s_mk[0] > mk ? s_mk[0] : mk;
     const double m = okey_inv(mk);
-    for (int c = 1 + tid; c < ncol; c += 256) {
-        double acc = 0.0;
-        for (int b = 0; b < nblk; ++b) {
-            const double mb = is_part[(i64)b * ncol];
-            if (!(mb > -__builtin_huge_val())) continue;
-            acc += det_exp(mb - m) * is_part[(i64)b * ncol + c];
-        }
-        s_col[c] = acc;
+    // thread tid folds blocks tid, tid + 256, ... (nblk <= kMaxBlocks), then a
+    // fixed-order wave and block sum per column
+    constexpr int kPer = kMaxBlocks / 256;
+    double sc[kPer];
+    for (int j = 0; j < kPer; ++j) {
+        const int b = tid + 256 * j;
+        const double mb = b < nblk ? is_part[(i64)b * ncol] : -__builtin_huge_val();
+        sc[j] = mb > -__builtin_huge_val() ? det_exp(mb - m) : 0.0;
     }
+    for (int c = 1; c < ncol; ++c) {
+        double acc = 0.0;
+        for (int j = 0; j < kPer; ++j) {
+            const int b = tid + 256 * j;
+            if (b < nblk && sc[j] != 0.0) acc += sc[j] * is_part[(i64)b * ncol + c];
+        }
+        acc = wave_sum_f64(acc);
+        if (lane == 0) s_red[wid][c] = acc;
+    }
+    __syncthreads();
+    for (int c = 1 + tid; c < ncol; c += 256)
+        s_col[c] = ((s_red[0][c] + s_red[1][c]) + s_red[2][c]) + s_red[3][c];
     __syncthreads();
     const double E0 = s_col[1];
     if (init) {
@@ -389,6 +409,63 @@ __global__ __launch_bounds__(256) void k_copyback(const Ctrl *ctrl, i64 n, int d
         lp[i] = lp_scr[i];
         logw[i] = reset;
     }
+}
+
+// Particle filter: copies the resampled rows back in place (when resampling
+// ran; the weights are then equal, exp(0) = 1 each) and forms the sums of the
+// post-resampling estimate (Alg 1) from the rows it already holds; without
+// resampling the sums use the current weights against the exact max.  Same
+// block-partial layout as is_block_finish.
+template <int DT>
+__global__ __launch_bounds__(256) void k_copyback_est(const Ctrl *ctrl, i64 n,
+                                                      double *__restrict__ x,
+                                                      const double *__restrict__ x_scr,
+                                                      double *__restrict__ logw, double reset,
+                                                      double *is_part)
+{
+    __shared__ double s_acc[4][1 + 2 * DT];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
+    const bool rs = ctrl->resample && !ctrl->err_call;
+    const double m = rs ? reset : ctrl->m;
+    double e0 = 0.0, e1[DT], e2[DT];
+    for (int k = 0; k < DT; ++k) e1[k] = e2[k] = 0.0;
+    for (i64 i = gtid; i < n; i += gsz) {
+        double xk[DT];
+        double e;
+        if (rs) {
+            for (int k = 0; k < DT; ++k) xk[k] = x_scr[i * DT + k];
+            for (int k = 0; k < DT; ++k) x[i * DT + k] = xk[k];
+            logw[i] = reset;
+            e = 1.0;
+        } else {
+            for (int k = 0; k < DT; ++k) xk[k] = x[i * DT + k];
+            e = det_exp(logw[i] - m);
+        }
+        e0 += e;
+        for (int k = 0; k < DT; ++k) {
+            const double ex = e * xk[k];
+            e1[k] += ex;
+            e2[k] += ex * xk[k];
+        }
+    }
+    e0 = wave_sum_f64(e0);
+    for (int k = 0; k < DT; ++k) {
+        e1[k] = wave_sum_f64(e1[k]);
+        e2[k] = wave_sum_f64(e2[k]);
+    }
+    if (lane == 0) {
+        s_acc[wid][0] = e0;
+        for (int k = 0; k < DT; ++k) {
+            s_acc[wid][1 + k] = e1[k];
+            s_acc[wid][1 + DT + k] = e2[k];
+        }
+    }
+    __syncthreads();
+    double *part = is_part + (i64)blockIdx.x * (2 + 2 * DT);
+    for (int c = tid; c < 2 + 2 * DT; c += 256)
+        part[c] = c == 0 ? m : ((s_acc[0][c - 1] + s_acc[1][c - 1]) + s_acc[2][c - 1]) +
+                                   s_acc[3][c - 1];
 }
 
 // Weighted sums of the population after resampling (Alg 1 takes its mean
@@ -752,17 +829,19 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
                            grid_for(n), c.d, w.rec_num, est, info, 0);
         if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     }
-    if (launch_expand(w, n, 0, x, w.x_scr, c.d * 8, w.lp, w.lp_scr, 8, nullptr, nullptr, s,
-                      true) != hipSuccess)
+    // the particle filter carries no cached log-target
+    if (launch_expand(w, n, 0, x, w.x_scr, c.d * 8, pf ? nullptr : w.lp,
+                      pf ? nullptr : w.lp_scr, 8, nullptr, nullptr, s, true) != hipSuccess)
         return SMC_E_DEVICE;
     const double reset = -std::log((double)n);
-    hipLaunchKernelGGL(k_copyback, dim3(grid_for(n * c.d)), dim3(256), 0, s, w.ctrl, (i64)n, c.d,
-                       x, w.x_scr, w.lp, w.lp_scr, logw, reset);
     if (pf) {  // Alg 1 takes the mean after resampling
-        hipLaunchKernelGGL(k_post_est<4>, dim3(grid_for(n)), dim3(256), 0, s, w.ctrl, (i64)n,
-                           c.d, x, logw, reset, w.is_part);
+        hipLaunchKernelGGL(k_copyback_est<4>, dim3(grid_for(n)), dim3(256), 0, s, w.ctrl,
+                           (i64)n, x, w.x_scr, logw, reset, w.is_part);
         hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
                            grid_for(n), c.d, w.rec_num, est, info, 0);
+    } else {
+        hipLaunchKernelGGL(k_copyback, dim3(grid_for(n * c.d)), dim3(256), 0, s, w.ctrl, (i64)n,
+                           c.d, x, w.x_scr, w.lp, w.lp_scr, logw, reset);
     }
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
