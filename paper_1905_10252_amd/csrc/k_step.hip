@@ -332,9 +332,9 @@ __global__ __launch_bounds__(256) void k_step_stats(Ctrl *ctrl, const double *is
     for (int i = 1; i < 4; ++i) mk = s_mk[i] > mk ? s_mk[i] : mk;
     mk = s_mk[0] > mk ? s_mk[0] : mk;
     const double m = okey_inv(mk);
-    // thread tid folds blocks tid, tid + 256, ... (nblk <= kMaxBlocks), then a
+    // thread tid folds blocks tid, tid + 256, ... (nblk <= kIsBlocks), then a
     // fixed-order wave and block sum per column
-    constexpr int kPer = kMaxBlocks / 256;
+    constexpr int kPer = kIsBlocks / 256;
     double sc[kPer];
     for (int j = 0; j < kPer; ++j) {
         const int b = tid + 256 * j;
@@ -763,7 +763,7 @@ hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, do
                      double *logw, hipStream_t s)
 {
     const TArgs a = targs(c, w, is_bf16(c));
-    const dim3 g(grid_for(c.n));
+    const dim3 g(w.is_grid);
     const i64 n = c.n;
     u64 *sp = w.slots + (par & 1) * kSlots * kSlotStride;
     switch (c.target) {
@@ -793,7 +793,43 @@ hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, do
     return kInit ? launch_fold(w, par, s) : hipSuccess;
 }
 
+template <int kKind, int DT>
+int resident_blocks()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_is<kKind, false, DT>, 256, 0) !=
+        hipSuccess)
+        return 0;
+    return nb;
+}
+
 }  // namespace
+
+int sampler_grid(const smc_config &c)
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    int per_cu = 0;
+    switch (c.target) {
+    case SMC_TARGET_GAUSS:
+        per_cu = c.d == 1 ? resident_blocks<SMC_TARGET_GAUSS, 1>()
+                 : c.d == 4 ? resident_blocks<SMC_TARGET_GAUSS, 4>()
+                            : resident_blocks<SMC_TARGET_GAUSS, 0>();
+        break;
+    case SMC_TARGET_STUDENT: per_cu = resident_blocks<SMC_TARGET_STUDENT, 1>(); break;
+    case SMC_TARGET_BEARING: per_cu = resident_blocks<SMC_TARGET_BEARING, 4>(); break;
+    case SMC_TARGET_LOGREG: per_cu = resident_blocks<SMC_TARGET_LOGREG, 0>(); break;
+    default: return 0;
+    }
+    if (per_cu < 1) return 0;
+    int64_t g = (int64_t)per_cu * cus;
+    const int64_t need = (c.n + 255) / 256;
+    g = g < need ? g : need;
+    g = g < kIsBlocks ? g : kIsBlocks;
+    return (int)(g < 1 ? 1 : g);
+}
 
 smc_status step_init(const smc_config &c, const Work &w, int par, double *x, double *logw,
                      hipStream_t s)
@@ -807,9 +843,9 @@ smc_status step_init(const smc_config &c, const Work &w, int par, double *x, dou
     }
     if (launch_is<true>(c, w, par, 0u, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
     if (c.target == SMC_TARGET_BEARING)  // equal initial weights: sums from the common reference
-        hipLaunchKernelGGL(k_post_est<4>, dim3(grid_for(c.n)), dim3(256), 0, s, w.ctrl, (i64)c.n,
+        hipLaunchKernelGGL(k_post_est<4>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)c.n,
                            c.d, x, logw, -std::log((double)c.n), w.is_part);
-    hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part, grid_for(c.n),
+    hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part, w.is_grid,
                        c.d, w.rec_num, (double *)nullptr, (smc_resample_info *)nullptr, 1);
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
@@ -826,7 +862,7 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
     const bool pf = c.target == SMC_TARGET_BEARING;
     if (!pf) {  // Alg 2 estimates come before resampling
         hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
-                           grid_for(n), c.d, w.rec_num, est, info, 0);
+                           w.is_grid, c.d, w.rec_num, est, info, 0);
         if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     }
     // the particle filter carries no cached log-target
@@ -835,10 +871,10 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
         return SMC_E_DEVICE;
     const double reset = -std::log((double)n);
     if (pf) {  // Alg 1 takes the mean after resampling
-        hipLaunchKernelGGL(k_copyback_est<4>, dim3(grid_for(n)), dim3(256), 0, s, w.ctrl,
+        hipLaunchKernelGGL(k_copyback_est<4>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl,
                            (i64)n, x, w.x_scr, logw, reset, w.is_part);
         hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
-                           grid_for(n), c.d, w.rec_num, est, info, 0);
+                           w.is_grid, c.d, w.rec_num, est, info, 0);
     } else {
         hipLaunchKernelGGL(k_copyback, dim3(grid_for(n * c.d)), dim3(256), 0, s, w.ctrl, (i64)n,
                            c.d, x, w.x_scr, w.lp, w.lp_scr, logw, reset);

@@ -13,6 +13,7 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kTile = kScanThreads * kScanItems;  // 4096 elements per scan tile
 constexpr int kMaxBlocks = 1024;                  // grid of the max / reweight passes
+constexpr int kIsBlocks = 2048;                   // max grid of the sampler kernels
 constexpr int kExpandThreads = 256;
 constexpr int kSegLen = 2048;                     // merge-path steps per expand workgroup
 constexpr int kLogregSplit = 8;                   // row blocks of the likelihood contraction
@@ -35,7 +36,7 @@ struct Work {
     double *lp_new;     // [n] proposal log-target (costly targets)
     double *x_scr;      // [n * d] redistribute destination
     double *lp_scr;     // [n]
-    double *is_part;    // [kMaxBlocks * (2 + 2d)] per-block estimate sums
+    double *is_part;    // [kIsBlocks * (2 + 2d)] per-block estimate sums
     double *rec_num;    // [2d] recycled estimate sums
     // logistic regression (NULL otherwise)
     unsigned short *xs;   // [mpad][dp] bf16 rows of X times (1 - 2 y)
@@ -44,6 +45,7 @@ struct Work {
     int64_t mpad, npad;
     int dp;
     int n_tiles;
+    int is_grid;        // blocks of the sampler kernels (rows of is_part)
 };
 
 inline int n_tiles_of(int64_t n) { return (int)((n + kTile - 1) / kTile); }

@@ -92,7 +92,7 @@ Layout layout_of(const smc_config *c)
         L.lp_new = take(8 * n);
         L.x_scr = take(8 * n * d);
         L.lp_scr = take(8 * n);
-        L.is_part = take(8 * (size_t)kMaxBlocks * (2 + 2 * d));
+        L.is_part = take(8 * (size_t)kIsBlocks * (2 + 2 * d));
         L.rec_num = take(8 * 2 * d);
         if (c->target == SMC_TARGET_LOGREG) {
             L.lpart = take(8 * (size_t)kLogregSplit * n);
@@ -182,7 +182,8 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
     w.mpad = L.mpad;
     w.npad = L.npad;
     w.dp = L.dp;
-    if (launch_init_ctrl(w, S(stream)) != hipSuccess) {
+    w.is_grid = samp ? sampler_grid(ctx->cfg) : 0;
+    if ((samp && w.is_grid < 1) || launch_init_ctrl(w, S(stream)) != hipSuccess) {
         delete ctx;
         return SMC_E_DEVICE;
     }

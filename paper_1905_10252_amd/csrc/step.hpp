@@ -11,6 +11,10 @@ namespace smc {
 
 constexpr int kMaxDim = 64;
 
+// Grid of the sampler kernels: one full residency of the update kernel on
+// this device, at most kIsBlocks and at most one block per 256 particles;
+// 0 if the device cannot be queried.
+int sampler_grid(const smc_config &cfg);
 // par: parity of the max slots this call uses (alternates between calls).
 smc_status step_init(const smc_config &cfg, const Work &w, int par, double *x, double *logw,
                      hipStream_t s);
