@@ -18,7 +18,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 MODE_AUTO, MODE_FORCE, MODE_NEVER = 0, 1, 2
 E_OK, E_ARG, E_NONFINITE, E_DEGENERATE = 0, 1, 2, 3
-T_GAUSS, T_STUDENT, T_LOGREG = 1, 2, 3
+T_GAUSS, T_STUDENT, T_LOGREG, T_GAUSS_CHOL = 1, 2, 3, 5
 TAG_INIT, TAG_PROPOSE, TAG_RESAMPLE = 1, 2, 3
 DMAX = 64
 
@@ -54,7 +54,7 @@ class SmcCfg(C.Structure):
                 ("mean", C.POINTER(C.c_double)), ("prec", C.POINTER(C.c_double)),
                 ("nu", C.c_double), ("mu", C.c_double),
                 ("m_rows", C.c_int64), ("X", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)),
-                ("prior_prec", C.c_double)]
+                ("prior_prec", C.c_double), ("chol", C.POINTER(C.c_double))]
 
 
 class Recycle(C.Structure):
@@ -215,7 +215,7 @@ class Sampler:
     def __init__(self, n, d, target, *, seed=0, sampler_id=0, rw_sd=0.5, init_mean=0.0,
                  init_sd=3.0, mode=MODE_AUTO, ess_num=1, ess_den=2, mean=None, var=None,
                  nu=None, mu=None, X=None, y=None, prior_var=None, log_norm=None,
-                 init_log_norm=None):
+                 init_log_norm=None, chol=None):
         import math
         self.cfg = SmcCfg()
         c = self.cfg
@@ -231,6 +231,12 @@ class Sampler:
             self._keep += [mean, prec]
             c.mean, c.prec = _p(mean, C.c_double), _p(prec, C.c_double)
             c.log_norm = gauss_log_norm(var)
+        elif target == T_GAUSS_CHOL:
+            mean = np.ascontiguousarray(mean, dtype=np.float64)
+            U = np.ascontiguousarray(chol, dtype=np.float64)
+            self._keep += [mean, U]
+            c.mean, c.chol = _p(mean, C.c_double), _p(U, C.c_double)
+            c.log_norm = gauss_chol_log_norm(U)
         elif target == T_STUDENT:
             c.nu, c.mu = nu, mu
             c.log_norm = student_log_norm(nu)
@@ -278,6 +284,15 @@ class Sampler:
         lp = np.zeros(n, dtype=np.float64)
         lib().orc_log_target_batch(C.byref(self.cfg), _p(xa, C.c_double), n, _p(lp, C.c_double))
         return lp
+
+
+def gauss_chol_log_norm(U) -> float:
+    """Additive constant of a Gaussian log-density with precision U^T U:
+    -d/2 log(2 pi) + log det U (U triangular, so its diagonal)."""
+    import math
+    U = np.asarray(U, dtype=np.float64)
+    d = U.shape[0]
+    return -0.5 * d * math.log(2.0 * math.pi) + float(np.sum(np.log(np.diag(U))))
 
 
 def gauss_log_norm(var) -> float:

@@ -60,7 +60,7 @@ typedef unsigned __int128 u128;
 enum { ORC_OK = 0, ORC_E_ARG = 1, ORC_E_NONFINITE = 2, ORC_E_DEGENERATE = 3 };
 enum { ORC_MODE_AUTO = 0, ORC_MODE_FORCE = 1, ORC_MODE_NEVER = 2 };
 enum { ORC_TAG_INIT = 1, ORC_TAG_PROPOSE = 2, ORC_TAG_RESAMPLE = 3 };
-enum { ORC_T_GAUSS = 1, ORC_T_STUDENT = 2, ORC_T_LOGREG = 3 };
+enum { ORC_T_GAUSS = 1, ORC_T_STUDENT = 2, ORC_T_LOGREG = 3, ORC_T_GAUSS_CHOL = 5 };
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10: 10 rounds of the Philox S-box on a 4x32-bit counter with a  */
@@ -375,6 +375,8 @@ typedef struct {
     int64_t m_rows;                           /* logistic regression: X [M][d], y [M] */
     const double *X, *y;
     double prior_prec;
+    const double *chol;                       /* Gaussian with full precision P = U^T U: */
+                                              /* U upper triangular [d][d], row-major    */
 } orc_smc_cfg;
 
 #define ORC_DMAX 64
@@ -408,6 +410,17 @@ double orc_log_target(const orc_smc_cfg *c, const double *x)
         for (int32_t k = 0; k < c->d; ++k) {
             double t = x[k] - c->mean[k];
             acc = acc + (t * t) * c->prec[k];
+        }
+        return c->log_norm - 0.5 * acc;
+    }
+    if (c->target == ORC_T_GAUSS_CHOL) {
+        /* (x - mean)^T P (x - mean) = |U (x - mean)|^2, row i of U from its diagonal on */
+        double acc = 0.0;
+        for (int32_t i = 0; i < c->d; ++i) {
+            double r = 0.0;
+            for (int32_t k = i; k < c->d; ++k)
+                r = r + c->chol[(int64_t)i * c->d + k] * (x[k] - c->mean[k]);
+            acc = acc + r * r;
         }
         return c->log_norm - 0.5 * acc;
     }

@@ -107,3 +107,39 @@ def bearing_track(T: int, seed: int, x0=BEARING["x0"], delta=BEARING["delta"],
         xs.append(A @ xs[-1] + L @ rng.standard_normal(4))
         ys.append(np.arctan(xs[-1][2] / xs[-1][0]) + np.sqrt(obs_var) * rng.standard_normal())
     return np.array(xs), np.array(ys)
+
+
+# Batched samplers: many independent Gaussian targets of uneven size and
+# dimension.  N log-uniform in [2^8, 2^16], d uniform in 1..64, mean ~ N(0, I),
+# covariance W / (d + 2) with W ~ Wishart(I, d + 2) (so its mean is I),
+# q0 = N(0, 9 I), random-walk sd 0.5 / sqrt(d).
+BATCH = dict(count=256, n_lo=1 << 8, n_hi=1 << 16, d_lo=1, d_hi=64, init_sd=3.0, seed=300,
+             iters=20)
+
+
+def wishart_target(d: int, rng: np.random.Generator):
+    """Mean, upper-triangular U with precision U^T U, and the covariance."""
+    g = rng.standard_normal((d + 2, d))
+    cov = (g.T @ g) / (d + 2)
+    prec = np.linalg.inv(cov)
+    prec = 0.5 * (prec + prec.T)
+    U = np.ascontiguousarray(np.linalg.cholesky(prec).T)
+    mean = rng.standard_normal(d)
+    return mean, U, cov
+
+
+def batch_specs(count: int = BATCH["count"], seed: int = BATCH["seed"],
+                n_lo: int = BATCH["n_lo"], n_hi: int = BATCH["n_hi"],
+                d_lo: int = BATCH["d_lo"], d_hi: int = BATCH["d_hi"]) -> list:
+    """Per-sampler sizes, targets, proposal scale and random-number keys."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        d = int(rng.integers(d_lo, d_hi + 1))
+        mean, U, cov = wishart_target(d, rng)
+        out.append(dict(n=n, d=d, mean=mean, chol=U, cov=cov, rw_sd=0.5 / math.sqrt(d),
+                        seed=(seed << 32) + s, sampler_id=s, init_mean=0.0,
+                        init_sd=BATCH["init_sd"]))
+    return out
+

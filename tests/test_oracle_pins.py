@@ -507,3 +507,49 @@ def test_pf_evidence_increment_is_ratio_of_weight_sums():
     before = special.logsumexp(f.logw)
     out = f.step()
     assert abs(out["log_c"] - (special.logsumexp(f.logw) - before)) < 1e-10
+
+
+# --------------------------------- Gaussian target with a full precision U^T U
+@pytest.mark.parametrize("d", [1, 2, 7, 33, 64])
+def test_gauss_chol_log_target_vs_scipy(d):
+    """log pi for the batched workload's Wishart targets equals scipy's
+    multivariate normal log-density (a transposed U, a dropped diagonal or a
+    wrong mean sign all fail this)."""
+    rng = np.random.default_rng(40 + d)
+    mean, U, cov = I.wishart_target(d, rng)
+    s = O.Sampler(1, d, O.T_GAUSS_CHOL, mean=mean, chol=U)
+    x = mean + 0.3 * rng.standard_normal((60, d))
+    got = s.log_target(x)
+    ref = stats.multivariate_normal(mean, cov).logpdf(x)
+    assert np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref))) < 1e-8
+
+
+def test_gauss_chol_diagonal_reduces_to_diagonal_gauss():
+    rng = np.random.default_rng(5)
+    var = rng.uniform(0.3, 3.0, 6)
+    mean = rng.standard_normal(6)
+    a = O.Sampler(1, 6, O.T_GAUSS_CHOL, mean=mean, chol=np.diag(1.0 / np.sqrt(var)))
+    b = O.Sampler(1, 6, O.T_GAUSS, mean=mean, var=var)
+    x = rng.standard_normal((20, 6))
+    assert np.allclose(a.log_target(x), b.log_target(x), rtol=1e-13, atol=1e-13)
+
+
+def test_gauss_chol_importance_sampling_moments():
+    """Correlated 3-d target, one iteration without resampling (the L = q
+    weights keep targeting pi): the weighted mean and raw second moment match
+    mean and diag(cov) + mean^2."""
+    mean = np.array([1.0, -1.0, 0.5])
+    cov = np.array([[1.0, 0.5, 0.2], [0.5, 2.0, 0.3], [0.2, 0.3, 0.5]])
+    U = np.linalg.cholesky(np.linalg.inv(cov)).T
+    ms, m2s = [], []
+    for seed in range(1, 41):
+        s = O.Sampler(8192, 3, O.T_GAUSS_CHOL, seed=seed, rw_sd=0.3, init_mean=0.0,
+                      init_sd=3.0, mean=mean, chol=U, mode=O.MODE_NEVER)
+        s.init()
+        out = s.step()
+        ms.append(out["mean"])
+        m2s.append(out["m2"])
+    ms, m2s = np.array(ms), np.array(m2s)
+    k = math.sqrt(ms.shape[0])
+    assert np.all(np.abs(ms.mean(0) - mean) < 5 * ms.std(0) / k + 1e-3)
+    assert np.all(np.abs(m2s.mean(0) - (np.diag(cov) + mean ** 2)) < 5 * m2s.std(0) / k + 2e-3)
