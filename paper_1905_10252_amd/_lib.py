@@ -23,7 +23,11 @@ MODE_AUTO, MODE_FORCE, MODE_NEVER = 0, 1, 2
 PREC_F64, PREC_BF16 = 0, 1
 
 EXPORTS = ("smc_workspace_bytes", "smc_init", "smc_step", "smc_resample", "smc_redistribute",
-           "smc_log_target", "smc_sync_error", "smc_destroy", "smc_status_string")
+           "smc_log_target", "smc_sync_error", "smc_destroy", "smc_status_string",
+           "smc_batch_sampler_bytes", "smc_batch_workspace_bytes", "smc_batch_create",
+           "smc_batch_attach", "smc_batch_detach", "smc_batch_step", "smc_batch_set_graph",
+           "smc_batch_counts", "smc_batch_sync_error", "smc_batch_destroy")
+BATCH_DMAX, BATCH_EST_STRIDE = 64, 256
 
 
 class SmcConfig(C.Structure):
@@ -50,6 +54,17 @@ class SmcInfo(C.Structure):
 
 
 INFO_BYTES = C.sizeof(SmcInfo)
+
+
+class SmcBatchSampler(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("d", C.c_int32), ("mode", C.c_int32), ("ess_num", C.c_int32),
+        ("ess_den", C.c_int32), ("sampler_id", C.c_uint32), ("pad0", C.c_int32),
+        ("seed", C.c_uint64), ("rw_sd", C.c_double), ("init_mean", C.c_double),
+        ("init_sd", C.c_double), ("init_log_norm", C.c_double), ("log_norm", C.c_double),
+        ("mean", C.c_void_p), ("chol", C.c_void_p), ("x", C.c_void_p), ("logw", C.c_void_p),
+        ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
+    ]
 
 
 class SmcError(RuntimeError):
@@ -83,6 +98,22 @@ def load():
     L.smc_status_string.restype = C.c_char_p
     for f in ("smc_init", "smc_step", "smc_resample", "smc_redistribute", "smc_log_target",
               "smc_sync_error", "smc_destroy"):
+        getattr(L, f).restype = C.c_int
+    L.smc_batch_sampler_bytes.argtypes = [P(SmcBatchSampler)]
+    L.smc_batch_sampler_bytes.restype = C.c_size_t
+    L.smc_batch_workspace_bytes.argtypes = [C.c_int32]
+    L.smc_batch_workspace_bytes.restype = C.c_size_t
+    L.smc_batch_create.argtypes = [P(vp), C.c_int32, vp, C.c_size_t, vp]
+    L.smc_batch_attach.argtypes = [vp, C.c_int32, P(SmcBatchSampler), vp]
+    L.smc_batch_detach.argtypes = [vp, C.c_int32, vp]
+    L.smc_batch_step.argtypes = [vp, vp, vp, vp]
+    L.smc_batch_set_graph.argtypes = [vp, C.c_int32]
+    L.smc_batch_counts.argtypes = [vp, P(C.c_int32), P(C.c_int64)]
+    L.smc_batch_sync_error.argtypes = [vp, C.c_int32, vp]
+    L.smc_batch_destroy.argtypes = [vp]
+    for f in ("smc_batch_create", "smc_batch_attach", "smc_batch_detach", "smc_batch_step",
+              "smc_batch_set_graph", "smc_batch_counts", "smc_batch_sync_error",
+              "smc_batch_destroy"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L

@@ -1,0 +1,1097 @@
+// Batched SMC samplers: every attached sampler runs Alg 2 (random-walk
+// proposal, L = q weights by eq. smcs_drawing_weights, estimates before
+// resampling by eq. estimation_at_t, the exact-integer ESS decision and
+// systematic resampling of Alg 4 in S-R order, reset to 1/N, c_t and
+// recycling by eq. normconst and eq. recycling) on a Gaussian target with
+// precision U^T U.  One step is one sequence of launches for all samplers:
+//
+//   k_bis<DB>   per tile of 4096 particles of samplers whose dimension falls
+//               in the bucket (DB - 8, DB]: proposal, |U (x - mean)|^2 with U
+//               staged in LDS and the row in registers, weight update, tile
+//               max key.  One launch per bucket.
+//   k_bscan     per tile of every sampler: the sampler's max from its tile
+//               keys, 64-bit fixed-point weights, FP64 sums, the exact sum of
+//               squares, and the inclusive prefix by a decoupled lookback
+//               that stays inside the sampler's own tiles (segmented scan);
+//               also the tile's estimate sums sum e x_k, sum e x_k^2.
+//   k_bdecide   one workgroup per sampler: tile partials in a fixed order,
+//               integer decision, offset, log Z, ESS, estimates, c_t,
+//               recycling, the sampler's info record.
+//   k_bexpand   per 256 outputs of resampling samplers: ancestor by binary
+//               search on the prefix, rows copied by whole wavefronts.
+//   k_bcopyback per tile of resampling samplers: rows and cached log-target
+//               back in place, weights reset.
+//
+// Tiles never straddle samplers, a tile waits only on earlier tiles of its own
+// sampler, and every reduction runs in a fixed order over that sampler's
+// tiles, so a sampler's results do not depend on the rest of the batch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "../../include/smc.h"
+#include "../../include/smc_batch.h"
+#include "common.hpp"
+#include "det.hpp"
+#include "kernels.hpp"
+#include "rng_wave.hpp"
+
+namespace smc {
+namespace {
+
+constexpr int kBT = 256;               // threads per workgroup
+constexpr int kBItems = 16;            // particles per thread and tile
+constexpr int kBTile = kBT * kBItems;  // particles per tile
+constexpr int kBChunk = 256;           // expand outputs per workgroup
+constexpr int kBSpin = 1 << 22;        // lookback poll bound
+constexpr int kBuckets = 8;            // dimension buckets (8b, 8b + 8]
+constexpr int kBMaxCap = 4096;
+constexpr int64_t kBMaxN = 1ll << 28;
+
+__host__ __device__ constexpr int bpad(int i) { return i + (i >> 4); }
+
+// Per-sampler control block (in the sampler's workspace).
+struct BCtrl {
+    u64 S, U, Q2lo, Q2hi, mkey;
+    double m, logZ, ess, Z, Z2, log_c;
+    double logZ_prev, lc_max, rec_den;
+    unsigned t;          // iteration of the next step (1, 2, ...)
+    unsigned resample;   // decision of the last step
+    unsigned err_call, err_latch, spin_fail, bad, rec_steps, pad;
+};
+
+// Per-tile output of the update kernel.
+struct BTileIS {
+    u64 key;
+    unsigned bad, pad;
+    double m, E;  // initialisation: tile reference and sum exp(l - m)
+};
+
+// Device descriptor of one slot (n == 0: free).
+struct BSlot {
+    i64 n;
+    int d, mode, ess_num, ess_den, K, ntile, nchunk, bucket;
+    uint32_t sampler, pad;
+    u64 seed;
+    double rw_sd, init_mean, init_sd, init_prec, init_log_norm, log_norm, reset;
+    const double *mean, *chol;
+    double *x, *logw;
+    BCtrl *ctrl;
+    double *lp, *x_scr, *lp_scr, *epart, *rec_num;
+    u64 *pref, *status;
+    TilePart *tpart;
+    BTileIS *tis;
+};
+
+struct BTabs {
+    int *n_act;       // [1 + kBuckets]: attached samplers, then per bucket
+    int *act;         // [cap] attached slots, ascending
+    int *tile_pref;   // [cap + 1] tile prefix over act
+    int *chunk_pref;  // [cap + 1] expand-chunk prefix over act
+    int *bact;        // [kBuckets][cap]
+    int *btile_pref;  // [kBuckets][cap + 1]
+};
+
+// Position of block b in a prefix table: slot and index within the slot.
+__device__ inline bool locate(const int *pref, const int *act, int nact, int b, int &slot,
+                              int &local)
+{
+    if (nact <= 0 || b >= pref[nact]) return false;
+    int lo = 0, hi = nact;  // pref[lo] <= b < pref[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pref[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    slot = act[lo];
+    local = b - pref[lo];
+    return true;
+}
+
+// ------------------------------------------------------------------ tables
+__global__ void k_bslot_set(BSlot v, BSlot *dst) { *dst = v; }
+
+__global__ void k_bslots_clear(BSlot *slots, int cap)
+{
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x)
+        slots[s].n = 0;
+}
+
+// Tables of the attached slots in slot order; thread t owns a contiguous
+// range of slots, counts are combined by a block scan.
+__global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, BTabs tb)
+{
+    constexpr int NV = 3 + 2 * kBuckets;  // act, tiles, chunks, bucket counts, bucket tiles
+    __shared__ int s_v[NV][256];
+    const int tid = threadIdx.x;
+    const int per = (cap + 255) / 256;
+    const int s0 = tid * per, s1 = (s0 + per < cap) ? s0 + per : cap;
+    int v[NV];
+    for (int q = 0; q < NV; ++q) v[q] = 0;
+    for (int s = s0; s < s1; ++s) {
+        if (slots[s].n <= 0) continue;
+        const int b = slots[s].bucket;
+        v[0] += 1;
+        v[1] += slots[s].ntile;
+        v[2] += slots[s].nchunk;
+        v[3 + b] += 1;
+        v[3 + kBuckets + b] += slots[s].ntile;
+    }
+    for (int q = 0; q < NV; ++q) s_v[q][tid] = v[q];
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {  // inclusive Hillis-Steele scan
+        int add[NV];
+        for (int q = 0; q < NV; ++q) add[q] = tid >= o ? s_v[q][tid - o] : 0;
+        __syncthreads();
+        for (int q = 0; q < NV; ++q) s_v[q][tid] += add[q];
+        __syncthreads();
+    }
+    int off[NV];
+    for (int q = 0; q < NV; ++q) off[q] = s_v[q][tid] - v[q];
+    for (int s = s0; s < s1; ++s) {
+        if (slots[s].n <= 0) continue;
+        const int b = slots[s].bucket;
+        tb.act[off[0]] = s;
+        tb.tile_pref[off[0]] = off[1];
+        tb.chunk_pref[off[0]] = off[2];
+        tb.bact[b * cap + off[3 + b]] = s;
+        tb.btile_pref[b * (cap + 1) + off[3 + b]] = off[3 + kBuckets + b];
+        off[0] += 1;
+        off[1] += slots[s].ntile;
+        off[2] += slots[s].nchunk;
+        off[3 + b] += 1;
+        off[3 + kBuckets + b] += slots[s].ntile;
+    }
+    if (tid == 255) {
+        const int na = s_v[0][255];
+        tb.n_act[0] = na;
+        tb.tile_pref[na] = s_v[1][255];
+        tb.chunk_pref[na] = s_v[2][255];
+        for (int b = 0; b < kBuckets; ++b) {
+            const int nb = s_v[3 + b][255];
+            tb.n_act[1 + b] = nb;
+            tb.btile_pref[b * (cap + 1) + nb] = s_v[3 + kBuckets + b][255];
+        }
+    }
+}
+
+// ---------------------------------------------------- proposal + weights
+// single >= 0: every block is a tile of that slot (initialisation);
+// otherwise blocks map to the tiles of the bucket's samplers.
+template <int DB, bool kInit>
+__global__ __launch_bounds__(256) void k_bis(const BSlot *slots, const int *n_act,
+                                             const int *bact, const int *btile_pref, int bucket,
+                                             int cap, int single)
+{
+    __shared__ double sU[DB * DB];
+    __shared__ double sM[DB];
+    __shared__ u64 s_key[4];
+    __shared__ unsigned s_bad[4];
+    __shared__ double s_m[4], s_e[4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int slot, tile;
+    if (single >= 0) {
+        slot = single;
+        tile = blockIdx.x;
+    } else if (!locate(btile_pref + bucket * (cap + 1), bact + bucket * cap, n_act[1 + bucket],
+                       blockIdx.x, slot, tile)) {
+        return;
+    }
+    const BSlot &S = slots[slot];
+    const i64 n = S.n;
+    const int d = S.d;
+    // U zero-padded to DB x DB (lower triangle and beyond d are zero), so the
+    // quadratic form needs no per-element guard: the extra terms add +0.
+    for (int e = tid; e < DB * DB; e += 256) {
+        const int r = e / DB, k = e - r * DB;
+        sU[e] = (r < d && k < d && k >= r) ? S.chol[r * d + k] : 0.0;
+    }
+    for (int e = tid; e < DB; e += 256) sM[e] = e < d ? S.mean[e] : 0.0;
+    if (tid == 0) S.status[tile] = 0;  // lookback word of this step's scan
+    __syncthreads();
+    const uint32_t t = kInit ? 0u : S.ctrl->t;
+    const uint32_t tag = kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose;
+    u64 key = 0;
+    unsigned bad = 0;
+    double om = -__builtin_huge_val(), oe = 0.0;  // initialisation: running reference and sum
+    const i64 base = (i64)tile * kBTile;
+    for (int it = 0; it < kBItems; ++it) {
+        const i64 i = base + it * 256 + tid;
+        const bool act = i < n;
+        double *xi = S.x + i * d;
+        double acc0 = 0.0;
+        for (int k2 = 0; 2 * k2 < d; ++k2) {
+            double z[2];
+            normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)i, (uint32_t)k2, act, z[0],
+                             z[1]);
+            if (!act) continue;
+            for (int h = 0; h < 2; ++h) {
+                const int kk = 2 * k2 + h;
+                if (kk >= d) break;
+                const double xk = kInit ? S.init_mean + S.init_sd * z[h] : xi[kk] + S.rw_sd * z[h];
+                xi[kk] = xk;
+                if (kInit) {
+                    const double t0 = xk - S.init_mean;
+                    acc0 = acc0 + (t0 * t0) * S.init_prec;
+                }
+            }
+        }
+        if (!act) continue;
+        // An opaque zero offset keeps the LDS reads of U inside this loop:
+        // hoisted, they would hold DB^2 / 2 values in registers.
+        int zo = 0;
+        asm volatile("" : "+v"(zo));
+        const double *u = sU + zo;
+        const double *mu = sM + zo;
+        double tv[DB];
+#pragma unroll
+        for (int k = 0; k < DB; ++k) tv[k] = k < d ? xi[k] - mu[k] : 0.0;
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < DB; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = r; k < DB; ++k) s = s + u[r * DB + k] * tv[k];
+            acc = acc + s * s;
+        }
+        const double lpn = S.log_norm - 0.5 * acc;
+        const double lw = kInit ? lpn - (S.init_log_norm - 0.5 * acc0) : S.logw[i] + (lpn - S.lp[i]);
+        S.lp[i] = lpn;
+        S.logw[i] = lw;
+        bad |= (lw != lw) | (lw == __builtin_huge_val());
+        const u64 kk = okey(lw);
+        key = kk > key ? kk : key;
+        if (kInit && lw > -__builtin_huge_val()) {
+            if (lw > om) {
+                if (om > -__builtin_huge_val()) oe *= det_exp(om - lw);
+                om = lw;
+            }
+            oe += det_exp(lw - om);
+        }
+    }
+    key = wave_max_u64(key);
+    bad = wave_or(bad);
+    double mw = 0.0, ew = 0.0;
+    if (kInit) {
+        mw = wave_max_f64(om);
+        ew = wave_sum_f64(om > -__builtin_huge_val() ? oe * det_exp(om - mw) : 0.0);
+    }
+    if (lane == 0) {
+        s_key[wid] = key;
+        s_bad[wid] = bad;
+        s_m[wid] = mw;
+        s_e[wid] = ew;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        BTileIS o;
+        o.key = s_key[0];
+        o.bad = s_bad[0];
+        for (int w = 1; w < 4; ++w) {
+            o.key = s_key[w] > o.key ? s_key[w] : o.key;
+            o.bad |= s_bad[w];
+        }
+        o.pad = 0;
+        o.m = -__builtin_huge_val();
+        o.E = 0.0;
+        if (kInit) {
+            double mb = s_m[0];
+            for (int w = 1; w < 4; ++w) mb = fmax(mb, s_m[w]);
+            double E = 0.0;
+            for (int w = 0; w < 4; ++w)
+                E += s_m[w] > -__builtin_huge_val() ? s_e[w] * det_exp(s_m[w] - mb) : 0.0;
+            o.m = mb;
+            o.E = E;
+        }
+        S.tis[tile] = o;
+    }
+}
+
+// Initialisation statistics: log sum w_0 from the tile partials (fixed
+// order), error of the initial weights, cleared recycling sums.
+__global__ __launch_bounds__(64) void k_binit(const BSlot *slots, int slot)
+{
+    const BSlot &S = slots[slot];
+    BCtrl *c = S.ctrl;
+    const int lane = threadIdx.x;
+    for (int k = lane; k < 2 * S.d; k += 64) S.rec_num[k] = 0.0;
+    if (lane != 0) return;
+    u64 key = 0;
+    unsigned bad = 0;
+    double m = -__builtin_huge_val();
+    for (int k = 0; k < S.ntile; ++k) {
+        key = S.tis[k].key > key ? S.tis[k].key : key;
+        bad |= S.tis[k].bad;
+        m = fmax(m, S.tis[k].m);
+    }
+    double E = 0.0;
+    for (int k = 0; k < S.ntile; ++k)
+        if (S.tis[k].m > -__builtin_huge_val()) E += S.tis[k].E * det_exp(S.tis[k].m - m);
+    unsigned err = 0;
+    if (bad) err = kErrNonfinite;
+    else if (key <= okey(-__builtin_huge_val())) err = kErrDegenerate;
+    c->logZ_prev = m + log(E);
+    c->lc_max = -__builtin_huge_val();
+    c->rec_den = 0.0;
+    c->rec_steps = 0;
+    c->t = 1;
+    c->resample = 0;
+    c->err_call = err;
+    c->err_latch = err;
+    c->spin_fail = 0;
+    c->bad = 0;
+}
+
+// --------------------------------------------------------- segmented scan
+__global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_act,
+                                               const int *act, const int *tile_pref)
+{
+    __shared__ double se[bpad(kBTile)];
+    __shared__ u64 s_k[4], s_wsum[4], s_lo[4], s_hi[4];
+    __shared__ unsigned s_b[4];
+    __shared__ double s_z[4], s_z2[4];
+    __shared__ u64 s_prefix;
+    __shared__ double s_col[4][2 * SMC_BATCH_DMAX];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int slot, tile;
+    if (!locate(tile_pref, act, n_act[0], blockIdx.x, slot, tile)) return;
+    const BSlot &S = slots[slot];
+    const i64 n = S.n;
+    const int d = S.d, K = S.K, ntile = S.ntile;
+
+    // the sampler's max and non-finite flag from its tile keys
+    u64 key = 0;
+    unsigned bad = 0;
+    for (int k = tid; k < ntile; k += 256) {
+        const u64 kk = S.tis[k].key;
+        key = kk > key ? kk : key;
+        bad |= S.tis[k].bad;
+    }
+    key = wave_max_u64(key);
+    bad = wave_or(bad);
+    if (lane == 0) {
+        s_k[wid] = key;
+        s_b[wid] = bad;
+    }
+    __syncthreads();
+    key = s_k[0];
+    bad = s_b[0];
+    for (int w = 1; w < 4; ++w) {
+        key = s_k[w] > key ? s_k[w] : key;
+        bad |= s_b[w];
+    }
+    const double m = okey_inv(key);
+    if (tile == 0 && tid == 0) {
+        S.ctrl->mkey = key;
+        S.ctrl->bad = bad;
+    }
+
+    // fixed-point weights of 16 consecutive particles, FP64 and exact sums
+    const i64 base = (i64)tile * kBTile;
+    const u64 top = 1ull << K;
+    double z = 0.0, z2 = 0.0;
+    U128 q2{0, 0};
+    u64 loc[kBItems];
+    u64 run = 0;
+#pragma unroll
+    for (int j = 0; j < kBItems; ++j) {
+        const i64 i = base + tid * kBItems + j;
+        const double v = i < n ? S.logw[i] : -__builtin_huge_val();
+        double e = det_exp(v - m);
+        u64 q = 0;
+        if (e >= 0.0) {
+            z += e;
+            z2 += e * e;
+            q = (u64)floor(ldexp(e, K));
+            q = q > top ? top : q;
+            q2 = add128(q2, mul64(q, q));
+        } else {
+            e = 0.0;
+        }
+        se[bpad(tid * kBItems + j)] = e;
+        run += q;
+        loc[j] = run;
+    }
+    const u64 incl = wave_incl_scan_u64(run);
+    if (lane == 63) s_wsum[wid] = incl;
+    __syncthreads();
+    u64 wpre = 0, agg = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        wpre += (w < wid) ? s_wsum[w] : 0;
+        agg += s_wsum[w];
+    }
+    const u64 texcl = wpre + incl - run;
+
+    // decoupled lookback over this sampler's earlier tiles
+    if (wid == 0) {
+        u64 excl = 0;
+        if (tile == 0) {
+            if (lane == 0) st_relaxed(&S.status[0], kFlagInc | agg);
+        } else {
+            if (lane == 0) st_relaxed(&S.status[tile], kFlagAgg | agg);
+            i64 top_idx = (i64)tile - 1;
+            int spins = 0;
+            while (true) {
+                const i64 idx = top_idx - lane;
+                const u64 sv = idx >= 0 ? ld_relaxed(&S.status[idx]) : kFlagInc;
+                const u64 flag = sv >> 62;
+                const u64 inc_mask = __ballot(flag == 2);
+                const u64 zero_mask = __ballot(flag == 0);
+                const int first_inc = inc_mask ? __ffsll((long long)inc_mask) - 1 : 64;
+                const u64 need = first_inc >= 64 ? ~0ull : ((1ull << first_inc) - 1);
+                if (zero_mask & need) {
+                    if (++spins > kBSpin) {
+                        if (lane == 0) S.ctrl->spin_fail = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                u64 acc = lane <= first_inc ? (sv & kValMask) : 0;
+                for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+                excl += acc;
+                if (first_inc < 64) break;
+                top_idx -= 64;
+            }
+            if (lane == 0) st_relaxed(&S.status[tile], kFlagInc | (excl + agg));
+        }
+        if (lane == 0) s_prefix = excl;
+    }
+    z = wave_sum_f64(z);
+    z2 = wave_sum_f64(z2);
+    q2 = wave_sum_u128(q2);
+    if (lane == 0) {
+        s_z[wid] = z;
+        s_z2[wid] = z2;
+        s_lo[wid] = q2.lo;
+        s_hi[wid] = q2.hi;
+    }
+    __syncthreads();
+    const u64 pre = s_prefix + texcl;
+#pragma unroll
+    for (int j = 0; j < kBItems; ++j) {
+        const i64 i = base + tid * kBItems + j;
+        if (i < n) S.pref[i] = pre + loc[j];
+    }
+    if (tid == 0) {
+        TilePart p;
+        p.Z = ((s_z[0] + s_z[1]) + s_z[2]) + s_z[3];
+        p.Z2 = ((s_z2[0] + s_z2[1]) + s_z2[2]) + s_z2[3];
+        U128 t{s_lo[0], s_hi[0]};
+        for (int w = 1; w < 4; ++w) t = add128(t, U128{s_lo[w], s_hi[w]});
+        p.q2lo = t.lo;
+        p.q2hi = t.hi;
+        S.tpart[tile] = p;
+    }
+
+    // estimate sums of the tile: lanes split into rows x columns (a column
+    // per lane, 64 / dp2 rows per wave step), reduced in a fixed order
+    int dp2 = 1;
+    while (dp2 < d) dp2 <<= 1;
+    const int R = 64 / dp2;
+    const int col = lane & (dp2 - 1), rsub = lane / dp2;
+    const i64 rem = n - base;
+    const int cnt = rem < kBTile ? (int)rem : kBTile;
+    double s1 = 0.0, s2 = 0.0;
+    if (col < d) {
+        for (int r = wid * R + rsub; r < cnt; r += 4 * R) {
+            const double e = se[bpad(r)];
+            if (e != 0.0) {
+                const double xv = S.x[(base + r) * d + col];
+                const double ex = e * xv;
+                s1 += ex;
+                s2 += ex * xv;
+            }
+        }
+    }
+    for (int o = dp2; o < 64; o <<= 1) {
+        s1 += __shfl_xor(s1, o, kWave);
+        s2 += __shfl_xor(s2, o, kWave);
+    }
+    if (lane < d) {
+        s_col[wid][lane] = s1;
+        s_col[wid][SMC_BATCH_DMAX + lane] = s2;
+    }
+    __syncthreads();
+    if (tid < 2 * d) {
+        const int cc = tid < d ? tid : SMC_BATCH_DMAX + (tid - d);
+        S.epart[(i64)tile * 2 * d + tid] =
+            ((s_col[0][cc] + s_col[1][cc]) + s_col[2][cc]) + s_col[3][cc];
+    }
+}
+
+// ------------------------------------------------------- per-sampler decide
+__global__ __launch_bounds__(256) void k_bdecide(const BSlot *slots, const int *n_act,
+                                                 const int *act, smc_resample_info *info,
+                                                 double *est)
+{
+    __shared__ double s_z[4], s_z2[4];
+    __shared__ u64 s_lo[4], s_hi[4];
+    __shared__ double s_col[2 * SMC_BATCH_DMAX];
+    __shared__ double s_sc, s_wgt, s_den, s_Z;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if ((int)blockIdx.x >= n_act[0]) return;
+    const int slot = act[blockIdx.x];
+    const BSlot &S = slots[slot];
+    BCtrl *c = S.ctrl;
+    const int d = S.d, ntile = S.ntile;
+    const i64 n = S.n;
+    double z = 0.0, z2 = 0.0;
+    U128 q2{0, 0};
+    for (int k = tid; k < ntile; k += 256) {
+        const TilePart p = S.tpart[k];
+        z += p.Z;
+        z2 += p.Z2;
+        q2 = add128(q2, U128{p.q2lo, p.q2hi});
+    }
+    z = wave_sum_f64(z);
+    z2 = wave_sum_f64(z2);
+    q2 = wave_sum_u128(q2);
+    if (lane == 0) {
+        s_z[wid] = z;
+        s_z2[wid] = z2;
+        s_lo[wid] = q2.lo;
+        s_hi[wid] = q2.hi;
+    }
+    if (tid < 2 * d) {  // estimate columns, tiles in order
+        double a = 0.0;
+        for (int k = 0; k < ntile; ++k) a += S.epart[(i64)k * 2 * d + tid];
+        s_col[tid] = a;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double Z = ((s_z[0] + s_z[1]) + s_z[2]) + s_z[3];
+        const double Z2 = ((s_z2[0] + s_z2[1]) + s_z2[2]) + s_z2[3];
+        U128 Q2{s_lo[0], s_hi[0]};
+        for (int w = 1; w < 4; ++w) Q2 = add128(Q2, U128{s_lo[w], s_hi[w]});
+        const u64 Ssum = S.status[ntile - 1] & kValMask;
+        const u64 key = c->mkey;
+        const double m = okey_inv(key);
+        unsigned err = 0;
+        if (c->bad) err = kErrNonfinite;
+        else if (key <= okey(-__builtin_huge_val())) err = kErrDegenerate;
+        else if (c->spin_fail) err = SMC_E_DEVICE;
+        c->spin_fail = 0;
+        int resample;
+        if (S.mode == SMC_MODE_FORCE) {
+            resample = 1;
+        } else if (S.mode == SMC_MODE_NEVER) {
+            resample = 0;
+        } else {
+            const U128 lhs = mul128_small(mul64(Ssum, Ssum), (u64)S.ess_den);
+            const U128 rhs = mul128_small(mul128_small(Q2, (u64)n), (u64)S.ess_num);
+            resample = lt128(lhs, rhs) ? 1 : 0;
+        }
+        if (err) resample = 0;
+        const unsigned t = c->t;
+        const u64 r = resample_word(S.seed, S.sampler, t);
+        const u64 U = mul64(r, Ssum).hi;
+        const double logZ = m + log(Z);
+        const double ess = (Z * Z) / Z2;
+        // normalising constant (eq. normconst) and recycling (eq. recycling)
+        const double logc = logZ - c->logZ_prev;
+        double sc = 1.0, den = c->rec_den;
+        if (logc > c->lc_max) {
+            sc = c->rec_steps ? exp(c->lc_max - logc) : 0.0;
+            den *= sc;
+            c->lc_max = logc;
+        }
+        const double wgt = exp(logc - c->lc_max);
+        den += wgt;
+        c->rec_den = den;
+        c->rec_steps += 1;
+        c->log_c = logc;
+        c->logZ_prev = (resample && !err) ? 0.0 : logZ;
+        c->S = Ssum;
+        c->U = U;
+        c->Q2lo = Q2.lo;
+        c->Q2hi = Q2.hi;
+        c->m = m;
+        c->Z = Z;
+        c->Z2 = Z2;
+        c->logZ = logZ;
+        c->ess = ess;
+        c->resample = (unsigned)resample;
+        c->err_call = err;
+        if (err && !c->err_latch) c->err_latch = err;
+        c->t = t + 1;
+        s_sc = sc;
+        s_wgt = wgt;
+        s_den = den;
+        s_Z = Z;
+        if (info) {
+            smc_resample_info *o = info + slot;
+            o->m = m;
+            o->logZ = logZ;
+            o->ess = ess;
+            o->Z = Z;
+            o->Z2 = Z2;
+            o->S = Ssum;
+            o->U = U;
+            o->Q2_hi = Q2.hi;
+            o->Q2_lo = Q2.lo;
+            o->K = S.K;
+            o->resampled = resample;
+            o->err = (int)err;
+            o->pad = 0;
+            o->log_c = logc;
+        }
+    }
+    __syncthreads();
+    if (tid < 2 * d) {
+        const double f = s_col[tid] / s_Z;
+        const double num = S.rec_num[tid] * s_sc + s_wgt * f;
+        S.rec_num[tid] = num;
+        if (est) {
+            est[(i64)slot * SMC_BATCH_EST_STRIDE + tid] = f;
+            est[(i64)slot * SMC_BATCH_EST_STRIDE + 2 * d + tid] = num / s_den;
+        }
+    }
+}
+
+// ------------------------------------------------------------ redistribute
+__global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *n_act,
+                                                 const int *act, const int *chunk_pref)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int slot, ch;
+    if (!locate(chunk_pref, act, n_act[0], blockIdx.x, slot, ch)) return;
+    const BSlot &S = slots[slot];
+    const BCtrl *c = S.ctrl;
+    if (!c->resample || c->err_call) return;
+    const i64 n = S.n;
+    const int d = S.d;
+    const u64 Ssum = c->S, U = c->U;
+    const i64 p = (i64)ch * kBChunk + tid;
+    // anc(p) = first j with N S_j + U >= (p + 1) S (it exists: j = n - 1)
+    i64 lo = 0, hi = n - 1;
+    if (p < n) {
+        const U128 rhs = mul64((u64)(p + 1), Ssum);
+        while (lo < hi) {
+            const i64 mid = (lo + hi) >> 1;
+            if (lt128(add128(mul64((u64)n, S.pref[mid]), U), rhs)) lo = mid + 1;
+            else hi = mid;
+        }
+        S.lp_scr[p] = S.lp[lo];
+    }
+    const i64 anc = lo;
+    int dp2 = 1;
+    while (dp2 < d) dp2 <<= 1;
+    const int R = 64 / dp2;
+    const int col = lane & (dp2 - 1), rsub = lane / dp2;
+    const i64 pw = (i64)ch * kBChunk + wid * 64;
+    for (int o0 = 0; o0 < 64; o0 += R) {
+        const int o = o0 + rsub;
+        const int lo32 = __shfl((int)(anc & 0xffffffff), o, kWave);
+        const int hi32 = __shfl((int)(anc >> 32), o, kWave);
+        const i64 src = ((i64)hi32 << 32) | (i64)(unsigned)lo32;
+        const i64 pp = pw + o;
+        if (col < d && pp < n) S.x_scr[pp * d + col] = S.x[src * d + col];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bcopyback(const BSlot *slots, const int *n_act,
+                                                   const int *act, const int *tile_pref)
+{
+    int slot, tile;
+    if (!locate(tile_pref, act, n_act[0], blockIdx.x, slot, tile)) return;
+    const BSlot &S = slots[slot];
+    const BCtrl *c = S.ctrl;
+    if (!c->resample || c->err_call) return;
+    const i64 n = S.n;
+    const int d = S.d;
+    const i64 base = (i64)tile * kBTile;
+    const i64 cnt = (n - base) < kBTile ? (n - base) : kBTile;
+    const i64 e0 = base * d, e1 = (base + cnt) * d;
+    for (i64 e = e0 + threadIdx.x; e < e1; e += 256) S.x[e] = S.x_scr[e];
+    for (i64 i = base + threadIdx.x; i < base + cnt; i += 256) {
+        S.lp[i] = S.lp_scr[i];
+        S.logw[i] = S.reset;
+    }
+}
+
+// ------------------------------------------------------------------- host
+struct SamplerLayout {
+    size_t ctrl, lp, x_scr, lp_scr, pref, status, tpart, tis, epart, rec_num, total;
+};
+
+inline int64_t ntile_of(int64_t n) { return (n + kBTile - 1) / kBTile; }
+inline int64_t nchunk_of(int64_t n) { return (n + kBChunk - 1) / kBChunk; }
+
+SamplerLayout sampler_layout(int64_t n, int d)
+{
+    SamplerLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t nt = (size_t)ntile_of(n);
+    L.ctrl = take(sizeof(BCtrl));
+    L.lp = take(8 * (size_t)n);
+    L.x_scr = take(8 * (size_t)n * d);
+    L.lp_scr = take(8 * (size_t)n);
+    L.pref = take(8 * (size_t)n);
+    L.status = take(8 * nt);
+    L.tpart = take(sizeof(TilePart) * nt);
+    L.tis = take(sizeof(BTileIS) * nt);
+    L.epart = take(8 * 2 * (size_t)d * nt);
+    L.rec_num = take(8 * 2 * (size_t)d);
+    L.total = off;
+    return L;
+}
+
+struct BatchLayout {
+    size_t slots, n_act, act, tile_pref, chunk_pref, bact, btile_pref, total;
+};
+
+BatchLayout batch_layout(int cap)
+{
+    BatchLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    L.slots = take(sizeof(BSlot) * (size_t)cap);
+    L.n_act = take(4 * (1 + kBuckets));
+    L.act = take(4 * (size_t)cap);
+    L.tile_pref = take(4 * (size_t)(cap + 1));
+    L.chunk_pref = take(4 * (size_t)(cap + 1));
+    L.bact = take(4 * (size_t)kBuckets * cap);
+    L.btile_pref = take(4 * (size_t)kBuckets * (cap + 1));
+    L.total = off;
+    return L;
+}
+
+bool finite(double v) { return v == v && v != HUGE_VAL && v != -HUGE_VAL; }
+
+bool desc_ok(const smc_batch_sampler *s)
+{
+    if (!s || s->n < 1 || s->n > kBMaxN || s->d < 1 || s->d > SMC_BATCH_DMAX) return false;
+    if (s->mode < SMC_MODE_AUTO || s->mode > SMC_MODE_NEVER) return false;
+    if (s->ess_num < 0 || s->ess_num > 16 || s->ess_den < 1 || s->ess_den > 16) return false;
+    if (!finite(s->rw_sd) || !(s->rw_sd > 0.0) || !finite(s->init_sd) || !(s->init_sd > 0.0))
+        return false;
+    if (!finite(s->init_mean) || !finite(s->init_log_norm) || !finite(s->log_norm)) return false;
+    if (!s->mean || !s->chol || !s->x || !s->logw) return false;
+    return true;
+}
+
+}  // namespace
+}  // namespace smc
+
+using namespace smc;
+
+struct smc_batch {
+    int cap;
+    unsigned char *ws;
+    BSlot *d_slots;
+    BTabs tabs;
+    std::vector<BSlot> h_slots;
+    // host mirror of the tables (grid sizes)
+    int n_act, total_tiles, total_chunks;
+    int btiles[kBuckets];
+    // graph of one step for the current membership and output pointers
+    bool graph_on;
+    hipStream_t cap_stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    unsigned version, g_version, e_version;
+    int eager_same;  // eager steps since the last membership change
+    smc_resample_info *g_info;
+    double *g_est;
+};
+
+namespace {
+
+inline hipStream_t HS(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+void mirror_update(smc_batch *b)
+{
+    b->n_act = b->total_tiles = b->total_chunks = 0;
+    for (int q = 0; q < kBuckets; ++q) b->btiles[q] = 0;
+    for (int s = 0; s < b->cap; ++s) {
+        const BSlot &v = b->h_slots[s];
+        if (v.n <= 0) continue;
+        b->n_act += 1;
+        b->total_tiles += v.ntile;
+        b->total_chunks += v.nchunk;
+        b->btiles[v.bucket] += v.ntile;
+    }
+    b->version += 1;
+    b->eager_same = 0;
+}
+
+hipError_t launch_tables(smc_batch *b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_btables, dim3(1), dim3(256), 0, s, (const BSlot *)b->d_slots, b->cap,
+                       b->tabs);
+    return hipGetLastError();
+}
+
+template <bool kInit>
+void launch_bis_bucket(int q, dim3 g, hipStream_t s, const smc_batch *b, int single)
+{
+    const BSlot *sl = b->d_slots;
+    const BTabs &t = b->tabs;
+    switch (q) {
+#define SMC_BIS_CASE(Q)                                                                       \
+    case Q:                                                                                   \
+        hipLaunchKernelGGL((k_bis<8 * (Q + 1), kInit>), g, dim3(256), 0, s, sl, t.n_act, t.bact, \
+                           t.btile_pref, Q, b->cap, single);                                  \
+        break;
+        SMC_BIS_CASE(0) SMC_BIS_CASE(1) SMC_BIS_CASE(2) SMC_BIS_CASE(3)
+        SMC_BIS_CASE(4) SMC_BIS_CASE(5) SMC_BIS_CASE(6) SMC_BIS_CASE(7)
+#undef SMC_BIS_CASE
+    default: break;
+    }
+}
+
+hipError_t enqueue_step(smc_batch *b, smc_resample_info *info, double *est, hipStream_t s)
+{
+    const BSlot *sl = b->d_slots;
+    const BTabs &t = b->tabs;
+    for (int q = 0; q < kBuckets; ++q)
+        if (b->btiles[q] > 0) launch_bis_bucket<false>(q, dim3(b->btiles[q]), s, b, -1);
+    hipLaunchKernelGGL(k_bscan, dim3(b->total_tiles), dim3(256), 0, s, sl, t.n_act, t.act,
+                       t.tile_pref);
+    hipLaunchKernelGGL(k_bdecide, dim3(b->n_act), dim3(256), 0, s, sl, t.n_act, t.act, info, est);
+    hipLaunchKernelGGL(k_bexpand, dim3(b->total_chunks), dim3(256), 0, s, sl, t.n_act, t.act,
+                       t.chunk_pref);
+    hipLaunchKernelGGL(k_bcopyback, dim3(b->total_tiles), dim3(256), 0, s, sl, t.n_act, t.act,
+                       t.tile_pref);
+    return hipGetLastError();
+}
+
+void drop_graph(smc_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t smc_batch_sampler_bytes(const smc_batch_sampler *h_s)
+{
+    if (!desc_ok(h_s)) return 0;
+    return sampler_layout(h_s->n, h_s->d).total;
+}
+
+size_t smc_batch_workspace_bytes(int32_t capacity)
+{
+    if (capacity < 1 || capacity > kBMaxCap) return 0;
+    return batch_layout(capacity).total;
+}
+
+smc_status smc_batch_create(smc_batch **h_out, int32_t capacity, void *ws, size_t ws_bytes,
+                            void *stream)
+{
+    if (!h_out || capacity < 1 || capacity > kBMaxCap || !ws) return SMC_E_ARG;
+    if (((uintptr_t)ws & 255) != 0) return SMC_E_ARG;
+    const BatchLayout L = batch_layout(capacity);
+    if (ws_bytes < L.total) return SMC_E_NOMEM;
+    smc_batch *b = new (std::nothrow) smc_batch;
+    if (!b) return SMC_E_NOMEM;
+    b->cap = capacity;
+    b->ws = reinterpret_cast<unsigned char *>(ws);
+    b->d_slots = reinterpret_cast<BSlot *>(b->ws + L.slots);
+    b->tabs.n_act = reinterpret_cast<int *>(b->ws + L.n_act);
+    b->tabs.act = reinterpret_cast<int *>(b->ws + L.act);
+    b->tabs.tile_pref = reinterpret_cast<int *>(b->ws + L.tile_pref);
+    b->tabs.chunk_pref = reinterpret_cast<int *>(b->ws + L.chunk_pref);
+    b->tabs.bact = reinterpret_cast<int *>(b->ws + L.bact);
+    b->tabs.btile_pref = reinterpret_cast<int *>(b->ws + L.btile_pref);
+    b->h_slots.assign((size_t)capacity, BSlot());
+    for (auto &v : b->h_slots) v.n = 0;
+    b->graph_on = true;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->version = 0;
+    b->g_version = ~0u;
+    b->e_version = ~0u;
+    b->eager_same = 0;
+    b->g_info = nullptr;
+    b->g_est = nullptr;
+    if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return SMC_E_DEVICE;
+    }
+    mirror_update(b);
+    hipLaunchKernelGGL(k_bslots_clear, dim3((capacity + 255) / 256), dim3(256), 0, HS(stream),
+                       b->d_slots, capacity);
+    if (hipGetLastError() != hipSuccess || launch_tables(b, HS(stream)) != hipSuccess) {
+        (void)hipStreamDestroy(b->cap_stream);
+        delete b;
+        return SMC_E_DEVICE;
+    }
+    *h_out = b;
+    return SMC_OK;
+}
+
+smc_status smc_batch_attach(smc_batch *b, int32_t slot, const smc_batch_sampler *h_s,
+                            void *stream)
+{
+    if (!b || slot < 0 || slot >= b->cap || !desc_ok(h_s)) return SMC_E_ARG;
+    if (b->h_slots[slot].n > 0) return SMC_E_ARG;
+    if (!h_s->ws || ((uintptr_t)h_s->ws & 255) != 0) return SMC_E_ARG;
+    const SamplerLayout L = sampler_layout(h_s->n, h_s->d);
+    if (h_s->ws_bytes < L.total) return SMC_E_NOMEM;
+    const int64_t nt = ntile_of(h_s->n), nc = nchunk_of(h_s->n);
+    if ((int64_t)b->total_tiles + nt > 0x7fffffff || (int64_t)b->total_chunks + nc > 0x7fffffff)
+        return SMC_E_UNSUPPORTED;
+    unsigned char *w = reinterpret_cast<unsigned char *>(h_s->ws);
+    BSlot v;
+    v.n = h_s->n;
+    v.d = h_s->d;
+    v.mode = h_s->mode;
+    v.ess_num = h_s->ess_num;
+    v.ess_den = h_s->ess_den;
+    {
+        int c = 0;
+        while ((1LL << c) < h_s->n) ++c;
+        v.K = 61 - c < 52 ? 61 - c : 52;
+    }
+    v.ntile = (int)nt;
+    v.nchunk = (int)nc;
+    v.bucket = (h_s->d - 1) / 8;
+    v.sampler = h_s->sampler_id;
+    v.pad = 0;
+    v.seed = h_s->seed;
+    v.rw_sd = h_s->rw_sd;
+    v.init_mean = h_s->init_mean;
+    v.init_sd = h_s->init_sd;
+    v.init_prec = 1.0 / (h_s->init_sd * h_s->init_sd);
+    v.init_log_norm = h_s->init_log_norm;
+    v.log_norm = h_s->log_norm;
+    v.reset = -std::log((double)h_s->n);
+    v.mean = h_s->mean;
+    v.chol = h_s->chol;
+    v.x = h_s->x;
+    v.logw = h_s->logw;
+    v.ctrl = reinterpret_cast<BCtrl *>(w + L.ctrl);
+    v.lp = reinterpret_cast<double *>(w + L.lp);
+    v.x_scr = reinterpret_cast<double *>(w + L.x_scr);
+    v.lp_scr = reinterpret_cast<double *>(w + L.lp_scr);
+    v.epart = reinterpret_cast<double *>(w + L.epart);
+    v.rec_num = reinterpret_cast<double *>(w + L.rec_num);
+    v.pref = reinterpret_cast<u64 *>(w + L.pref);
+    v.status = reinterpret_cast<u64 *>(w + L.status);
+    v.tpart = reinterpret_cast<TilePart *>(w + L.tpart);
+    v.tis = reinterpret_cast<BTileIS *>(w + L.tis);
+    const hipStream_t s = HS(stream);
+    hipLaunchKernelGGL(k_bslot_set, dim3(1), dim3(1), 0, s, v, b->d_slots + slot);
+    launch_bis_bucket<true>(v.bucket, dim3(v.ntile), s, b, slot);
+    hipLaunchKernelGGL(k_binit, dim3(1), dim3(64), 0, s, (const BSlot *)b->d_slots, slot);
+    if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
+    b->h_slots[slot] = v;
+    mirror_update(b);
+    return launch_tables(b, s) == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+}
+
+smc_status smc_batch_detach(smc_batch *b, int32_t slot, void *stream)
+{
+    if (!b || slot < 0 || slot >= b->cap || b->h_slots[slot].n <= 0) return SMC_E_ARG;
+    BSlot v = BSlot();
+    v.n = 0;
+    const hipStream_t s = HS(stream);
+    hipLaunchKernelGGL(k_bslot_set, dim3(1), dim3(1), 0, s, v, b->d_slots + slot);
+    if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
+    b->h_slots[slot].n = 0;
+    mirror_update(b);
+    return launch_tables(b, s) == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+}
+
+smc_status smc_batch_step(smc_batch *b, smc_resample_info *info, double *est, void *stream)
+{
+    if (!b) return SMC_E_ARG;
+    if (b->n_act == 0) return SMC_OK;
+    const hipStream_t s = HS(stream);
+    if (b->graph_on) {
+        const bool same = b->g_version == b->version && b->g_info == info && b->g_est == est;
+        if (same && b->exec)
+            return hipGraphLaunch(b->exec, s) == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+        // capture once the membership has held for two eager steps
+        if (b->e_version == b->version && b->eager_same >= 2) {
+            drop_graph(b);
+            hipGraph_t g = nullptr;
+            if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) !=
+                hipSuccess)
+                return SMC_E_DEVICE;
+            const hipError_t le = enqueue_step(b, info, est, b->cap_stream);
+            const hipError_t ce = hipStreamEndCapture(b->cap_stream, &g);
+            if (le != hipSuccess || ce != hipSuccess || !g) {
+                if (g) (void)hipGraphDestroy(g);
+                return SMC_E_DEVICE;
+            }
+            b->graph = g;
+            if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+                drop_graph(b);
+                return SMC_E_DEVICE;
+            }
+            b->g_version = b->version;
+            b->g_info = info;
+            b->g_est = est;
+            return hipGraphLaunch(b->exec, s) == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+        }
+    }
+    if (b->e_version != b->version) {
+        b->e_version = b->version;
+        b->eager_same = 0;
+    }
+    b->eager_same += 1;
+    return enqueue_step(b, info, est, s) == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+}
+
+smc_status smc_batch_set_graph(smc_batch *b, int32_t enable)
+{
+    if (!b) return SMC_E_ARG;
+    b->graph_on = enable != 0;
+    if (!b->graph_on) {
+        drop_graph(b);
+        b->g_version = ~0u;
+    }
+    return SMC_OK;
+}
+
+smc_status smc_batch_counts(const smc_batch *b, int32_t *h_samplers, int64_t *h_tiles)
+{
+    if (!b) return SMC_E_ARG;
+    if (h_samplers) *h_samplers = b->n_act;
+    if (h_tiles) *h_tiles = b->total_tiles;
+    return SMC_OK;
+}
+
+smc_status smc_batch_sync_error(smc_batch *b, int32_t slot, void *stream)
+{
+    if (!b || slot < 0 || slot >= b->cap || b->h_slots[slot].n <= 0) return SMC_E_ARG;
+    if (hipStreamSynchronize(HS(stream)) != hipSuccess) return SMC_E_DEVICE;
+    BCtrl *c = b->h_slots[slot].ctrl;
+    unsigned e = 0;
+    if (hipMemcpy(&e, &c->err_latch, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess)
+        return SMC_E_DEVICE;
+    const unsigned zero = 0;
+    if (e && hipMemcpy(&c->err_latch, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+        return SMC_E_DEVICE;
+    return (smc_status)e;
+}
+
+smc_status smc_batch_destroy(smc_batch *b)
+{
+    if (!b) return SMC_E_ARG;
+    drop_graph(b);
+    (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return SMC_OK;
+}
+
+}  // extern "C"

@@ -218,3 +218,117 @@ class Sampler:
 
     def sync_error(self) -> int:
         return self._lib.smc_sync_error(self.ctx, _stream())
+
+
+def _aligned(nbytes: int, device) -> tuple:
+    """A uint8 device buffer and its first 256-byte aligned address."""
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    return buf, (buf.data_ptr() + 255) & ~255
+
+
+class Batch:
+    """Many independent samplers advanced by one sequence of launches
+    (include/smc_batch.h): Gaussian targets with precision U^T U, each
+    sampler of its own size N and dimension d <= 64.
+
+    ``attach(slot, ...)`` allocates the sampler's particles and workspace as
+    torch tensors and initialises it; ``step()`` advances every attached
+    sampler one iteration; ``detach(slot)`` frees the slot.  A sampler's
+    results depend only on its own arguments, not on the rest of the batch.
+    """
+
+    def __init__(self, capacity: int, *, graph: bool = True, device=None):
+        lib = L.load()
+        self._lib = lib
+        self.capacity = int(capacity)
+        self.device = torch.device(device or "cuda")
+        nb = lib.smc_batch_workspace_bytes(self.capacity)
+        if nb == 0:
+            raise L.SmcError(L.SMC_E_ARG, "smc_batch_workspace_bytes")
+        self._ws, ws = _aligned(nb, self.device)
+        self.info_buf = torch.zeros(self.capacity * L.INFO_BYTES, dtype=torch.uint8,
+                                    device=self.device)
+        self.est = torch.zeros(self.capacity * L.BATCH_EST_STRIDE, dtype=torch.float64,
+                               device=self.device)
+        self.h = C.c_void_p()
+        L.check(lib.smc_batch_create(C.byref(self.h), self.capacity, C.c_void_p(ws), nb,
+                                     _stream()), "smc_batch_create")
+        L.check(lib.smc_batch_set_graph(self.h, 1 if graph else 0), "smc_batch_set_graph")
+        self.slots = {}
+
+    def __del__(self):
+        if getattr(self, "h", None) and self.h.value:
+            self._lib.smc_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def attach(self, slot: int, n: int, d: int, mean, chol, *, seed: int = 0,
+               sampler_id: int = 0, rw_sd: float = 0.5, init_mean: float = 0.0,
+               init_sd: float = 3.0, mode: int = L.MODE_AUTO, ess_num: int = 1,
+               ess_den: int = 2, log_norm=None, init_log_norm=None) -> None:
+        dev = self.device
+        n, d = int(n), int(d)
+        m = torch.as_tensor(mean, dtype=torch.float64).reshape(-1).contiguous()
+        U = torch.as_tensor(chol, dtype=torch.float64).reshape(d, d).contiguous()
+        if m.numel() != d:
+            raise ValueError("mean must have d entries")
+        desc = L.SmcBatchSampler()
+        desc.n, desc.d, desc.mode = n, d, mode
+        desc.ess_num, desc.ess_den = ess_num, ess_den
+        desc.sampler_id, desc.seed = sampler_id, int(seed) & (2**64 - 1)
+        desc.rw_sd, desc.init_mean, desc.init_sd = rw_sd, init_mean, init_sd
+        desc.init_log_norm = (init_log_norm if init_log_norm is not None
+                              else -0.5 * d * math.log(2.0 * math.pi * init_sd * init_sd))
+        desc.log_norm = (log_norm if log_norm is not None else
+                         -0.5 * d * math.log(2.0 * math.pi)
+                         + float(torch.log(torch.diagonal(U)).sum()))
+        md, Ud = m.to(dev), U.to(dev)
+        x = torch.empty((n, d), dtype=torch.float64, device=dev)
+        logw = torch.empty(n, dtype=torch.float64, device=dev)
+        desc.mean, desc.chol = md.data_ptr(), Ud.data_ptr()
+        desc.x, desc.logw = x.data_ptr(), logw.data_ptr()
+        nb = self._lib.smc_batch_sampler_bytes(C.byref(desc))
+        if nb == 0:
+            raise L.SmcError(L.SMC_E_ARG, "smc_batch_sampler_bytes")
+        wsb, ws = _aligned(nb, dev)
+        desc.ws, desc.ws_bytes = ws, nb
+        L.check(self._lib.smc_batch_attach(self.h, int(slot), C.byref(desc), _stream()),
+                "smc_batch_attach")
+        self.slots[int(slot)] = {"n": n, "d": d, "x": x, "logw": logw, "ws": wsb,
+                                 "mean": md, "chol": Ud, "desc": desc}
+
+    def detach(self, slot: int) -> None:
+        L.check(self._lib.smc_batch_detach(self.h, int(slot), _stream()), "smc_batch_detach")
+        self.slots.pop(int(slot))
+
+    def step(self, info: bool = True, est: bool = True) -> None:
+        L.check(self._lib.smc_batch_step(self.h, _ptr(self.info_buf) if info else None,
+                                         _ptr(self.est) if est else None, _stream()),
+                "smc_batch_step")
+
+    def set_graph(self, enable: bool) -> None:
+        L.check(self._lib.smc_batch_set_graph(self.h, 1 if enable else 0), "smc_batch_set_graph")
+
+    def counts(self) -> tuple:
+        ns, nt = C.c_int32(), C.c_int64()
+        L.check(self._lib.smc_batch_counts(self.h, C.byref(ns), C.byref(nt)), "smc_batch_counts")
+        return ns.value, nt.value
+
+    def x(self, slot: int) -> torch.Tensor:
+        return self.slots[int(slot)]["x"]
+
+    def logw(self, slot: int) -> torch.Tensor:
+        return self.slots[int(slot)]["logw"]
+
+    def info(self, slot: int) -> dict:
+        o = int(slot) * L.INFO_BYTES
+        return decode_info(self.info_buf[o:o + L.INFO_BYTES])
+
+    def estimates(self, slot: int) -> dict:
+        d = self.slots[int(slot)]["d"]
+        o = int(slot) * L.BATCH_EST_STRIDE
+        e = self.est[o:o + 4 * d].cpu().numpy()
+        return {"mean": e[:d], "m2": e[d:2 * d], "rec_mean": e[2 * d:3 * d],
+                "rec_m2": e[3 * d:4 * d]}
+
+    def sync_error(self, slot: int) -> int:
+        return self._lib.smc_batch_sync_error(self.h, int(slot), _stream())

@@ -10,9 +10,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "smc.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:size_t|smc_status|const char \*)\s*(smc_\w+)\s*\(",
-                                 text, re.M)))
+    out = set()
+    inc = os.path.join(ROOT, "include")
+    for f in sorted(os.listdir(inc)):
+        if f.endswith(".h"):
+            text = open(os.path.join(inc, f)).read()
+            out |= set(re.findall(r"^\s*(?:size_t|smc_status|const char \*)\s*(smc_\w+)\s*\(",
+                                  text, re.M))
+    return sorted(out)
 
 
 @pytest.fixture(scope="module")
@@ -27,7 +32,8 @@ def lib():
 def test_header_declares_the_entry_points():
     syms = declared_symbols()
     for s in ("smc_init", "smc_step", "smc_resample", "smc_redistribute", "smc_workspace_bytes",
-              "smc_destroy", "smc_status_string"):
+              "smc_destroy", "smc_status_string", "smc_batch_create", "smc_batch_attach",
+              "smc_batch_step", "smc_batch_detach"):
         assert s in syms
 
 
@@ -69,3 +75,23 @@ def test_struct_sizes_match_header():
     from paper_1905_10252_amd import _lib as L
     assert C.sizeof(L.SmcInfo) == 96
     assert C.sizeof(L.SmcConfig) == 192  # sizeof(smc_config) on x86-64 (gcc)
+
+
+def test_batch_workspace_bytes(lib):
+    from paper_1905_10252_amd import _lib as L
+    assert C.sizeof(L.SmcBatchSampler) == 128
+    assert lib.smc_batch_workspace_bytes(0) == 0
+    assert lib.smc_batch_workspace_bytes(4097) == 0
+    assert lib.smc_batch_workspace_bytes(256) > 256 * 200
+    d = L.SmcBatchSampler()
+    d.n, d.d, d.mode, d.ess_num, d.ess_den = 10000, 33, 0, 1, 2
+    d.rw_sd, d.init_sd = 0.1, 3.0
+    d.mean = d.chol = d.x = d.logw = 256
+    b = lib.smc_batch_sampler_bytes(C.byref(d))
+    assert 8 * 10000 * (3 + 33) < b < 8 * 10000 * (3 + 33) + (1 << 16)  # lp, scratch, prefix
+    d.d = 65
+    assert lib.smc_batch_sampler_bytes(C.byref(d)) == 0
+    d.d, d.n = 4, 0
+    assert lib.smc_batch_sampler_bytes(C.byref(d)) == 0
+    d.n, d.chol = 5, None
+    assert lib.smc_batch_sampler_bytes(C.byref(d)) == 0
