@@ -1,0 +1,206 @@
+"""GPU parity of the batched sampler (include/smc_batch.h) against the CPU
+oracle, sampler by sampler.
+
+Particle rows and log-weights are fixed IEEE sequences (deterministic normals,
+the quadratic form summed in index order) and resampling is integer-exact, so
+they must match the oracle bit for bit; estimates, log Z and log c_t are FP64
+sums in another order (1e-11 / 1e-10 relative).  A sampler's bits must not
+depend on the other samplers of the batch, on graph replay, or on samplers
+attached and detached around it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_10252_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def smc(dev):
+    from paper_1905_10252_amd import smc as S
+    return S
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint64)
+
+
+def close(a, b, rtol):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return np.max(np.abs(a - b) / np.maximum(np.abs(b), 1.0)) <= rtol
+
+
+def spec(k, n, d, mode, seed=500):
+    rng = np.random.default_rng(seed + k)
+    mean, U, _ = I.wishart_target(d, rng)
+    return dict(n=n, d=d, mean=mean, chol=U, rw_sd=0.5 / math.sqrt(d),
+                seed=(seed << 32) + k, sampler_id=k, mode=mode)
+
+
+def attach(B, slot, sp):
+    B.attach(slot, sp["n"], sp["d"], sp["mean"], sp["chol"], seed=sp["seed"],
+             sampler_id=sp["sampler_id"], rw_sd=sp["rw_sd"], init_mean=sp.get("init_mean", 0.0),
+             init_sd=sp.get("init_sd", 3.0), mode=sp["mode"])
+
+
+def oracle_of(B, slot, sp):
+    desc = B.slots[slot]["desc"]
+    o = O.Sampler(sp["n"], sp["d"], O.T_GAUSS_CHOL, seed=sp["seed"], sampler_id=sp["sampler_id"],
+                  rw_sd=sp["rw_sd"], init_mean=sp.get("init_mean", 0.0),
+                  init_sd=sp.get("init_sd", 3.0), mean=sp["mean"], chol=sp["chol"],
+                  mode=sp["mode"], log_norm=desc.log_norm, init_log_norm=desc.init_log_norm)
+    o.init()
+    return o
+
+
+def check_state(B, slot, o, where):
+    assert np.array_equal(bits(B.x(slot).cpu().numpy()), bits(o.x)), where
+    assert np.array_equal(bits(B.logw(slot).cpu().numpy()), bits(o.logw)), where
+
+
+def check_step(B, slot, o, out, where):
+    info = B.info(slot)
+    for k in ("S", "U", "Q2_hi", "Q2_lo", "resampled", "err", "K"):
+        assert info[k] == out["info"][k], (where, k, info[k], out["info"][k])
+    check_state(B, slot, o, where)
+    e = B.estimates(slot)
+    assert close(e["mean"], out["mean"], 1e-11), where
+    assert close(e["m2"], out["m2"], 1e-11), where
+    assert close(e["rec_mean"], out["rec_mean"], 1e-10), where
+    assert abs(info["log_c"] - out["log_c"]) <= 1e-10 * max(1.0, abs(out["log_c"])), where
+
+
+# (n, d, mode): ragged tiles, every dimension bucket, all three triggers
+MIX = [(1, 1, O.MODE_AUTO), (255, 3, O.MODE_FORCE), (4096, 8, O.MODE_AUTO),
+       (4097, 9, O.MODE_FORCE), (10000, 33, O.MODE_AUTO), (20000, 64, O.MODE_NEVER),
+       (7000, 17, O.MODE_FORCE), (3000, 56, O.MODE_AUTO)]
+SLOTS = [3, 0, 9, 1, 5, 2, 4, 7]
+
+
+def test_batch_mix_bit_exact_vs_oracle(smc, dev):
+    print("batch mix", flush=True)
+    B = smc.Batch(10, device=dev)
+    specs = [spec(k, *m) for k, m in enumerate(MIX)]
+    for slot, sp in zip(SLOTS, specs):
+        attach(B, slot, sp)
+    assert B.counts()[0] == len(MIX)
+    orcs = {slot: oracle_of(B, slot, sp) for slot, sp in zip(SLOTS, specs)}
+    for slot in SLOTS:
+        check_state(B, slot, orcs[slot], ("init", slot))
+    for t in range(1, 7):  # steps 3.. replay the captured graph
+        B.step()
+        for slot in SLOTS:
+            check_step(B, slot, orcs[slot], orcs[slot].step(), (t, slot))
+    for slot in SLOTS:
+        assert B.sync_error(slot) == 0
+
+
+def run_alone(smc, dev, sp, steps, graph=True):
+    B = smc.Batch(1, graph=graph, device=dev)
+    attach(B, 0, sp)
+    for _ in range(steps):
+        B.step()
+    return B.x(0).cpu().numpy(), B.estimates(0)
+
+
+def test_batch_results_independent_of_the_mix(smc, dev):
+    print("batch alone vs mix", flush=True)
+    specs = [spec(20 + k, *m) for k, m in enumerate(MIX)]
+    B = smc.Batch(len(MIX), device=dev)
+    for slot, sp in enumerate(specs):
+        attach(B, slot, sp)
+    for _ in range(5):
+        B.step()
+    for slot in (1, 4, 5):
+        x, e = run_alone(smc, dev, specs[slot], 5, graph=(slot != 4))
+        assert np.array_equal(bits(B.x(slot).cpu().numpy()), bits(x)), slot
+        got = B.estimates(slot)
+        for k in ("mean", "m2", "rec_mean", "rec_m2"):
+            assert np.array_equal(bits(got[k]), bits(e[k])), (slot, k)
+
+
+def test_batch_graph_replay_equals_eager(smc, dev):
+    print("batch graph vs eager", flush=True)
+    specs = [spec(40 + k, *m) for k, m in enumerate(MIX[:5])]
+    outs = []
+    for graph in (True, False):
+        B = smc.Batch(5, graph=graph, device=dev)
+        for slot, sp in enumerate(specs):
+            attach(B, slot, sp)
+        for _ in range(6):
+            B.step()
+        outs.append([B.x(s).cpu().numpy() for s in range(5)])
+    for a, b in zip(*outs):
+        assert np.array_equal(bits(a), bits(b))
+
+
+def test_batch_attach_detach_midrun(smc, dev):
+    print("batch attach/detach", flush=True)
+    a, b, c = spec(60, 5000, 12, O.MODE_FORCE), spec(61, 9000, 40, O.MODE_AUTO), \
+        spec(62, 300, 2, O.MODE_FORCE)
+    B = smc.Batch(4, device=dev)
+    attach(B, 0, a)
+    attach(B, 1, b)
+    oa, ob = oracle_of(B, 0, a), oracle_of(B, 1, b)
+    for t in range(3):
+        B.step()
+        check_step(B, 0, oa, oa.step(), ("a", t))
+        ob.step()
+    B.detach(1)
+    attach(B, 1, c)
+    attach(B, 3, b | {"seed": b["seed"] + 1})
+    oc = oracle_of(B, 1, c)
+    for t in range(4):
+        B.step()
+        check_step(B, 0, oa, oa.step(), ("a2", t))
+        check_step(B, 1, oc, oc.step(), ("c", t))
+    assert B.counts()[0] == 3
+
+
+def test_batch_large_sampler(smc, dev):
+    print("batch n=2^20+5", flush=True)
+    sp = spec(70, (1 << 20) + 5, 2, O.MODE_FORCE)
+    B = smc.Batch(2, device=dev)
+    attach(B, 1, sp)
+    o = oracle_of(B, 1, sp)
+    for t in range(2):
+        B.step()
+        check_step(B, 1, o, o.step(), t)
+
+
+def test_batch_workload_sampled(smc, dev):
+    """The 256-sampler workload (N log-uniform 2^8..2^16, d 1..64): sampled
+    samplers bit-exact against the oracle over three steps."""
+    print("batch workload 256 samplers", flush=True)
+    specs = I.batch_specs()
+    B = smc.Batch(len(specs), device=dev)
+    for slot, sp in enumerate(specs):
+        attach(B, slot, sp | {"mode": O.MODE_AUTO})
+    ns = np.array([s["n"] for s in specs])
+    ds = np.array([s["d"] for s in specs])
+    pick = sorted({int(np.argmin(ns)), int(np.argmax(ns)), int(np.argmax(ds)), 17})
+    orcs = {k: oracle_of(B, k, specs[k] | {"mode": O.MODE_AUTO}) for k in pick}
+    for t in range(3):
+        B.step()
+        for k in pick:
+            check_step(B, k, orcs[k], orcs[k].step(), (t, k))
+    infos = [B.info(k) for k in range(len(specs))]
+    assert all(i["err"] == 0 for i in infos)
+
+
+def test_batch_rejects_bad_arguments(smc, dev):
+    B = smc.Batch(2, device=dev)
+    sp = spec(80, 100, 4, O.MODE_AUTO)
+    attach(B, 0, sp)
+    with pytest.raises(smc.L.SmcError):
+        attach(B, 0, sp)          # slot taken
+    with pytest.raises(smc.L.SmcError):
+        attach(B, 2, sp)          # no such slot
+    with pytest.raises(smc.L.SmcError):
+        B.attach(1, 100, 65, np.zeros(65), np.eye(65))   # d > 64
+    with pytest.raises(smc.L.SmcError):
+        B.detach(1)               # free slot
