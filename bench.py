@@ -144,7 +144,61 @@ def sampler_metrics(dev):
         out["logreg_%s" % prec] = {"iters_per_s": round(k / (ms / 1e3), 2),
                                    "ms_per_iter": round(ms / k, 3)}
         del S
+    out["batch256"] = batch_metrics(dev, timed_steps)
     return out
+
+
+def batch_metrics(dev, timed_steps):
+    """256 Gaussian samplers (N log-uniform 2^8..2^16, d 1..64, Wishart
+    covariances, ESS-triggered resampling): one batched step per iteration
+    (graph replay) against per-sampler launch sequences, eager and graphed.
+    Rates are sampler-iterations per second."""
+    import torch
+    from paper_1905_10252_amd import inputs as I
+    from paper_1905_10252_amd import smc
+    specs = I.batch_specs()
+    ns = len(specs)
+
+    def make(group, graph):
+        b = smc.Batch(len(group), graph=graph, device=dev)
+        for k, sp in enumerate(group):
+            b.attach(k, sp["n"], sp["d"], sp["mean"], sp["chol"], seed=sp["seed"],
+                     sampler_id=sp["sampler_id"], rw_sd=sp["rw_sd"], init_sd=sp["init_sd"])
+        return b
+
+    res = {"samplers": ns, "particles": int(sum(sp["n"] for sp in specs)),
+           "mean_d": round(sum(sp["d"] for sp in specs) / ns, 2)}
+    b = make(specs, True)
+    timed_steps(b, 4)  # the third eager step captures the graph
+    k = 20
+    ms, per = timed_steps(b, k)
+    res.update({"sampler_iters_per_s": round(k * ns / (ms / 1e3), 1),
+                "ms_per_step": round(ms / k, 4), "p50_ms": round(pctl(per, 50), 4),
+                "p99_ms": round(pctl(per, 99), 4)})
+    del b
+    torch.cuda.synchronize()
+    for name, graph in (("per_sampler_eager", False), ("per_sampler_graph", True)):
+        bs = [make([sp], graph) for sp in specs]
+        for _ in range(4):
+            for one in bs:
+                one.step(info=False, est=False)
+        torch.cuda.synchronize()
+        rounds = 5
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(rounds):
+            for one in bs:
+                one.step(info=False, est=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        res[name] = {"sampler_iters_per_s": round(rounds * ns / (ms / 1e3), 1),
+                     "ms_per_round": round(ms / rounds, 3)}
+        del bs
+        torch.cuda.synchronize()
+    res["speedup_vs_eager"] = round(res["sampler_iters_per_s"]
+                                    / res["per_sampler_eager"]["sampler_iters_per_s"], 2)
+    return res
 
 
 def main():

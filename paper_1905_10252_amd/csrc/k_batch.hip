@@ -5,21 +5,23 @@
 // recycling by eq. normconst and eq. recycling) on a Gaussian target with
 // precision U^T U.  One step is one sequence of launches for all samplers:
 //
-//   k_bis<DB>   per tile of 4096 particles of samplers whose dimension falls
+//   k_bis<DB>   per chunk of 256 particles of samplers whose dimension falls
 //               in the bucket (DB - 8, DB]: proposal, |U (x - mean)|^2 with U
-//               staged in LDS and the row in registers, weight update, tile
-//               max key.  One launch per bucket.
-//   k_bscan     per tile of every sampler: the sampler's max from its tile
-//               keys, 64-bit fixed-point weights, FP64 sums, the exact sum of
-//               squares, and the inclusive prefix by a decoupled lookback
-//               that stays inside the sampler's own tiles (segmented scan);
-//               also the tile's estimate sums sum e x_k, sum e x_k^2.
+//               staged in LDS and the row in registers, weight update, chunk
+//               max key and estimate sums against the chunk's max.  One launch
+//               per bucket.
+//   k_bscan     per tile of 4096 particles of every sampler: the sampler's max
+//               from its chunk keys, 64-bit fixed-point weights, FP64 sums,
+//               the exact sum of squares, and the inclusive prefix by a
+//               decoupled lookback that stays inside the sampler's own tiles
+//               (segmented scan); the tile's chunk estimate sums rescaled to
+//               the sampler's max.
 //   k_bdecide   one workgroup per sampler: tile partials in a fixed order,
 //               integer decision, offset, log Z, ESS, estimates, c_t,
 //               recycling, the sampler's info record.
 //   k_bexpand   per 256 outputs of resampling samplers: ancestor by binary
 //               search on the prefix, rows copied by whole wavefronts.
-//   k_bcopyback per tile of resampling samplers: rows and cached log-target
+//   k_bcopyback per chunk of resampling samplers: rows and cached log-target
 //               back in place, weights reset.
 //
 // Tiles never straddle samplers, a tile waits only on earlier tiles of its own
@@ -44,13 +46,12 @@ namespace {
 constexpr int kBT = 256;               // threads per workgroup
 constexpr int kBItems = 16;            // particles per thread and tile
 constexpr int kBTile = kBT * kBItems;  // particles per tile
-constexpr int kBChunk = 256;           // expand outputs per workgroup
+constexpr int kBChunk = 256;           // particles of an update / expand / copy workgroup
+constexpr int kChunksPerTile = kBTile / kBChunk;
 constexpr int kBSpin = 1 << 22;        // lookback poll bound
 constexpr int kBuckets = 8;            // dimension buckets (8b, 8b + 8]
 constexpr int kBMaxCap = 4096;
 constexpr int64_t kBMaxN = 1ll << 28;
-
-__host__ __device__ constexpr int bpad(int i) { return i + (i >> 4); }
 
 // Per-sampler control block (in the sampler's workspace).
 struct BCtrl {
@@ -62,11 +63,10 @@ struct BCtrl {
     unsigned err_call, err_latch, spin_fail, bad, rec_steps, pad;
 };
 
-// Per-tile output of the update kernel.
+// Per-chunk max key and non-finite flag of the update kernel.
 struct BTileIS {
     u64 key;
     unsigned bad, pad;
-    double m, E;  // initialisation: tile reference and sum exp(l - m)
 };
 
 // Device descriptor of one slot (n == 0: free).
@@ -79,7 +79,7 @@ struct BSlot {
     const double *mean, *chol;
     double *x, *logw;
     BCtrl *ctrl;
-    double *lp, *x_scr, *lp_scr, *epart, *rec_num;
+    double *lp, *x_scr, *lp_scr, *epart, *cpart, *rec_num;
     u64 *pref, *status;
     TilePart *tpart;
     BTileIS *tis;
@@ -91,7 +91,7 @@ struct BTabs {
     int *tile_pref;   // [cap + 1] tile prefix over act
     int *chunk_pref;  // [cap + 1] expand-chunk prefix over act
     int *bact;        // [kBuckets][cap]
-    int *btile_pref;  // [kBuckets][cap + 1]
+    int *btile_pref;  // [kBuckets][cap + 1] chunk prefix over bact
 };
 
 // Position of block b in a prefix table: slot and index within the slot.
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, BT
         v[1] += slots[s].ntile;
         v[2] += slots[s].nchunk;
         v[3 + b] += 1;
-        v[3 + kBuckets + b] += slots[s].ntile;
+        v[3 + kBuckets + b] += slots[s].nchunk;
     }
     for (int q = 0; q < NV; ++q) s_v[q][tid] = v[q];
     __syncthreads();
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, BT
         off[1] += slots[s].ntile;
         off[2] += slots[s].nchunk;
         off[3 + b] += 1;
-        off[3 + kBuckets + b] += slots[s].ntile;
+        off[3 + kBuckets + b] += slots[s].nchunk;
     }
     if (tid == 255) {
         const int na = s_v[0][255];
@@ -178,25 +178,28 @@ __global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, BT
 }
 
 // ---------------------------------------------------- proposal + weights
-// single >= 0: every block is a tile of that slot (initialisation);
-// otherwise blocks map to the tiles of the bucket's samplers.
+// One workgroup per chunk of 256 particles (one per thread).  single >= 0:
+// every block is a chunk of that slot (initialisation); otherwise blocks map to
+// the chunks of the bucket's samplers.  Besides the update it leaves the
+// chunk's max key, non-finite flag and estimate sums against the chunk's own
+// max m_b: [m_b, sum e, sum e x_k, sum e x_k^2], e = exp(l - m_b).
 template <int DB, bool kInit>
 __global__ __launch_bounds__(256) void k_bis(const BSlot *slots, const int *n_act,
-                                             const int *bact, const int *btile_pref, int bucket,
+                                             const int *bact, const int *bchunk_pref, int bucket,
                                              int cap, int single)
 {
     __shared__ double sU[DB * DB];
     __shared__ double sM[DB];
     __shared__ u64 s_key[4];
     __shared__ unsigned s_bad[4];
-    __shared__ double s_m[4], s_e[4];
+    __shared__ double s_col[4][1 + 2 * DB];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    int slot, tile;
+    int slot, chunk;
     if (single >= 0) {
         slot = single;
-        tile = blockIdx.x;
-    } else if (!locate(btile_pref + bucket * (cap + 1), bact + bucket * cap, n_act[1 + bucket],
-                       blockIdx.x, slot, tile)) {
+        chunk = blockIdx.x;
+    } else if (!locate(bchunk_pref + bucket * (cap + 1), bact + bucket * cap, n_act[1 + bucket],
+                       blockIdx.x, slot, chunk)) {
         return;
     }
     const BSlot &S = slots[slot];
@@ -209,28 +212,37 @@ __global__ __launch_bounds__(256) void k_bis(const BSlot *slots, const int *n_ac
         sU[e] = (r < d && k < d && k >= r) ? S.chol[r * d + k] : 0.0;
     }
     for (int e = tid; e < DB; e += 256) sM[e] = e < d ? S.mean[e] : 0.0;
-    if (tid == 0) S.status[tile] = 0;  // lookback word of this step's scan
+    if (tid == 0 && (chunk % kChunksPerTile) == 0) S.status[chunk / kChunksPerTile] = 0;
     __syncthreads();
     const uint32_t t = kInit ? 0u : S.ctrl->t;
     const uint32_t tag = kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose;
-    u64 key = 0;
-    unsigned bad = 0;
-    double om = -__builtin_huge_val(), oe = 0.0;  // initialisation: running reference and sum
-    const i64 base = (i64)tile * kBTile;
-    for (int it = 0; it < kBItems; ++it) {
-        const i64 i = base + it * 256 + tid;
-        const bool act = i < n;
-        double *xi = S.x + i * d;
-        double acc0 = 0.0;
-        for (int k2 = 0; 2 * k2 < d; ++k2) {
-            double z[2];
-            normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)i, (uint32_t)k2, act, z[0],
-                             z[1]);
-            if (!act) continue;
+    const i64 i = (i64)chunk * kBChunk + tid;
+    const bool act = i < n;
+    double *xi = S.x + i * d;
+    double acc0 = 0.0;
+    // the current coordinates are loaded two pairs ahead of their use, so the
+    // strided loads overlap the normal generation
+    const bool ld = !kInit && act;
+    double p0 = 0.0, p1 = 0.0, q0 = 0.0, q1 = 0.0;
+    if (ld) {
+        p0 = xi[0];
+        if (d > 1) p1 = xi[1];
+        if (d > 2) q0 = xi[2];
+        if (d > 3) q1 = xi[3];
+    }
+    for (int k2 = 0; 2 * k2 < d; ++k2) {
+        const int kn = 2 * k2 + 4;
+        double r0 = 0.0, r1 = 0.0;
+        if (ld && kn < d) r0 = xi[kn];
+        if (ld && kn + 1 < d) r1 = xi[kn + 1];
+        double z[2];
+        normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)i, (uint32_t)k2, act, z[0], z[1]);
+        if (act) {
             for (int h = 0; h < 2; ++h) {
                 const int kk = 2 * k2 + h;
                 if (kk >= d) break;
-                const double xk = kInit ? S.init_mean + S.init_sd * z[h] : xi[kk] + S.rw_sd * z[h];
+                const double xk =
+                    kInit ? S.init_mean + S.init_sd * z[h] : (h ? p1 : p0) + S.rw_sd * z[h];
                 xi[kk] = xk;
                 if (kInit) {
                     const double t0 = xk - S.init_mean;
@@ -238,97 +250,99 @@ __global__ __launch_bounds__(256) void k_bis(const BSlot *slots, const int *n_ac
                 }
             }
         }
-        if (!act) continue;
-        // An opaque zero offset keeps the LDS reads of U inside this loop:
-        // hoisted, they would hold DB^2 / 2 values in registers.
-        int zo = 0;
-        asm volatile("" : "+v"(zo));
-        const double *u = sU + zo;
-        const double *mu = sM + zo;
-        double tv[DB];
+        p0 = q0;
+        p1 = q1;
+        q0 = r0;
+        q1 = r1;
+    }
+    double lw = -__builtin_huge_val();
+    double tv[DB];
 #pragma unroll
-        for (int k = 0; k < DB; ++k) tv[k] = k < d ? xi[k] - mu[k] : 0.0;
+    for (int k = 0; k < DB; ++k) tv[k] = (act && k < d) ? xi[k] - sM[k] : 0.0;
+    if (act) {
         double acc = 0.0;
 #pragma unroll
         for (int r = 0; r < DB; ++r) {
-            double s = 0.0;
+            double sr = 0.0;
 #pragma unroll
-            for (int k = r; k < DB; ++k) s = s + u[r * DB + k] * tv[k];
-            acc = acc + s * s;
+            for (int k = r; k < DB; ++k) sr = sr + sU[r * DB + k] * tv[k];
+            acc = acc + sr * sr;
         }
         const double lpn = S.log_norm - 0.5 * acc;
-        const double lw = kInit ? lpn - (S.init_log_norm - 0.5 * acc0) : S.logw[i] + (lpn - S.lp[i]);
+        lw = kInit ? lpn - (S.init_log_norm - 0.5 * acc0) : S.logw[i] + (lpn - S.lp[i]);
         S.lp[i] = lpn;
         S.logw[i] = lw;
-        bad |= (lw != lw) | (lw == __builtin_huge_val());
-        const u64 kk = okey(lw);
-        key = kk > key ? kk : key;
-        if (kInit && lw > -__builtin_huge_val()) {
-            if (lw > om) {
-                if (om > -__builtin_huge_val()) oe *= det_exp(om - lw);
-                om = lw;
-            }
-            oe += det_exp(lw - om);
-        }
     }
-    key = wave_max_u64(key);
-    bad = wave_or(bad);
-    double mw = 0.0, ew = 0.0;
-    if (kInit) {
-        mw = wave_max_f64(om);
-        ew = wave_sum_f64(om > -__builtin_huge_val() ? oe * det_exp(om - mw) : 0.0);
-    }
+    const unsigned bad = wave_or((lw != lw) | (lw == __builtin_huge_val()));
+    const u64 key = wave_max_u64(act ? okey(lw) : 0ull);
     if (lane == 0) {
         s_key[wid] = key;
         s_bad[wid] = bad;
-        s_m[wid] = mw;
-        s_e[wid] = ew;
     }
     __syncthreads();
+    u64 bk = s_key[0];
+    unsigned bb = s_bad[0];
+    for (int w = 1; w < 4; ++w) {
+        bk = s_key[w] > bk ? s_key[w] : bk;
+        bb |= s_bad[w];
+    }
+    const double mb = okey_inv(bk);
+    const bool live = act && mb > -__builtin_huge_val();
+    const double e = live ? det_exp(lw - mb) : 0.0;
+    // column sums over the chunk: one wave sum per column, waves in order.
+    // The row is taken from the registers as (x - mean) + mean, within an ulp
+    // of x: these sums feed FP64 estimates, not the particle trajectories.
+    double se = wave_sum_f64(e);
+    if (lane == 0) s_col[wid][0] = se;
+#pragma unroll
+    for (int k = 0; k < DB; ++k) {
+        if (k < d) {
+            const double xk = act ? tv[k] + sM[k] : 0.0;
+            const double ex = e * xk;
+            const double s1 = wave_sum_f64(ex), s2 = wave_sum_f64(ex * xk);
+            if (lane == 0) {
+                s_col[wid][1 + k] = s1;
+                s_col[wid][1 + d + k] = s2;
+            }
+        }
+    }
+    __syncthreads();
+    double *cp = S.cpart + (i64)chunk * (2 + 2 * d);
+    for (int c = tid; c < 1 + 2 * d; c += 256)
+        cp[1 + c] = ((s_col[0][c] + s_col[1][c]) + s_col[2][c]) + s_col[3][c];
     if (tid == 0) {
+        cp[0] = mb;
         BTileIS o;
-        o.key = s_key[0];
-        o.bad = s_bad[0];
-        for (int w = 1; w < 4; ++w) {
-            o.key = s_key[w] > o.key ? s_key[w] : o.key;
-            o.bad |= s_bad[w];
-        }
+        o.key = bk;
+        o.bad = bb;
         o.pad = 0;
-        o.m = -__builtin_huge_val();
-        o.E = 0.0;
-        if (kInit) {
-            double mb = s_m[0];
-            for (int w = 1; w < 4; ++w) mb = fmax(mb, s_m[w]);
-            double E = 0.0;
-            for (int w = 0; w < 4; ++w)
-                E += s_m[w] > -__builtin_huge_val() ? s_e[w] * det_exp(s_m[w] - mb) : 0.0;
-            o.m = mb;
-            o.E = E;
-        }
-        S.tis[tile] = o;
+        S.tis[chunk] = o;
     }
 }
 
-// Initialisation statistics: log sum w_0 from the tile partials (fixed
+// Initialisation statistics: log sum w_0 from the chunk partials (fixed
 // order), error of the initial weights, cleared recycling sums.
 __global__ __launch_bounds__(64) void k_binit(const BSlot *slots, int slot)
 {
     const BSlot &S = slots[slot];
     BCtrl *c = S.ctrl;
     const int lane = threadIdx.x;
+    const int cw = 2 + 2 * S.d;
     for (int k = lane; k < 2 * S.d; k += 64) S.rec_num[k] = 0.0;
     if (lane != 0) return;
     u64 key = 0;
     unsigned bad = 0;
     double m = -__builtin_huge_val();
-    for (int k = 0; k < S.ntile; ++k) {
+    for (int k = 0; k < S.nchunk; ++k) {
         key = S.tis[k].key > key ? S.tis[k].key : key;
         bad |= S.tis[k].bad;
-        m = fmax(m, S.tis[k].m);
+        m = fmax(m, S.cpart[(i64)k * cw]);
     }
     double E = 0.0;
-    for (int k = 0; k < S.ntile; ++k)
-        if (S.tis[k].m > -__builtin_huge_val()) E += S.tis[k].E * det_exp(S.tis[k].m - m);
+    for (int k = 0; k < S.nchunk; ++k) {
+        const double mk = S.cpart[(i64)k * cw];
+        if (mk > -__builtin_huge_val()) E += S.cpart[(i64)k * cw + 1] * det_exp(mk - m);
+    }
     unsigned err = 0;
     if (bad) err = kErrNonfinite;
     else if (key <= okey(-__builtin_huge_val())) err = kErrDegenerate;
@@ -345,26 +359,25 @@ __global__ __launch_bounds__(64) void k_binit(const BSlot *slots, int slot)
 }
 
 // --------------------------------------------------------- segmented scan
+// One workgroup per tile of 4096 particles (16 consecutive per thread).
 __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_act,
                                                const int *act, const int *tile_pref)
 {
-    __shared__ double se[bpad(kBTile)];
     __shared__ u64 s_k[4], s_wsum[4], s_lo[4], s_hi[4];
     __shared__ unsigned s_b[4];
     __shared__ double s_z[4], s_z2[4];
     __shared__ u64 s_prefix;
-    __shared__ double s_col[4][2 * SMC_BATCH_DMAX];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     int slot, tile;
     if (!locate(tile_pref, act, n_act[0], blockIdx.x, slot, tile)) return;
     const BSlot &S = slots[slot];
     const i64 n = S.n;
-    const int d = S.d, K = S.K, ntile = S.ntile;
+    const int d = S.d, K = S.K, ntile = S.ntile, nchunk = S.nchunk;
 
-    // the sampler's max and non-finite flag from its tile keys
+    // the sampler's max and non-finite flag from its chunk keys
     u64 key = 0;
     unsigned bad = 0;
-    for (int k = tid; k < ntile; k += 256) {
+    for (int k = tid; k < nchunk; k += 256) {
         const u64 kk = S.tis[k].key;
         key = kk > key ? kk : key;
         bad |= S.tis[k].bad;
@@ -388,6 +401,19 @@ __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_
         S.ctrl->bad = bad;
     }
 
+    // estimate sums of the tile's chunks, rescaled to the sampler's max
+    const int cw = 2 + 2 * d;
+    const int c0 = tile * kChunksPerTile;
+    const int c1 = (c0 + kChunksPerTile < nchunk) ? c0 + kChunksPerTile : nchunk;
+    if (tid < 2 * d) {
+        double a = 0.0;
+        for (int c = c0; c < c1; ++c) {
+            const double mc = S.cpart[(i64)c * cw];
+            if (mc > -__builtin_huge_val()) a += det_exp(mc - m) * S.cpart[(i64)c * cw + 2 + tid];
+        }
+        S.epart[(i64)tile * 2 * d + tid] = a;
+    }
+
     // fixed-point weights of 16 consecutive particles, FP64 and exact sums
     const i64 base = (i64)tile * kBTile;
     const u64 top = 1ull << K;
@@ -399,7 +425,7 @@ __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_
     for (int j = 0; j < kBItems; ++j) {
         const i64 i = base + tid * kBItems + j;
         const double v = i < n ? S.logw[i] : -__builtin_huge_val();
-        double e = det_exp(v - m);
+        const double e = det_exp(v - m);
         u64 q = 0;
         if (e >= 0.0) {
             z += e;
@@ -407,10 +433,7 @@ __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_
             q = (u64)floor(ldexp(e, K));
             q = q > top ? top : q;
             q2 = add128(q2, mul64(q, q));
-        } else {
-            e = 0.0;
         }
-        se[bpad(tid * kBItems + j)] = e;
         run += q;
         loc[j] = run;
     }
@@ -486,41 +509,7 @@ __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_
         p.q2hi = t.hi;
         S.tpart[tile] = p;
     }
-
-    // estimate sums of the tile: lanes split into rows x columns (a column
-    // per lane, 64 / dp2 rows per wave step), reduced in a fixed order
-    int dp2 = 1;
-    while (dp2 < d) dp2 <<= 1;
-    const int R = 64 / dp2;
-    const int col = lane & (dp2 - 1), rsub = lane / dp2;
-    const i64 rem = n - base;
-    const int cnt = rem < kBTile ? (int)rem : kBTile;
-    double s1 = 0.0, s2 = 0.0;
-    if (col < d) {
-        for (int r = wid * R + rsub; r < cnt; r += 4 * R) {
-            const double e = se[bpad(r)];
-            if (e != 0.0) {
-                const double xv = S.x[(base + r) * d + col];
-                const double ex = e * xv;
-                s1 += ex;
-                s2 += ex * xv;
-            }
-        }
-    }
-    for (int o = dp2; o < 64; o <<= 1) {
-        s1 += __shfl_xor(s1, o, kWave);
-        s2 += __shfl_xor(s2, o, kWave);
-    }
-    if (lane < d) {
-        s_col[wid][lane] = s1;
-        s_col[wid][SMC_BATCH_DMAX + lane] = s2;
-    }
-    __syncthreads();
-    if (tid < 2 * d) {
-        const int cc = tid < d ? tid : SMC_BATCH_DMAX + (tid - d);
-        S.epart[(i64)tile * 2 * d + tid] =
-            ((s_col[0][cc] + s_col[1][cc]) + s_col[2][cc]) + s_col[3][cc];
-    }
+    (void)ntile;
 }
 
 // ------------------------------------------------------- per-sampler decide
@@ -694,20 +683,26 @@ __global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *
 }
 
 __global__ __launch_bounds__(256) void k_bcopyback(const BSlot *slots, const int *n_act,
-                                                   const int *act, const int *tile_pref)
+                                                   const int *act, const int *chunk_pref)
 {
     int slot, tile;
-    if (!locate(tile_pref, act, n_act[0], blockIdx.x, slot, tile)) return;
+    if (!locate(chunk_pref, act, n_act[0], blockIdx.x, slot, tile)) return;
     const BSlot &S = slots[slot];
     const BCtrl *c = S.ctrl;
     if (!c->resample || c->err_call) return;
     const i64 n = S.n;
     const int d = S.d;
-    const i64 base = (i64)tile * kBTile;
-    const i64 cnt = (n - base) < kBTile ? (n - base) : kBTile;
-    const i64 e0 = base * d, e1 = (base + cnt) * d;
-    for (i64 e = e0 + threadIdx.x; e < e1; e += 256) S.x[e] = S.x_scr[e];
-    for (i64 i = base + threadIdx.x; i < base + cnt; i += 256) {
+    const i64 base = (i64)tile * kBChunk;
+    const i64 cnt = (n - base) < kBChunk ? (n - base) : kBChunk;
+    // rows [base, base + cnt) are one contiguous run of cnt * d doubles; base
+    // is even, so the run starts 16-byte aligned
+    const i64 e0 = base * d, ne = cnt * d;
+    const double2 *src2 = reinterpret_cast<const double2 *>(S.x_scr + e0);
+    double2 *dst2 = reinterpret_cast<double2 *>(S.x + e0);
+    for (i64 e = threadIdx.x; e < ne / 2; e += 256) dst2[e] = src2[e];
+    if ((ne & 1) && threadIdx.x == 0) S.x[e0 + ne - 1] = S.x_scr[e0 + ne - 1];
+    const i64 i = base + threadIdx.x;
+    if (i < base + cnt) {
         S.lp[i] = S.lp_scr[i];
         S.logw[i] = S.reset;
     }
@@ -715,7 +710,7 @@ __global__ __launch_bounds__(256) void k_bcopyback(const BSlot *slots, const int
 
 // ------------------------------------------------------------------- host
 struct SamplerLayout {
-    size_t ctrl, lp, x_scr, lp_scr, pref, status, tpart, tis, epart, rec_num, total;
+    size_t ctrl, lp, x_scr, lp_scr, pref, status, tpart, tis, epart, cpart, rec_num, total;
 };
 
 inline int64_t ntile_of(int64_t n) { return (n + kBTile - 1) / kBTile; }
@@ -738,8 +733,9 @@ SamplerLayout sampler_layout(int64_t n, int d)
     L.pref = take(8 * (size_t)n);
     L.status = take(8 * nt);
     L.tpart = take(sizeof(TilePart) * nt);
-    L.tis = take(sizeof(BTileIS) * nt);
+    L.tis = take(sizeof(BTileIS) * (size_t)nchunk_of(n));
     L.epart = take(8 * 2 * (size_t)d * nt);
+    L.cpart = take(8 * (2 + 2 * (size_t)d) * (size_t)nchunk_of(n));
     L.rec_num = take(8 * 2 * (size_t)d);
     L.total = off;
     return L;
@@ -822,7 +818,7 @@ void mirror_update(smc_batch *b)
         b->n_act += 1;
         b->total_tiles += v.ntile;
         b->total_chunks += v.nchunk;
-        b->btiles[v.bucket] += v.ntile;
+        b->btiles[v.bucket] += v.nchunk;
     }
     b->version += 1;
     b->eager_same = 0;
@@ -864,8 +860,8 @@ hipError_t enqueue_step(smc_batch *b, smc_resample_info *info, double *est, hipS
     hipLaunchKernelGGL(k_bdecide, dim3(b->n_act), dim3(256), 0, s, sl, t.n_act, t.act, info, est);
     hipLaunchKernelGGL(k_bexpand, dim3(b->total_chunks), dim3(256), 0, s, sl, t.n_act, t.act,
                        t.chunk_pref);
-    hipLaunchKernelGGL(k_bcopyback, dim3(b->total_tiles), dim3(256), 0, s, sl, t.n_act, t.act,
-                       t.tile_pref);
+    hipLaunchKernelGGL(k_bcopyback, dim3(b->total_chunks), dim3(256), 0, s, sl, t.n_act, t.act,
+                       t.chunk_pref);
     return hipGetLastError();
 }
 
@@ -983,6 +979,7 @@ smc_status smc_batch_attach(smc_batch *b, int32_t slot, const smc_batch_sampler 
     v.x_scr = reinterpret_cast<double *>(w + L.x_scr);
     v.lp_scr = reinterpret_cast<double *>(w + L.lp_scr);
     v.epart = reinterpret_cast<double *>(w + L.epart);
+    v.cpart = reinterpret_cast<double *>(w + L.cpart);
     v.rec_num = reinterpret_cast<double *>(w + L.rec_num);
     v.pref = reinterpret_cast<u64 *>(w + L.pref);
     v.status = reinterpret_cast<u64 *>(w + L.status);
@@ -990,7 +987,7 @@ smc_status smc_batch_attach(smc_batch *b, int32_t slot, const smc_batch_sampler 
     v.tis = reinterpret_cast<BTileIS *>(w + L.tis);
     const hipStream_t s = HS(stream);
     hipLaunchKernelGGL(k_bslot_set, dim3(1), dim3(1), 0, s, v, b->d_slots + slot);
-    launch_bis_bucket<true>(v.bucket, dim3(v.ntile), s, b, slot);
+    launch_bis_bucket<true>(v.bucket, dim3(v.nchunk), s, b, slot);
     hipLaunchKernelGGL(k_binit, dim3(1), dim3(64), 0, s, (const BSlot *)b->d_slots, slot);
     if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     b->h_slots[slot] = v;
