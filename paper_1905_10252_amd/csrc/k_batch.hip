@@ -5,11 +5,12 @@
 // recycling by eq. normconst and eq. recycling) on a Gaussian target with
 // precision U^T U.  One step is one sequence of launches for all samplers:
 //
-//   k_bis<DB>   per chunk of 256 particles of samplers whose dimension falls
-//               in the bucket (DB - 8, DB]: proposal, |U (x - mean)|^2 with U
-//               staged in LDS and the row in registers, weight update, chunk
-//               max key and estimate sums against the chunk's max.  One launch
-//               per bucket.
+//   k_bprop     per chunk of 256 particles of every sampler: the random-walk
+//               proposal in place (normals generated wave-cooperatively).
+//   k_bquad<DB> per chunk of samplers whose dimension falls in the bucket
+//               (DB - 8, DB]: |U (x - mean)|^2 with U staged in LDS and the row
+//               in registers, weight update, chunk max key and estimate sums
+//               against the chunk's max.  One launch per bucket.
 //   k_bscan     per tile of 4096 particles of every sampler: the sampler's max
 //               from its chunk keys, 64-bit fixed-point weights, FP64 sums,
 //               the exact sum of squares, and the inclusive prefix by a
@@ -53,6 +54,17 @@ constexpr int kBuckets = 8;            // dimension buckets (8b, 8b + 8]
 constexpr int kBMaxCap = 4096;
 constexpr int64_t kBMaxN = 1ll << 28;
 
+// The per-sampler arrays are reached through pointers read from the slot
+// table, which the compiler would address as generic (flat) memory; flat
+// accesses also count against the LDS wait counter, so every wave shuffle
+// would drain them.  These casts keep them on the global path.
+#define GLB(T) __attribute__((address_space(1))) T
+template <class T>
+__device__ inline GLB(T) *glb(T *p)
+{
+    return (GLB(T) *)p;
+}
+
 // Per-sampler control block (in the sampler's workspace).
 struct BCtrl {
     u64 S, U, Q2lo, Q2hi, mkey;
@@ -90,6 +102,7 @@ struct BTabs {
     int *act;         // [cap] attached slots, ascending
     int *tile_pref;   // [cap + 1] tile prefix over act
     int *chunk_pref;  // [cap + 1] expand-chunk prefix over act
+    int *unit_pref;   // [cap + 1] proposal-unit prefix over act (chunk x pair group)
     int *bact;        // [kBuckets][cap]
     int *btile_pref;  // [kBuckets][cap + 1] chunk prefix over bact
 };
@@ -121,9 +134,14 @@ __global__ void k_bslots_clear(BSlot *slots, int cap)
 
 // Tables of the attached slots in slot order; thread t owns a contiguous
 // range of slots, counts are combined by a block scan.
-__global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, BTabs tb)
+__device__ __host__ inline int units_of(int nchunk, int d, int G)
 {
-    constexpr int NV = 3 + 2 * kBuckets;  // act, tiles, chunks, bucket counts, bucket tiles
+    return nchunk * (((d + 1) / 2 + G - 1) / G);
+}
+
+__global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, int G, BTabs tb)
+{
+    constexpr int NV = 4 + 2 * kBuckets;  // act, tiles, chunks, bucket counts, bucket chunks, units
     __shared__ int s_v[NV][256];
     const int tid = threadIdx.x;
     const int per = (cap + 255) / 256;
@@ -138,6 +156,7 @@ __global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, BT
         v[2] += slots[s].nchunk;
         v[3 + b] += 1;
         v[3 + kBuckets + b] += slots[s].nchunk;
+        v[3 + 2 * kBuckets] += units_of(slots[s].nchunk, slots[s].d, G);
     }
     for (int q = 0; q < NV; ++q) s_v[q][tid] = v[q];
     __syncthreads();
@@ -156,6 +175,7 @@ __global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, BT
         tb.act[off[0]] = s;
         tb.tile_pref[off[0]] = off[1];
         tb.chunk_pref[off[0]] = off[2];
+        tb.unit_pref[off[0]] = off[3 + 2 * kBuckets];
         tb.bact[b * cap + off[3 + b]] = s;
         tb.btile_pref[b * (cap + 1) + off[3 + b]] = off[3 + kBuckets + b];
         off[0] += 1;
@@ -163,12 +183,14 @@ __global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, BT
         off[2] += slots[s].nchunk;
         off[3 + b] += 1;
         off[3 + kBuckets + b] += slots[s].nchunk;
+        off[3 + 2 * kBuckets] += units_of(slots[s].nchunk, slots[s].d, G);
     }
     if (tid == 255) {
         const int na = s_v[0][255];
         tb.n_act[0] = na;
         tb.tile_pref[na] = s_v[1][255];
         tb.chunk_pref[na] = s_v[2][255];
+        tb.unit_pref[na] = s_v[3 + 2 * kBuckets][255];
         for (int b = 0; b < kBuckets; ++b) {
             const int nb = s_v[3 + b][255];
             tb.n_act[1 + b] = nb;
@@ -177,16 +199,93 @@ __global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, BT
     }
 }
 
-// ---------------------------------------------------- proposal + weights
-// One workgroup per chunk of 256 particles (one per thread).  single >= 0:
-// every block is a chunk of that slot (initialisation); otherwise blocks map to
-// the chunks of the bucket's samplers.  Besides the update it leaves the
-// chunk's max key, non-finite flag and estimate sums against the chunk's own
-// max m_b: [m_b, sum e, sum e x_k, sum e x_k^2], e = exp(l - m_b).
+// ---------------------------------------------------------------- proposal
+// One workgroup per chunk of 256 particles (one per thread), every sampler in
+// one launch (single >= 0: the chunks of that slot only).  Draws the proposal
+// (or x0 ~ q0) in place; at initialisation also leaves the quadratic term of
+// log q0 in lp_scr.  Kept apart from the target so that its register use, and
+// with it the occupancy of the normal generation, does not depend on d.
+template <bool kInit>
+__global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_act,
+                                               const int *act_list, const int *unit_pref, int G,
+                                               int single)
+{
+    const int tid = threadIdx.x;
+    int slot, unit;
+    if (single >= 0) {
+        slot = single;
+        unit = blockIdx.x;
+    } else if (!locate(unit_pref, act_list, n_act[0], blockIdx.x, slot, unit)) {
+        return;
+    }
+    // a local copy: stores through the sampler's arrays cannot alias it
+    const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
+    const i64 n = S.n;
+    const int d = S.d;
+    // a unit is one chunk of 256 particles and a group of G coordinate pairs
+    // (all pairs at initialisation, where log q0 sums over the whole row)
+    const int npair = (d + 1) / 2;
+    const int ng = kInit ? 1 : (npair + G - 1) / G;
+    const int chunk = unit / ng, grp = unit - chunk * ng;
+    const int kp0 = kInit ? 0 : grp * G;
+    const int kp1 = kInit ? npair : (kp0 + G < npair ? kp0 + G : npair);
+    if (tid == 0 && grp == 0 && (chunk % kChunksPerTile) == 0) S.status[chunk / kChunksPerTile] = 0;
+    const uint32_t t = kInit ? 0u : S.ctrl->t;
+    const uint32_t tag = kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose;
+    const i64 i = (i64)chunk * kBChunk + tid;
+    const bool act = i < n;
+    GLB(double) *xi = glb(S.x) + i * d;
+    double acc0 = 0.0;
+    // The pair's current coordinates are loaded before its normals are drawn,
+    // so the strided loads overlap the normal generation.  Its new values are
+    // stored at the top of the next iteration, after that iteration's loads:
+    // a load into a register that an outstanding store still reads must wait
+    // for the store, and a store a whole pair old has long completed.
+    const bool ld = !kInit && act;
+    double w0 = 0.0, w1 = 0.0;  // values of the previous pair, not yet stored
+    int wk = -1;
+    for (int k2 = kp0; k2 < kp1; ++k2) {
+        const int k0 = 2 * k2;
+        double c0 = 0.0, c1 = 0.0;
+        if (ld) c0 = xi[k0];
+        if (ld && k0 + 1 < d) c1 = xi[k0 + 1];
+        if (act && wk >= 0) {
+            xi[wk] = w0;
+            xi[wk + 1] = w1;  // wk + 1 < d: the previous pair was complete
+        }
+        double z[2];
+        normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)i, (uint32_t)k2, act, z[0], z[1]);
+        if (act) {
+            w0 = kInit ? S.init_mean + S.init_sd * z[0] : c0 + S.rw_sd * z[0];
+            w1 = kInit ? S.init_mean + S.init_sd * z[1] : c1 + S.rw_sd * z[1];
+            if (kInit) {
+                const double t0 = w0 - S.init_mean;
+                acc0 = acc0 + (t0 * t0) * S.init_prec;
+                if (k0 + 1 < d) {
+                    const double t1 = w1 - S.init_mean;
+                    acc0 = acc0 + (t1 * t1) * S.init_prec;
+                }
+            }
+            wk = k0;
+        }
+    }
+    if (act && wk >= 0) {
+        xi[wk] = w0;
+        if (wk + 1 < d) xi[wk + 1] = w1;
+    }
+    if (kInit && act) glb(S.lp_scr)[i] = acc0;
+}
+
+// ------------------------------------------------------ target + weights
+// One workgroup per chunk of samplers whose dimension falls in the bucket
+// (DB - 8, DB] (single >= 0: the chunks of that slot): |U (x - mean)|^2 with U
+// staged in LDS and the row in registers, the weight update, the chunk's max
+// key, non-finite flag and estimate sums against the chunk's own max m_b:
+// [m_b, sum e, sum e x_k, sum e x_k^2], e = exp(l - m_b).
 template <int DB, bool kInit>
-__global__ __launch_bounds__(256) void k_bis(const BSlot *slots, const int *n_act,
-                                             const int *bact, const int *bchunk_pref, int bucket,
-                                             int cap, int single)
+__global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_act,
+                                               const int *bact, const int *bchunk_pref,
+                                               int bucket, int cap, int single)
 {
     __shared__ double sU[DB * DB];
     __shared__ double sM[DB];
@@ -202,7 +301,8 @@ __global__ __launch_bounds__(256) void k_bis(const BSlot *slots, const int *n_ac
                        blockIdx.x, slot, chunk)) {
         return;
     }
-    const BSlot &S = slots[slot];
+    // a local copy: stores through the sampler's arrays cannot alias it
+    const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
     const i64 n = S.n;
     const int d = S.d;
     // U zero-padded to DB x DB (lower triangle and beyond d are zero), so the
@@ -212,49 +312,12 @@ __global__ __launch_bounds__(256) void k_bis(const BSlot *slots, const int *n_ac
         sU[e] = (r < d && k < d && k >= r) ? S.chol[r * d + k] : 0.0;
     }
     for (int e = tid; e < DB; e += 256) sM[e] = e < d ? S.mean[e] : 0.0;
-    if (tid == 0 && (chunk % kChunksPerTile) == 0) S.status[chunk / kChunksPerTile] = 0;
     __syncthreads();
-    const uint32_t t = kInit ? 0u : S.ctrl->t;
-    const uint32_t tag = kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose;
     const i64 i = (i64)chunk * kBChunk + tid;
     const bool act = i < n;
-    double *xi = S.x + i * d;
-    double acc0 = 0.0;
-    // the current coordinates are loaded two pairs ahead of their use, so the
-    // strided loads overlap the normal generation
-    const bool ld = !kInit && act;
-    double p0 = 0.0, p1 = 0.0, q0 = 0.0, q1 = 0.0;
-    if (ld) {
-        p0 = xi[0];
-        if (d > 1) p1 = xi[1];
-        if (d > 2) q0 = xi[2];
-        if (d > 3) q1 = xi[3];
-    }
-    for (int k2 = 0; 2 * k2 < d; ++k2) {
-        const int kn = 2 * k2 + 4;
-        double r0 = 0.0, r1 = 0.0;
-        if (ld && kn < d) r0 = xi[kn];
-        if (ld && kn + 1 < d) r1 = xi[kn + 1];
-        double z[2];
-        normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)i, (uint32_t)k2, act, z[0], z[1]);
-        if (act) {
-            for (int h = 0; h < 2; ++h) {
-                const int kk = 2 * k2 + h;
-                if (kk >= d) break;
-                const double xk =
-                    kInit ? S.init_mean + S.init_sd * z[h] : (h ? p1 : p0) + S.rw_sd * z[h];
-                xi[kk] = xk;
-                if (kInit) {
-                    const double t0 = xk - S.init_mean;
-                    acc0 = acc0 + (t0 * t0) * S.init_prec;
-                }
-            }
-        }
-        p0 = q0;
-        p1 = q1;
-        q0 = r0;
-        q1 = r1;
-    }
+    const GLB(double) *xi = glb(S.x) + i * d;
+    GLB(double) *lpg = glb(S.lp);
+    GLB(double) *lwg = glb(S.logw);
     double lw = -__builtin_huge_val();
     double tv[DB];
 #pragma unroll
@@ -269,9 +332,9 @@ __global__ __launch_bounds__(256) void k_bis(const BSlot *slots, const int *n_ac
             acc = acc + sr * sr;
         }
         const double lpn = S.log_norm - 0.5 * acc;
-        lw = kInit ? lpn - (S.init_log_norm - 0.5 * acc0) : S.logw[i] + (lpn - S.lp[i]);
-        S.lp[i] = lpn;
-        S.logw[i] = lw;
+        lw = kInit ? lpn - (S.init_log_norm - 0.5 * glb(S.lp_scr)[i]) : lwg[i] + (lpn - lpg[i]);
+        lpg[i] = lpn;
+        lwg[i] = lw;
     }
     const unsigned bad = wave_or((lw != lw) | (lw == __builtin_huge_val()));
     const u64 key = wave_max_u64(act ? okey(lw) : 0ull);
@@ -324,7 +387,8 @@ __global__ __launch_bounds__(256) void k_bis(const BSlot *slots, const int *n_ac
 // order), error of the initial weights, cleared recycling sums.
 __global__ __launch_bounds__(64) void k_binit(const BSlot *slots, int slot)
 {
-    const BSlot &S = slots[slot];
+    // a local copy: stores through the sampler's arrays cannot alias it
+    const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
     BCtrl *c = S.ctrl;
     const int lane = threadIdx.x;
     const int cw = 2 + 2 * S.d;
@@ -370,7 +434,8 @@ __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     int slot, tile;
     if (!locate(tile_pref, act, n_act[0], blockIdx.x, slot, tile)) return;
-    const BSlot &S = slots[slot];
+    // a local copy: stores through the sampler's arrays cannot alias it
+    const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
     const i64 n = S.n;
     const int d = S.d, K = S.K, ntile = S.ntile, nchunk = S.nchunk;
 
@@ -424,7 +489,7 @@ __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_
 #pragma unroll
     for (int j = 0; j < kBItems; ++j) {
         const i64 i = base + tid * kBItems + j;
-        const double v = i < n ? S.logw[i] : -__builtin_huge_val();
+        const double v = i < n ? glb(S.logw)[i] : -__builtin_huge_val();
         const double e = det_exp(v - m);
         u64 q = 0;
         if (e >= 0.0) {
@@ -497,7 +562,7 @@ __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_
 #pragma unroll
     for (int j = 0; j < kBItems; ++j) {
         const i64 i = base + tid * kBItems + j;
-        if (i < n) S.pref[i] = pre + loc[j];
+        if (i < n) glb(S.pref)[i] = pre + loc[j];
     }
     if (tid == 0) {
         TilePart p;
@@ -524,7 +589,8 @@ __global__ __launch_bounds__(256) void k_bdecide(const BSlot *slots, const int *
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if ((int)blockIdx.x >= n_act[0]) return;
     const int slot = act[blockIdx.x];
-    const BSlot &S = slots[slot];
+    // a local copy: stores through the sampler's arrays cannot alias it
+    const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
     BCtrl *c = S.ctrl;
     const int d = S.d, ntile = S.ntile;
     const i64 n = S.n;
@@ -648,7 +714,8 @@ __global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     int slot, ch;
     if (!locate(chunk_pref, act, n_act[0], blockIdx.x, slot, ch)) return;
-    const BSlot &S = slots[slot];
+    // a local copy: stores through the sampler's arrays cannot alias it
+    const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
     const BCtrl *c = S.ctrl;
     if (!c->resample || c->err_call) return;
     const i64 n = S.n;
@@ -659,12 +726,13 @@ __global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *
     i64 lo = 0, hi = n - 1;
     if (p < n) {
         const U128 rhs = mul64((u64)(p + 1), Ssum);
+        const GLB(u64) *pg = glb(S.pref);
         while (lo < hi) {
             const i64 mid = (lo + hi) >> 1;
-            if (lt128(add128(mul64((u64)n, S.pref[mid]), U), rhs)) lo = mid + 1;
+            if (lt128(add128(mul64((u64)n, pg[mid]), U), rhs)) lo = mid + 1;
             else hi = mid;
         }
-        S.lp_scr[p] = S.lp[lo];
+        glb(S.lp_scr)[p] = glb(S.lp)[lo];
     }
     const i64 anc = lo;
     int dp2 = 1;
@@ -678,7 +746,7 @@ __global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *
         const int hi32 = __shfl((int)(anc >> 32), o, kWave);
         const i64 src = ((i64)hi32 << 32) | (i64)(unsigned)lo32;
         const i64 pp = pw + o;
-        if (col < d && pp < n) S.x_scr[pp * d + col] = S.x[src * d + col];
+        if (col < d && pp < n) glb(S.x_scr)[pp * d + col] = glb(S.x)[src * d + col];
     }
 }
 
@@ -687,7 +755,8 @@ __global__ __launch_bounds__(256) void k_bcopyback(const BSlot *slots, const int
 {
     int slot, tile;
     if (!locate(chunk_pref, act, n_act[0], blockIdx.x, slot, tile)) return;
-    const BSlot &S = slots[slot];
+    // a local copy: stores through the sampler's arrays cannot alias it
+    const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
     const BCtrl *c = S.ctrl;
     if (!c->resample || c->err_call) return;
     const i64 n = S.n;
@@ -697,14 +766,15 @@ __global__ __launch_bounds__(256) void k_bcopyback(const BSlot *slots, const int
     // rows [base, base + cnt) are one contiguous run of cnt * d doubles; base
     // is even, so the run starts 16-byte aligned
     const i64 e0 = base * d, ne = cnt * d;
-    const double2 *src2 = reinterpret_cast<const double2 *>(S.x_scr + e0);
-    double2 *dst2 = reinterpret_cast<double2 *>(S.x + e0);
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    const GLB(f64x2) *src2 = glb(reinterpret_cast<const f64x2 *>(S.x_scr + e0));
+    GLB(f64x2) *dst2 = glb(reinterpret_cast<f64x2 *>(S.x + e0));
     for (i64 e = threadIdx.x; e < ne / 2; e += 256) dst2[e] = src2[e];
-    if ((ne & 1) && threadIdx.x == 0) S.x[e0 + ne - 1] = S.x_scr[e0 + ne - 1];
+    if ((ne & 1) && threadIdx.x == 0) glb(S.x)[e0 + ne - 1] = glb(S.x_scr)[e0 + ne - 1];
     const i64 i = base + threadIdx.x;
     if (i < base + cnt) {
-        S.lp[i] = S.lp_scr[i];
-        S.logw[i] = S.reset;
+        glb(S.lp)[i] = glb(S.lp_scr)[i];
+        glb(S.logw)[i] = S.reset;
     }
 }
 
@@ -742,7 +812,7 @@ SamplerLayout sampler_layout(int64_t n, int d)
 }
 
 struct BatchLayout {
-    size_t slots, n_act, act, tile_pref, chunk_pref, bact, btile_pref, total;
+    size_t slots, n_act, act, tile_pref, chunk_pref, unit_pref, bact, btile_pref, total;
 };
 
 BatchLayout batch_layout(int cap)
@@ -759,6 +829,7 @@ BatchLayout batch_layout(int cap)
     L.act = take(4 * (size_t)cap);
     L.tile_pref = take(4 * (size_t)(cap + 1));
     L.chunk_pref = take(4 * (size_t)(cap + 1));
+    L.unit_pref = take(4 * (size_t)(cap + 1));
     L.bact = take(4 * (size_t)kBuckets * cap);
     L.btile_pref = take(4 * (size_t)kBuckets * (cap + 1));
     L.total = off;
@@ -792,6 +863,8 @@ struct smc_batch {
     std::vector<BSlot> h_slots;
     // host mirror of the tables (grid sizes)
     int n_act, total_tiles, total_chunks;
+    int64_t total_units;
+    int G;  // coordinate pairs per proposal unit
     int btiles[kBuckets];
     // graph of one step for the current membership and output pointers
     bool graph_on;
@@ -811,6 +884,7 @@ inline hipStream_t HS(void *s) { return reinterpret_cast<hipStream_t>(s); }
 void mirror_update(smc_batch *b)
 {
     b->n_act = b->total_tiles = b->total_chunks = 0;
+    b->total_units = 0;
     for (int q = 0; q < kBuckets; ++q) b->btiles[q] = 0;
     for (int s = 0; s < b->cap; ++s) {
         const BSlot &v = b->h_slots[s];
@@ -818,6 +892,7 @@ void mirror_update(smc_batch *b)
         b->n_act += 1;
         b->total_tiles += v.ntile;
         b->total_chunks += v.nchunk;
+        b->total_units += units_of(v.nchunk, v.d, b->G);
         b->btiles[v.bucket] += v.nchunk;
     }
     b->version += 1;
@@ -827,20 +902,20 @@ void mirror_update(smc_batch *b)
 hipError_t launch_tables(smc_batch *b, hipStream_t s)
 {
     hipLaunchKernelGGL(k_btables, dim3(1), dim3(256), 0, s, (const BSlot *)b->d_slots, b->cap,
-                       b->tabs);
+                       b->G, b->tabs);
     return hipGetLastError();
 }
 
 template <bool kInit>
-void launch_bis_bucket(int q, dim3 g, hipStream_t s, const smc_batch *b, int single)
+void launch_quad_bucket(int q, dim3 g, hipStream_t s, const smc_batch *b, int single)
 {
     const BSlot *sl = b->d_slots;
     const BTabs &t = b->tabs;
     switch (q) {
-#define SMC_BIS_CASE(Q)                                                                       \
-    case Q:                                                                                   \
-        hipLaunchKernelGGL((k_bis<8 * (Q + 1), kInit>), g, dim3(256), 0, s, sl, t.n_act, t.bact, \
-                           t.btile_pref, Q, b->cap, single);                                  \
+#define SMC_BIS_CASE(Q)                                                                        \
+    case Q:                                                                                    \
+        hipLaunchKernelGGL((k_bquad<8 * (Q + 1), kInit>), g, dim3(256), 0, s, sl, t.n_act,       \
+                           t.bact, t.btile_pref, Q, b->cap, single);                           \
         break;
         SMC_BIS_CASE(0) SMC_BIS_CASE(1) SMC_BIS_CASE(2) SMC_BIS_CASE(3)
         SMC_BIS_CASE(4) SMC_BIS_CASE(5) SMC_BIS_CASE(6) SMC_BIS_CASE(7)
@@ -853,8 +928,10 @@ hipError_t enqueue_step(smc_batch *b, smc_resample_info *info, double *est, hipS
 {
     const BSlot *sl = b->d_slots;
     const BTabs &t = b->tabs;
+    hipLaunchKernelGGL(k_bprop<false>, dim3((unsigned)b->total_units), dim3(256), 0, s, sl,
+                       t.n_act, t.act, t.unit_pref, b->G, -1);
     for (int q = 0; q < kBuckets; ++q)
-        if (b->btiles[q] > 0) launch_bis_bucket<false>(q, dim3(b->btiles[q]), s, b, -1);
+        if (b->btiles[q] > 0) launch_quad_bucket<false>(q, dim3(b->btiles[q]), s, b, -1);
     hipLaunchKernelGGL(k_bscan, dim3(b->total_tiles), dim3(256), 0, s, sl, t.n_act, t.act,
                        t.tile_pref);
     hipLaunchKernelGGL(k_bdecide, dim3(b->n_act), dim3(256), 0, s, sl, t.n_act, t.act, info, est);
@@ -905,11 +982,13 @@ smc_status smc_batch_create(smc_batch **h_out, int32_t capacity, void *ws, size_
     b->tabs.act = reinterpret_cast<int *>(b->ws + L.act);
     b->tabs.tile_pref = reinterpret_cast<int *>(b->ws + L.tile_pref);
     b->tabs.chunk_pref = reinterpret_cast<int *>(b->ws + L.chunk_pref);
+    b->tabs.unit_pref = reinterpret_cast<int *>(b->ws + L.unit_pref);
     b->tabs.bact = reinterpret_cast<int *>(b->ws + L.bact);
     b->tabs.btile_pref = reinterpret_cast<int *>(b->ws + L.btile_pref);
     b->h_slots.assign((size_t)capacity, BSlot());
     for (auto &v : b->h_slots) v.n = 0;
     b->graph_on = true;
+    b->G = 8;
     b->graph = nullptr;
     b->exec = nullptr;
     b->version = 0;
@@ -943,7 +1022,8 @@ smc_status smc_batch_attach(smc_batch *b, int32_t slot, const smc_batch_sampler 
     const SamplerLayout L = sampler_layout(h_s->n, h_s->d);
     if (h_s->ws_bytes < L.total) return SMC_E_NOMEM;
     const int64_t nt = ntile_of(h_s->n), nc = nchunk_of(h_s->n);
-    if ((int64_t)b->total_tiles + nt > 0x7fffffff || (int64_t)b->total_chunks + nc > 0x7fffffff)
+    if ((int64_t)b->total_tiles + nt > 0x7fffffff || (int64_t)b->total_chunks + nc > 0x7fffffff ||
+        b->total_units + units_of((int)nc, h_s->d, 1) > 0x7fffffff)
         return SMC_E_UNSUPPORTED;
     unsigned char *w = reinterpret_cast<unsigned char *>(h_s->ws);
     BSlot v;
@@ -987,7 +1067,9 @@ smc_status smc_batch_attach(smc_batch *b, int32_t slot, const smc_batch_sampler 
     v.tis = reinterpret_cast<BTileIS *>(w + L.tis);
     const hipStream_t s = HS(stream);
     hipLaunchKernelGGL(k_bslot_set, dim3(1), dim3(1), 0, s, v, b->d_slots + slot);
-    launch_bis_bucket<true>(v.bucket, dim3(v.nchunk), s, b, slot);
+    hipLaunchKernelGGL(k_bprop<true>, dim3(v.nchunk), dim3(256), 0, s, (const BSlot *)b->d_slots,
+                       b->tabs.n_act, b->tabs.act, b->tabs.unit_pref, b->G, slot);
+    launch_quad_bucket<true>(v.bucket, dim3(v.nchunk), s, b, slot);
     hipLaunchKernelGGL(k_binit, dim3(1), dim3(64), 0, s, (const BSlot *)b->d_slots, slot);
     if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     b->h_slots[slot] = v;

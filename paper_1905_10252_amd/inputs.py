@@ -143,3 +143,45 @@ def batch_specs(count: int = BATCH["count"], seed: int = BATCH["seed"],
                         init_sd=BATCH["init_sd"]))
     return out
 
+
+
+# Serving: a stream of sampler requests mixing the shapes above.  Gaussian
+# requests (the 1-D workload's and the batched workload's kind) with N
+# log-uniform in [2^10, 2^20] and d uniform in 1..64; logistic-regression
+# requests with N log-uniform in [2^10, 2^16], D uniform in 8..64 and M rows
+# log-uniform in [2^10, 2^16]; iterations uniform in 20..100; exponential
+# inter-arrival gaps (a Poisson process) of mean 1 / rate.
+SERVE = dict(requests=2000, seed=400, logreg_share=1.0 / 3.0, n_lo=1 << 10, n_hi=1 << 20,
+             lr_n_hi=1 << 16, m_lo=1 << 10, m_hi=1 << 16, d_lr_lo=8, d_lr_hi=64, t_lo=20,
+             t_hi=100)
+
+
+def serve_requests(count: int, rate: float, seed: int = SERVE["seed"], scale: float = 1.0):
+    """Request descriptions (dicts) in arrival order; ``scale`` shrinks every
+    N and M (for quick runs)."""
+    rng = np.random.default_rng(seed)
+    c = SERVE
+    out, t = [], 0.0
+    for k in range(count):
+        t += float(rng.exponential(1.0 / rate)) if rate > 0 else 0.0
+        iters = int(rng.integers(c["t_lo"], c["t_hi"] + 1))
+        if rng.uniform() < c["logreg_share"]:
+            n = int(round(math.exp(rng.uniform(math.log(c["n_lo"]), math.log(c["lr_n_hi"])))))
+            m = int(round(math.exp(rng.uniform(math.log(c["m_lo"]), math.log(c["m_hi"])))))
+            d = int(rng.integers(c["d_lr_lo"], c["d_lr_hi"] + 1))
+            n, m = max(64, int(n * scale)), max(64, int(m * scale))
+            X, y, _ = logreg_data(m, d, int(rng.integers(0, 2**31)))
+            out.append(dict(kind="logreg", n=n, d=d, iters=iters, arrival=t,
+                            seed=(seed << 32) + k, sampler_id=k,
+                            params=dict(X=X.astype(np.float64), y=y, prior_var=10.0,
+                                        rw_sd=0.01)))
+        else:
+            n = int(round(math.exp(rng.uniform(math.log(c["n_lo"]), math.log(c["n_hi"])))))
+            d = int(rng.integers(1, 65))
+            n = max(1, int(n * scale))
+            mean, U, _ = wishart_target(d, rng)
+            out.append(dict(kind="gauss", n=n, d=d, iters=iters, arrival=t,
+                            seed=(seed << 32) + k, sampler_id=k,
+                            params=dict(mean=mean, chol=U, rw_sd=0.5 / math.sqrt(d),
+                                        init_sd=3.0)))
+    return out

@@ -1,0 +1,194 @@
+"""Continuous-batching request loop over libsmc.
+
+Requests are SMC-sampler runs (Alg 2) of their own size, dimension, target
+and iteration count.  Each tick of the loop admits arrived requests while a
+batch slot and the HBM budget allow (first come, first served), advances
+every admitted request by one iteration, and retires the finished ones:
+
+  - Gaussian requests (any N and d <= 64, full-precision target) share one
+    batched step of ``smc.Batch``: all of them advance in the same launches;
+  - logistic-regression requests each advance by one ``smc_step`` of their
+    own context (BF16 MFMA likelihood), on the same stream.
+
+Particle state stays on the device from admission to retirement.  A request's
+result depends only on the request: the batch gives every sampler the same
+bits alone and in a mix.  All device work is the library's; this module only
+schedules it and keeps time.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib as L
+from . import smc
+
+
+@dataclass
+class Request:
+    rid: int
+    kind: str                 # "gauss" or "logreg"
+    n: int
+    d: int
+    iters: int
+    arrival: float            # seconds (or ticks) from the start of the run
+    seed: int
+    sampler_id: int
+    params: dict = field(default_factory=dict)
+    admitted: float | None = None
+    finished: float | None = None
+    result: dict | None = None
+
+    @property
+    def latency(self):
+        return None if self.finished is None else self.finished - self.arrival
+
+
+def request_bytes(r: Request) -> int:
+    """Device bytes a request holds while admitted (state plus workspace)."""
+    if r.kind == "gauss":
+        # x, x scratch, lp, lp scratch, logw, prefix: (2d + 4) doubles a particle
+        return 8 * r.n * (2 * r.d + 4) + 8 * r.d * (r.d + 1) + (1 << 16)
+    m = r.params["X"].shape[0]
+    dp = (r.d + 15) // 16 * 16
+    # particles, scratch, weights, log-targets, prefix, 8 likelihood partials,
+    # bf16 copies of the particles and of the data
+    return 8 * r.n * (2 * r.d + 16) + 2 * r.n * dp + 2 * m * dp + 8 * m * (r.d + 1) + (1 << 16)
+
+
+class Server:
+    """Admits requests into a batch of ``capacity`` slots under an HBM budget
+    (bytes) and advances all admitted requests one iteration per tick."""
+
+    def __init__(self, capacity: int = 256, hbm_budget: int = 64 << 30, *, graph: bool = True,
+                 device=None):
+        self.device = torch.device(device or "cuda")
+        self.batch = smc.Batch(capacity, graph=graph, device=self.device)
+        self.capacity = capacity
+        self.budget = int(hbm_budget)
+        self.used = 0
+        self.free = list(range(capacity))[::-1]
+        self.queue = collections.deque()
+        self.gauss = {}    # slot -> [request, iterations left]
+        self.logreg = {}   # rid -> [request, sampler, iterations left]
+        self.iters_done = 0
+        self.peak_used = 0
+        self.peak_active = 0
+
+    # --------------------------------------------------------------- admission
+    def submit(self, r: Request) -> None:
+        if request_bytes(r) > self.budget:
+            raise ValueError("request %d needs more than the whole HBM budget" % r.rid)
+        self.queue.append(r)
+
+    def _fits(self, r: Request) -> bool:
+        if self.used + request_bytes(r) > self.budget:
+            return False
+        return r.kind == "logreg" or bool(self.free)
+
+    def _admit(self, now: float) -> None:
+        while self.queue and self.queue[0].arrival <= now and self._fits(self.queue[0]):
+            r = self.queue.popleft()
+            p = r.params
+            if r.kind == "gauss":
+                slot = self.free.pop()
+                self.batch.attach(slot, r.n, r.d, p["mean"], p["chol"], seed=r.seed,
+                                  sampler_id=r.sampler_id, rw_sd=p["rw_sd"],
+                                  init_mean=p.get("init_mean", 0.0),
+                                  init_sd=p.get("init_sd", 3.0), mode=p.get("mode", L.MODE_AUTO))
+                self.gauss[slot] = [r, r.iters]
+            else:
+                s = smc.Sampler(r.n, r.d, "logreg", seed=r.seed, sampler_id=r.sampler_id,
+                                X=p["X"], y=p["y"], prior_var=p["prior_var"],
+                                precision=p.get("precision", "bf16"), rw_sd=p["rw_sd"],
+                                init_sd=math.sqrt(p["prior_var"]), mode=p.get("mode", L.MODE_AUTO),
+                                device=self.device)
+                self.logreg[r.rid] = [r, s, r.iters]
+            self.used += request_bytes(r)
+            self.peak_used = max(self.peak_used, self.used)
+            self.peak_active = max(self.peak_active, len(self.gauss) + len(self.logreg))
+            r.admitted = now
+
+    # -------------------------------------------------------------------- tick
+    def busy(self) -> bool:
+        return bool(self.gauss or self.logreg)
+
+    def tick(self, now_fn) -> list:
+        """Admits, advances every admitted request by one iteration, retires
+        the finished ones (their results are read back); returns them."""
+        self._admit(now_fn())
+        if not self.busy():
+            return []
+        if self.gauss:
+            self.batch.step(info=False, est=True)
+            self.iters_done += len(self.gauss)
+        for ent in self.logreg.values():
+            ent[1].step(info=False, est=True)
+            self.iters_done += 1
+        done = []
+        for slot, ent in list(self.gauss.items()):
+            ent[1] -= 1
+            if ent[1] == 0:
+                done.append(("gauss", slot, ent[0]))
+        for rid, ent in list(self.logreg.items()):
+            ent[2] -= 1
+            if ent[2] == 0:
+                done.append(("logreg", rid, ent[0]))
+        if not done:
+            return []
+        torch.cuda.current_stream().synchronize()
+        t = now_fn()
+        out = []
+        for kind, key, r in done:
+            if kind == "gauss":
+                r.result = {"x": self.batch.x(key).cpu().numpy(), **self.batch.estimates(key)}
+                self.batch.detach(key)
+                self.free.append(key)
+                del self.gauss[key]
+            else:
+                s = self.logreg.pop(key)[1]
+                r.result = {"x": s.x.cpu().numpy(), **s.estimates()}
+            self.used -= request_bytes(r)
+            r.finished = t
+            out.append(r)
+        return out
+
+    # --------------------------------------------------------------------- run
+    def run(self, requests: list, *, clock: str = "wall") -> dict:
+        """Serves ``requests`` (arrival times in seconds, or in ticks with
+        clock="tick") to completion; returns latency and throughput figures."""
+        for r in sorted(requests, key=lambda q: (q.arrival, q.rid)):
+            self.submit(r)
+        ticks = [0]
+        t0 = time.perf_counter()
+        if clock == "tick":
+            def now():
+                return float(ticks[0])
+        else:
+            def now():
+                return time.perf_counter() - t0
+        finished = []
+        while len(finished) < len(requests):
+            if not self.busy() and self.queue and self.queue[0].arrival > now():
+                if clock == "tick":
+                    ticks[0] = int(math.ceil(self.queue[0].arrival))
+                else:
+                    time.sleep(min(1e-3, max(0.0, self.queue[0].arrival - now())))
+                continue
+            finished += self.tick(now)
+            ticks[0] += 1
+        torch.cuda.current_stream().synchronize()
+        wall = time.perf_counter() - t0
+        lat = sorted(r.latency for r in finished)
+        iters = sum(r.iters for r in finished)
+
+        def pct(p):
+            return lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
+
+        return {"requests": len(finished), "wall_s": wall, "sampler_iters": iters,
+                "sampler_iters_per_s": iters / wall, "p50_latency": pct(50),
+                "p99_latency": pct(99), "ticks": ticks[0]}
