@@ -414,13 +414,14 @@ double orc_log_target(const orc_smc_cfg *c, const double *x)
         return c->log_norm - 0.5 * acc;
     }
     if (c->target == ORC_T_GAUSS_CHOL) {
-        /* (x - mean)^T P (x - mean) = |U (x - mean)|^2, row i of U from its diagonal on */
+        /* (x - mean)^T P (x - mean) = |U (x - mean)|^2: row i of U from its
+         * diagonal on, each term a fused multiply-add, rows summed in order */
         double acc = 0.0;
         for (int32_t i = 0; i < c->d; ++i) {
             double r = 0.0;
             for (int32_t k = i; k < c->d; ++k)
-                r = r + c->chol[(int64_t)i * c->d + k] * (x[k] - c->mean[k]);
-            acc = acc + r * r;
+                r = fma(c->chol[(int64_t)i * c->d + k], x[k] - c->mean[k], r);
+            acc = fma(r, r, acc);
         }
         return c->log_norm - 0.5 * acc;
     }
