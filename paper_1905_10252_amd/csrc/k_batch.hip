@@ -64,6 +64,10 @@ __device__ inline GLB(T) *glb(T *p)
 {
     return (GLB(T) *)p;
 }
+// Read-only data that is the same for the whole wave (the target's U and
+// mean) is read through the constant address space: scalar loads into SGPRs,
+// no LDS or vector-memory traffic per lane.
+#define CST(T) __attribute__((address_space(4))) T
 
 // Per-sampler control block (in the sampler's workspace).
 struct BCtrl {
@@ -92,6 +96,7 @@ struct BSlot {
     double *x, *logw;
     BCtrl *ctrl;
     double *lp, *x_scr, *lp_scr, *epart, *cpart, *rec_num;
+    double *upad;  // [DB][DB] U zero-padded to the bucket width, then [DB] mean
     u64 *pref, *status;
     TilePart *tpart;
     BTileIS *tis;
@@ -106,6 +111,27 @@ struct BTabs {
     int *bact;        // [kBuckets][cap]
     int *btile_pref;  // [kBuckets][cap + 1] chunk prefix over bact
 };
+
+// Sum of each 16-lane row of the wave, left in the row's last lane (lanes
+// 15, 31, 47, 63), by DPP row shifts: VALU only, no LDS round trips.  Lanes
+// whose shifted source lies outside the row add 0.
+template <int CTRL>
+__device__ inline double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ inline double row16_sum(double v)
+{
+    v += dpp_f64<0x111>(v);  // row_shr:1
+    v += dpp_f64<0x112>(v);  // row_shr:2
+    v += dpp_f64<0x114>(v);  // row_shr:4
+    v += dpp_f64<0x118>(v);  // row_shr:8
+    return v;
+}
 
 // Position of block b in a prefix table: slot and index within the slot.
 __device__ inline bool locate(const int *pref, const int *act, int nact, int b, int &slot,
@@ -125,6 +151,25 @@ __device__ inline bool locate(const int *pref, const int *act, int nact, int b, 
 
 // ------------------------------------------------------------------ tables
 __global__ void k_bslot_set(BSlot v, BSlot *dst) { *dst = v; }
+
+// U zero-padded to DB x DB (lower triangle and beyond d are zero) and the
+// mean zero-padded to DB, so the quadratic form needs no per-element guard:
+// the extra terms are fma(0, 0, s) = s.
+__global__ __launch_bounds__(256) void k_bpad(const BSlot *slots, int slot)
+{
+    const BSlot S = slots[slot];
+    const int d = S.d, DB = 8 * (S.bucket + 1);
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < DB * DB + DB; e += gridDim.x * 256) {
+        double v = 0.0;
+        if (e < DB * DB) {
+            const int r = e / DB, k = e - r * DB;
+            if (r < d && k < d && k >= r) v = S.chol[r * d + k];
+        } else if (e - DB * DB < d) {
+            v = S.mean[e - DB * DB];
+        }
+        S.upad[e] = v;
+    }
+}
 
 __global__ void k_bslots_clear(BSlot *slots, int cap)
 {
@@ -236,42 +281,51 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
     const bool act = i < n;
     GLB(double) *xi = glb(S.x) + i * d;
     double acc0 = 0.0;
-    // The pair's current coordinates are loaded before its normals are drawn,
-    // so the strided loads overlap the normal generation.  Its new values are
-    // stored at the top of the next iteration, after that iteration's loads:
-    // a load into a register that an outstanding store still reads must wait
-    // for the store, and a store a whole pair old has long completed.
-    const bool ld = !kInit && act;
-    double w0 = 0.0, w1 = 0.0;  // values of the previous pair, not yet stored
-    int wk = -1;
+    if (!kInit) {
+        // Step: the unit's block of rows [base, base + cnt) x columns
+        // [k0, k0 + w), w <= 16, moves between HBM and LDS as whole 128-byte
+        // lines (16 lanes per row); each thread then updates its own row in
+        // LDS.  Strided per-thread row accesses would touch 64 lines per
+        // wave instruction.
+        __shared__ double sx[kBChunk][17];
+        const int k0 = 2 * kp0, w = (2 * kp1 < d ? 2 * kp1 : d) - k0;
+        const i64 base = (i64)chunk * kBChunk;
+        const int cnt = (int)((n - base) < kBChunk ? (n - base) : kBChunk);
+        const int lc = tid & 15, lr = tid >> 4;
+        GLB(double) *xb = glb(S.x) + base * d + k0;
+        for (int r = lr; r < cnt; r += 16)
+            if (lc < w) sx[r][lc] = xb[(i64)r * d + lc];
+        __syncthreads();
+        for (int k2 = kp0; k2 < kp1; ++k2) {
+            double z[2];
+            normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)i, (uint32_t)k2, act, z[0],
+                             z[1]);
+            const int c = 2 * k2 - k0;
+            if (act) {
+                sx[tid][c] = sx[tid][c] + S.rw_sd * z[0];
+                if (c + 1 < w) sx[tid][c + 1] = sx[tid][c + 1] + S.rw_sd * z[1];
+            }
+        }
+        __syncthreads();
+        for (int r = lr; r < cnt; r += 16)
+            if (lc < w) xb[(i64)r * d + lc] = sx[r][lc];
+        return;
+    }
+    // Initialisation (whole rows, all pairs; log q0 sums over the row)
     for (int k2 = kp0; k2 < kp1; ++k2) {
         const int k0 = 2 * k2;
-        double c0 = 0.0, c1 = 0.0;
-        if (ld) c0 = xi[k0];
-        if (ld && k0 + 1 < d) c1 = xi[k0 + 1];
-        if (act && wk >= 0) {
-            xi[wk] = w0;
-            xi[wk + 1] = w1;  // wk + 1 < d: the previous pair was complete
-        }
         double z[2];
         normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)i, (uint32_t)k2, act, z[0], z[1]);
         if (act) {
-            w0 = kInit ? S.init_mean + S.init_sd * z[0] : c0 + S.rw_sd * z[0];
-            w1 = kInit ? S.init_mean + S.init_sd * z[1] : c1 + S.rw_sd * z[1];
-            if (kInit) {
-                const double t0 = w0 - S.init_mean;
+            for (int h = 0; h < 2; ++h) {
+                const int kk = k0 + h;
+                if (kk >= d) break;
+                const double xk = S.init_mean + S.init_sd * z[h];
+                xi[kk] = xk;
+                const double t0 = xk - S.init_mean;
                 acc0 = acc0 + (t0 * t0) * S.init_prec;
-                if (k0 + 1 < d) {
-                    const double t1 = w1 - S.init_mean;
-                    acc0 = acc0 + (t1 * t1) * S.init_prec;
-                }
             }
-            wk = k0;
         }
-    }
-    if (act && wk >= 0) {
-        xi[wk] = w0;
-        if (wk + 1 < d) xi[wk + 1] = w1;
     }
     if (kInit && act) glb(S.lp_scr)[i] = acc0;
 }
@@ -287,11 +341,9 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
                                                const int *bact, const int *bchunk_pref,
                                                int bucket, int cap, int single)
 {
-    __shared__ double sU[DB * DB];
-    __shared__ double sM[DB];
     __shared__ u64 s_key[4];
     __shared__ unsigned s_bad[4];
-    __shared__ double s_col[4][1 + 2 * DB];
+    __shared__ double s_col[16][1 + 2 * DB];  // one partial per 16-lane row
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     int slot, chunk;
     if (single >= 0) {
@@ -305,31 +357,49 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
     const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
     const i64 n = S.n;
     const int d = S.d;
-    // U zero-padded to DB x DB (lower triangle and beyond d are zero), so the
-    // quadratic form needs no per-element guard: the extra terms add +0.
-    for (int e = tid; e < DB * DB; e += 256) {
-        const int r = e / DB, k = e - r * DB;
-        sU[e] = (r < d && k < d && k >= r) ? S.chol[r * d + k] : 0.0;
-    }
-    for (int e = tid; e < DB; e += 256) sM[e] = e < d ? S.mean[e] : 0.0;
-    __syncthreads();
+    const CST(double) *sU = (const CST(double) *)S.upad;
+    const CST(double) *sM = sU + DB * DB;
     const i64 i = (i64)chunk * kBChunk + tid;
     const bool act = i < n;
-    const GLB(double) *xi = glb(S.x) + i * d;
     GLB(double) *lpg = glb(S.lp);
     GLB(double) *lwg = glb(S.logw);
     double lw = -__builtin_huge_val();
+    // The chunk's rows come in through LDS in slices of 16 columns, each
+    // moved as whole 128-byte lines (16 lanes per row).
+    __shared__ double sx[kBChunk][17];
+    constexpr int PW = DB < 16 ? DB : 16;
+    const i64 base = (i64)chunk * kBChunk;
+    const int cnt = (int)((n - base) < kBChunk ? (n - base) : kBChunk);
+    const int lc = tid & 15, lr = tid >> 4;
+    const GLB(double) *xb = glb(S.x) + base * d;
+    constexpr int NQ = (DB + PW - 1) / PW;
     double tv[DB];
 #pragma unroll
-    for (int k = 0; k < DB; ++k) tv[k] = (act && k < d) ? xi[k] - sM[k] : 0.0;
+    for (int q = 0; q < NQ; ++q) {
+        if (q * PW < d) {
+            for (int r = lr; r < cnt; r += 16)
+                if (lc < PW && q * PW + lc < d) sx[r][lc] = xb[(i64)r * d + q * PW + lc];
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < PW; ++c) {
+                const int k = q * PW + c;
+                if (k < DB) tv[k] = (act && k < d) ? sx[tid][c] - sM[k] : 0.0;
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int c = 0; c < PW; ++c)
+                if (q * PW + c < DB) tv[q * PW + c] = 0.0;
+        }
+    }
     if (act) {
         double acc = 0.0;
 #pragma unroll
         for (int r = 0; r < DB; ++r) {
             double sr = 0.0;
 #pragma unroll
-            for (int k = r; k < DB; ++k) sr = sr + sU[r * DB + k] * tv[k];
-            acc = acc + sr * sr;
+            for (int k = r; k < DB; ++k) sr = fma(sU[r * DB + k], tv[k], sr);
+            acc = fma(sr, sr, acc);
         }
         const double lpn = S.log_norm - 0.5 * acc;
         lw = kInit ? lpn - (S.init_log_norm - 0.5 * glb(S.lp_scr)[i]) : lwg[i] + (lpn - lpg[i]);
@@ -352,27 +422,35 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
     const double mb = okey_inv(bk);
     const bool live = act && mb > -__builtin_huge_val();
     const double e = live ? det_exp(lw - mb) : 0.0;
-    // column sums over the chunk: one wave sum per column, waves in order.
-    // The row is taken from the registers as (x - mean) + mean, within an ulp
-    // of x: these sums feed FP64 estimates, not the particle trajectories.
-    double se = wave_sum_f64(e);
-    if (lane == 0) s_col[wid][0] = se;
+    // column sums over the chunk: a DPP sum per 16-lane row, then the 16 row
+    // partials in order.  The row is taken from the registers as
+    // (x - mean) + mean, within an ulp of x: these sums feed FP64 estimates,
+    // not the particle trajectories.
+    const int prow = tid >> 4;
+    const bool last = (lane & 15) == 15;
+    {
+        const double se = row16_sum(e);
+        if (last) s_col[prow][0] = se;
+    }
 #pragma unroll
     for (int k = 0; k < DB; ++k) {
         if (k < d) {
             const double xk = act ? tv[k] + sM[k] : 0.0;
             const double ex = e * xk;
-            const double s1 = wave_sum_f64(ex), s2 = wave_sum_f64(ex * xk);
-            if (lane == 0) {
-                s_col[wid][1 + k] = s1;
-                s_col[wid][1 + d + k] = s2;
+            const double s1 = row16_sum(ex), s2 = row16_sum(ex * xk);
+            if (last) {
+                s_col[prow][1 + k] = s1;
+                s_col[prow][1 + d + k] = s2;
             }
         }
     }
     __syncthreads();
     double *cp = S.cpart + (i64)chunk * (2 + 2 * d);
-    for (int c = tid; c < 1 + 2 * d; c += 256)
-        cp[1 + c] = ((s_col[0][c] + s_col[1][c]) + s_col[2][c]) + s_col[3][c];
+    for (int c = tid; c < 1 + 2 * d; c += 256) {
+        double a = s_col[0][c];
+        for (int r = 1; r < 16; ++r) a += s_col[r][c];
+        cp[1 + c] = a;
+    }
     if (tid == 0) {
         cp[0] = mb;
         BTileIS o;
@@ -780,7 +858,7 @@ __global__ __launch_bounds__(256) void k_bcopyback(const BSlot *slots, const int
 
 // ------------------------------------------------------------------- host
 struct SamplerLayout {
-    size_t ctrl, lp, x_scr, lp_scr, pref, status, tpart, tis, epart, cpart, rec_num, total;
+    size_t ctrl, lp, x_scr, lp_scr, pref, status, tpart, tis, epart, cpart, rec_num, upad, total;
 };
 
 inline int64_t ntile_of(int64_t n) { return (n + kBTile - 1) / kBTile; }
@@ -807,6 +885,8 @@ SamplerLayout sampler_layout(int64_t n, int d)
     L.epart = take(8 * 2 * (size_t)d * nt);
     L.cpart = take(8 * (2 + 2 * (size_t)d) * (size_t)nchunk_of(n));
     L.rec_num = take(8 * 2 * (size_t)d);
+    const size_t DB = (size_t)(d + 7) / 8 * 8;
+    L.upad = take(8 * (DB * DB + DB));
     L.total = off;
     return L;
 }
@@ -1060,6 +1140,7 @@ smc_status smc_batch_attach(smc_batch *b, int32_t slot, const smc_batch_sampler 
     v.lp_scr = reinterpret_cast<double *>(w + L.lp_scr);
     v.epart = reinterpret_cast<double *>(w + L.epart);
     v.cpart = reinterpret_cast<double *>(w + L.cpart);
+    v.upad = reinterpret_cast<double *>(w + L.upad);
     v.rec_num = reinterpret_cast<double *>(w + L.rec_num);
     v.pref = reinterpret_cast<u64 *>(w + L.pref);
     v.status = reinterpret_cast<u64 *>(w + L.status);
@@ -1067,6 +1148,7 @@ smc_status smc_batch_attach(smc_batch *b, int32_t slot, const smc_batch_sampler 
     v.tis = reinterpret_cast<BTileIS *>(w + L.tis);
     const hipStream_t s = HS(stream);
     hipLaunchKernelGGL(k_bslot_set, dim3(1), dim3(1), 0, s, v, b->d_slots + slot);
+    hipLaunchKernelGGL(k_bpad, dim3(4), dim3(256), 0, s, (const BSlot *)b->d_slots, slot);
     hipLaunchKernelGGL(k_bprop<true>, dim3(v.nchunk), dim3(256), 0, s, (const BSlot *)b->d_slots,
                        b->tabs.n_act, b->tabs.act, b->tabs.unit_pref, b->G, slot);
     launch_quad_bucket<true>(v.bucket, dim3(v.nchunk), s, b, slot);
