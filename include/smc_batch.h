@@ -13,7 +13,8 @@
  * output order of Alg 5, reset to 1/N).  The target is a Gaussian with a full
  * precision matrix P = U^T U (U upper triangular):
  *   log pi(x) = log_norm - |U (x - mean)|^2 / 2,
- * with |U t|^2 = sum_i (sum_{k >= i} U_ik t_k)^2 summed in index order.
+ * with |U t|^2 = sum_i (sum_{k >= i} U_ik t_k)^2 summed in index order, each
+ * term a fused multiply-add.
  *
  * A sampler's results depend only on its own description (seed, sampler id,
  * sizes, target), never on which other samplers share the batch: a sampler
@@ -43,7 +44,7 @@ enum { SMC_BATCH_DMAX = 64, SMC_BATCH_EST_STRIDE = 256 };
 
 /* One sampler of a batch, copied at smc_batch_attach. */
 typedef struct smc_batch_sampler {
-    int64_t n;               /* particles N_s, 1 <= N_s <= 2^26                       */
+    int64_t n;               /* particles N_s, 1 <= N_s <= 2^28                       */
     int32_t d;               /* dimension, 1 <= d <= 64                                */
     int32_t mode;            /* SMC_MODE_* resampling trigger                          */
     int32_t ess_num;         /* N* = ess_num / ess_den * N_s (Alg 2 default 1/2)       */
@@ -58,7 +59,8 @@ typedef struct smc_batch_sampler {
     double log_norm;         /* additive constant of log pi: -d/2 log 2pi + log det U  */
     const double *mean;      /* [d] target mean                                        */
     const double *chol;      /* [d][d] row-major upper-triangular U, P = U^T U          */
-    double *x;               /* [N_s][d] particles (FP64), the sampler's state         */
+    double *x;               /* [N_s][d] initial particle array (FP64); see            */
+                             /*   smc_batch_particles for where they are after a step   */
     double *logw;            /* [N_s] log-weights                                      */
     void *ws;                /* sampler workspace, 256-byte aligned                    */
     size_t ws_bytes;         /* >= smc_batch_sampler_bytes(this)                       */
@@ -93,6 +95,15 @@ smc_status smc_batch_detach(smc_batch *b, int32_t slot, void *stream);
  * a step are captured once per set of attached samplers (and info/est
  * pointers) and replayed as one HIP graph. */
 smc_status smc_batch_step(smc_batch *b, smc_resample_info *info, double *est, void *stream);
+
+/* Where slot `slot`'s particles are now (waits for the stream).  Resampling
+ * writes the redistributed particles into the sampler's workspace copy and
+ * the two copies then alternate (no copy back), so the current particles
+ * [N_s][d] and cached log-targets [N_s] are either the description's x and
+ * the workspace's log-target array, or the two workspace copies.  The
+ * log-weights always stay in the description's logw. */
+smc_status smc_batch_particles(smc_batch *b, int32_t slot, double **h_x, double **h_lp,
+                               void *stream);
 
 /* Enables (1) or disables (0) graph capture of the step. */
 smc_status smc_batch_set_graph(smc_batch *b, int32_t enable);

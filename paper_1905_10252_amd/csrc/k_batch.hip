@@ -22,8 +22,9 @@
 //               recycling, the sampler's info record.
 //   k_bexpand   per 256 outputs of resampling samplers: ancestor by binary
 //               search on the prefix, rows copied by whole wavefronts.
-//   k_bcopyback per chunk of resampling samplers: rows and cached log-target
-//               back in place, weights reset.
+//   k_bflip     per sampler that resampled: the redistributed copy becomes
+//               the current one (particles alternate between the caller's
+//               array and the workspace copy; no copy back).
 //
 // Tiles never straddle samplers, a tile waits only on earlier tiles of its own
 // sampler, and every reduction runs in a fixed order over that sampler's
@@ -76,7 +77,8 @@ struct BCtrl {
     double logZ_prev, lc_max, rec_den;
     unsigned t;          // iteration of the next step (1, 2, ...)
     unsigned resample;   // decision of the last step
-    unsigned err_call, err_latch, spin_fail, bad, rec_steps, pad;
+    unsigned err_call, err_latch, spin_fail, bad, rec_steps;
+    unsigned cur;        // 0: particles and log-targets in (x, lp); 1: in (x_scr, lp_scr)
 };
 
 // Per-chunk max key and non-finite flag of the update kernel.
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
         const i64 base = (i64)chunk * kBChunk;
         const int cnt = (int)((n - base) < kBChunk ? (n - base) : kBChunk);
         const int lc = tid & 15, lr = tid >> 4;
-        GLB(double) *xb = glb(S.x) + base * d + k0;
+        GLB(double) *xb = glb(S.ctrl->cur ? S.x_scr : S.x) + base * d + k0;
         for (int r = lr; r < cnt; r += 16)
             if (lc < w) sx[r][lc] = xb[(i64)r * d + lc];
         __syncthreads();
@@ -361,7 +363,8 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
     const CST(double) *sM = sU + DB * DB;
     const i64 i = (i64)chunk * kBChunk + tid;
     const bool act = i < n;
-    GLB(double) *lpg = glb(S.lp);
+    const bool alt = !kInit && S.ctrl->cur;
+    GLB(double) *lpg = glb(alt ? S.lp_scr : S.lp);
     GLB(double) *lwg = glb(S.logw);
     double lw = -__builtin_huge_val();
     // The chunk's rows come in through LDS in slices of 16 columns, each
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
     const i64 base = (i64)chunk * kBChunk;
     const int cnt = (int)((n - base) < kBChunk ? (n - base) : kBChunk);
     const int lc = tid & 15, lr = tid >> 4;
-    const GLB(double) *xb = glb(S.x) + base * d;
+    const GLB(double) *xb = glb(alt ? S.x_scr : S.x) + base * d;
     constexpr int NQ = (DB + PW - 1) / PW;
     double tv[DB];
 #pragma unroll
@@ -493,6 +496,7 @@ __global__ __launch_bounds__(64) void k_binit(const BSlot *slots, int slot)
     c->rec_den = 0.0;
     c->rec_steps = 0;
     c->t = 1;
+    c->cur = 0;
     c->resample = 0;
     c->err_call = err;
     c->err_latch = err;
@@ -799,6 +803,10 @@ __global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *
     const i64 n = S.n;
     const int d = S.d;
     const u64 Ssum = c->S, U = c->U;
+    // from the current copy into the other one
+    const bool alt = c->cur;
+    const double *xs = alt ? S.x_scr : S.x, *lps = alt ? S.lp_scr : S.lp;
+    double *xd = alt ? S.x : S.x_scr, *lpd = alt ? S.lp : S.lp_scr;
     const i64 p = (i64)ch * kBChunk + tid;
     // anc(p) = first j with N S_j + U >= (p + 1) S (it exists: j = n - 1)
     i64 lo = 0, hi = n - 1;
@@ -810,7 +818,8 @@ __global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *
             if (lt128(add128(mul64((u64)n, pg[mid]), U), rhs)) lo = mid + 1;
             else hi = mid;
         }
-        glb(S.lp_scr)[p] = glb(S.lp)[lo];
+        glb(lpd)[p] = glb(lps)[lo];
+        glb(S.logw)[p] = S.reset;
     }
     const i64 anc = lo;
     int dp2 = 1;
@@ -824,36 +833,18 @@ __global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *
         const int hi32 = __shfl((int)(anc >> 32), o, kWave);
         const i64 src = ((i64)hi32 << 32) | (i64)(unsigned)lo32;
         const i64 pp = pw + o;
-        if (col < d && pp < n) glb(S.x_scr)[pp * d + col] = glb(S.x)[src * d + col];
+        if (col < d && pp < n) glb(xd)[pp * d + col] = glb(xs)[src * d + col];
     }
 }
 
-__global__ __launch_bounds__(256) void k_bcopyback(const BSlot *slots, const int *n_act,
-                                                   const int *act, const int *chunk_pref)
+// After redistribution the new copy becomes the current one.
+__global__ __launch_bounds__(64) void k_bflip(const BSlot *slots, const int *n_act,
+                                              const int *act)
 {
-    int slot, tile;
-    if (!locate(chunk_pref, act, n_act[0], blockIdx.x, slot, tile)) return;
-    // a local copy: stores through the sampler's arrays cannot alias it
-    const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
-    const BCtrl *c = S.ctrl;
-    if (!c->resample || c->err_call) return;
-    const i64 n = S.n;
-    const int d = S.d;
-    const i64 base = (i64)tile * kBChunk;
-    const i64 cnt = (n - base) < kBChunk ? (n - base) : kBChunk;
-    // rows [base, base + cnt) are one contiguous run of cnt * d doubles; base
-    // is even, so the run starts 16-byte aligned
-    const i64 e0 = base * d, ne = cnt * d;
-    typedef double f64x2 __attribute__((ext_vector_type(2)));
-    const GLB(f64x2) *src2 = glb(reinterpret_cast<const f64x2 *>(S.x_scr + e0));
-    GLB(f64x2) *dst2 = glb(reinterpret_cast<f64x2 *>(S.x + e0));
-    for (i64 e = threadIdx.x; e < ne / 2; e += 256) dst2[e] = src2[e];
-    if ((ne & 1) && threadIdx.x == 0) glb(S.x)[e0 + ne - 1] = glb(S.x_scr)[e0 + ne - 1];
-    const i64 i = base + threadIdx.x;
-    if (i < base + cnt) {
-        glb(S.lp)[i] = glb(S.lp_scr)[i];
-        glb(S.logw)[i] = S.reset;
-    }
+    const int k = blockIdx.x * 64 + threadIdx.x;
+    if (k >= n_act[0]) return;
+    BCtrl *c = slots[act[k]].ctrl;
+    if (c->resample && !c->err_call) c->cur ^= 1u;
 }
 
 // ------------------------------------------------------------------- host
@@ -1017,8 +1008,7 @@ hipError_t enqueue_step(smc_batch *b, smc_resample_info *info, double *est, hipS
     hipLaunchKernelGGL(k_bdecide, dim3(b->n_act), dim3(256), 0, s, sl, t.n_act, t.act, info, est);
     hipLaunchKernelGGL(k_bexpand, dim3(b->total_chunks), dim3(256), 0, s, sl, t.n_act, t.act,
                        t.chunk_pref);
-    hipLaunchKernelGGL(k_bcopyback, dim3(b->total_chunks), dim3(256), 0, s, sl, t.n_act, t.act,
-                       t.chunk_pref);
+    hipLaunchKernelGGL(k_bflip, dim3((b->n_act + 63) / 64), dim3(64), 0, s, sl, t.n_act, t.act);
     return hipGetLastError();
 }
 
@@ -1211,6 +1201,20 @@ smc_status smc_batch_step(smc_batch *b, smc_resample_info *info, double *est, vo
     }
     b->eager_same += 1;
     return enqueue_step(b, info, est, s) == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+}
+
+smc_status smc_batch_particles(smc_batch *b, int32_t slot, double **h_x, double **h_lp,
+                               void *stream)
+{
+    if (!b || slot < 0 || slot >= b->cap || b->h_slots[slot].n <= 0) return SMC_E_ARG;
+    if (hipStreamSynchronize(HS(stream)) != hipSuccess) return SMC_E_DEVICE;
+    const BSlot &v = b->h_slots[slot];
+    unsigned cur = 0;
+    if (hipMemcpy(&cur, &v.ctrl->cur, sizeof(cur), hipMemcpyDeviceToHost) != hipSuccess)
+        return SMC_E_DEVICE;
+    if (h_x) *h_x = cur ? v.x_scr : v.x;
+    if (h_lp) *h_lp = cur ? v.lp_scr : v.lp;
+    return SMC_OK;
 }
 
 smc_status smc_batch_set_graph(smc_batch *b, int32_t enable)

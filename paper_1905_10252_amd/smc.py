@@ -314,7 +314,17 @@ class Batch:
         return ns.value, nt.value
 
     def x(self, slot: int) -> torch.Tensor:
-        return self.slots[int(slot)]["x"]
+        """The slot's current particles [N][d] (waits for the stream): the
+        attach-time array or the workspace copy, which alternate."""
+        e = self.slots[int(slot)]
+        px = C.c_void_p()
+        L.check(self._lib.smc_batch_particles(self.h, int(slot), C.byref(px), None, _stream()),
+                "smc_batch_particles")
+        if px.value == e["x"].data_ptr():
+            return e["x"]
+        off = px.value - e["ws"].data_ptr()
+        nb = 8 * e["n"] * e["d"]
+        return e["ws"][off:off + nb].view(torch.float64).view(e["n"], e["d"])
 
     def logw(self, slot: int) -> torch.Tensor:
         return self.slots[int(slot)]["logw"]
