@@ -166,9 +166,14 @@ def batch_metrics(dev, timed_steps):
                      sampler_id=sp["sampler_id"], rw_sd=sp["rw_sd"], init_sd=sp["init_sd"])
         return b
 
+    from paper_1905_10252_amd import tune
     res = {"samplers": ns, "particles": int(sum(sp["n"] for sp in specs)),
            "mean_d": round(sum(sp["d"] for sp in specs) / ns, 2)}
+    tuned = tune.tune_group(specs, device=dev)
+    res["unit_pairs"] = tuned["best"]
+    res["tuning_ms_per_step"] = {str(g): round(v, 4) for g, v in tuned["ms"].items()}
     b = make(specs, True)
+    b.set_group(tuned["best"])
     timed_steps(b, 4)  # the third eager step captures the graph
     k = 20
     ms, per = timed_steps(b, k)

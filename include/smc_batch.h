@@ -105,6 +105,11 @@ smc_status smc_batch_step(smc_batch *b, smc_resample_info *info, double *est, vo
 smc_status smc_batch_particles(smc_batch *b, int32_t slot, double **h_x, double **h_lp,
                                void *stream);
 
+/* Coordinate pairs per proposal work unit (a unit is 256 particles times
+ * `pairs` pairs of coordinates; 1 <= pairs <= 8, default 8).  A tuning knob:
+ * results do not depend on it. */
+smc_status smc_batch_set_group(smc_batch *b, int32_t pairs, void *stream);
+
 /* Enables (1) or disables (0) graph capture of the step. */
 smc_status smc_batch_set_graph(smc_batch *b, int32_t enable);
 

@@ -50,6 +50,7 @@ constexpr int kBItems = 16;            // particles per thread and tile
 constexpr int kBTile = kBT * kBItems;  // particles per tile
 constexpr int kBChunk = 256;           // particles of an update / expand / copy workgroup
 constexpr int kChunksPerTile = kBTile / kBChunk;
+constexpr int kMaxGroup = 8;           // coordinate pairs of a proposal unit (16 columns of LDS)
 constexpr int kBSpin = 1 << 22;        // lookback poll bound
 constexpr int kBuckets = 8;            // dimension buckets (8b, 8b + 8]
 constexpr int kBMaxCap = 4096;
@@ -396,13 +397,19 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
         }
     }
     if (act) {
+        // rows r and r + 1 advance together (two independent FMA chains);
+        // each row still sums k = r, r + 1, ... in order
         double acc = 0.0;
 #pragma unroll
-        for (int r = 0; r < DB; ++r) {
-            double sr = 0.0;
+        for (int r = 0; r < DB; r += 2) {
+            double s0 = fma(sU[r * DB + r], tv[r], 0.0), s1 = 0.0;
 #pragma unroll
-            for (int k = r; k < DB; ++k) sr = fma(sU[r * DB + k], tv[k], sr);
-            acc = fma(sr, sr, acc);
+            for (int k = r + 1; k < DB; ++k) {
+                s0 = fma(sU[r * DB + k], tv[k], s0);
+                s1 = fma(sU[(r + 1) * DB + k], tv[k], s1);
+            }
+            acc = fma(s0, s0, acc);
+            acc = fma(s1, s1, acc);
         }
         const double lpn = S.log_norm - 0.5 * acc;
         lw = kInit ? lpn - (S.init_log_norm - 0.5 * glb(S.lp_scr)[i]) : lwg[i] + (lpn - lpg[i]);
@@ -1215,6 +1222,15 @@ smc_status smc_batch_particles(smc_batch *b, int32_t slot, double **h_x, double 
     if (h_x) *h_x = cur ? v.x_scr : v.x;
     if (h_lp) *h_lp = cur ? v.lp_scr : v.lp;
     return SMC_OK;
+}
+
+smc_status smc_batch_set_group(smc_batch *b, int32_t pairs, void *stream)
+{
+    if (!b || pairs < 1 || pairs > kMaxGroup) return SMC_E_ARG;
+    if (pairs == b->G) return SMC_OK;
+    b->G = pairs;
+    mirror_update(b);
+    return launch_tables(b, HS(stream)) == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
 
 smc_status smc_batch_set_graph(smc_batch *b, int32_t enable)

@@ -305,6 +305,10 @@ class Batch:
                                          _ptr(self.est) if est else None, _stream()),
                 "smc_batch_step")
 
+    def set_group(self, pairs: int) -> None:
+        L.check(self._lib.smc_batch_set_group(self.h, int(pairs), _stream()),
+                "smc_batch_set_group")
+
     def set_graph(self, enable: bool) -> None:
         L.check(self._lib.smc_batch_set_graph(self.h, 1 if enable else 0), "smc_batch_set_graph")
 

@@ -204,3 +204,30 @@ def test_batch_rejects_bad_arguments(smc, dev):
         B.attach(1, 100, 65, np.zeros(65), np.eye(65))   # d > 64
     with pytest.raises(smc.L.SmcError):
         B.detach(1)               # free slot
+
+
+def test_batch_unit_size_does_not_change_results(smc, dev):
+    print("batch unit size", flush=True)
+    specs = [spec(90 + k, *m) for k, m in enumerate(MIX)]
+    outs = []
+    for g in (1, 3, 8):
+        B = smc.Batch(len(MIX), device=dev)
+        B.set_group(g)
+        for slot, sp in enumerate(specs):
+            attach(B, slot, sp)
+        for _ in range(3):
+            B.step()
+        outs.append([(B.x(s).cpu().numpy(), B.estimates(s)["mean"]) for s in range(len(MIX))])
+    for other in outs[1:]:
+        for (xa, ea), (xb, eb) in zip(outs[0], other):
+            assert np.array_equal(bits(xa), bits(xb))
+            assert np.array_equal(bits(ea), bits(eb))
+    with pytest.raises(smc.L.SmcError):
+        B.set_group(9)
+
+
+def test_autotuner_picks_a_candidate(dev):
+    from paper_1905_10252_amd import tune
+    specs = I.batch_specs(count=12, seed=301)
+    r = tune.tune_group(specs, device=dev, steps=1)
+    assert r["best"] in tune.GROUP_CANDIDATES and set(r["ms"]) == set(tune.GROUP_CANDIDATES)
