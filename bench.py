@@ -145,7 +145,63 @@ def sampler_metrics(dev):
                                    "ms_per_iter": round(ms / k, 3)}
         del S
     out["batch256"] = batch_metrics(dev, timed_steps)
+    out["serving"] = serve_metrics(dev)
     return out
+
+
+def serve_metrics(dev, count=300, sequential=60):
+    """Continuous-batching server on a stream of mixed requests (Gaussian and
+    logistic-regression samplers, N up to 2^20, 20-100 iterations): capacity
+    from a closed loop (all requests queued at the start), then an open loop
+    with Poisson arrivals at 0.7 x capacity (p50/p99 latency, aggregate
+    sampler-iterations/s); and on the first ``sequential`` requests, the
+    server against serving them one at a time with per-request launches."""
+    import time
+    import torch
+    from paper_1905_10252_amd import inputs as I
+    from paper_1905_10252_amd import serve, smc
+
+    def reqs(rate, k=count):
+        return [serve.Request(i, **r) for i, r in enumerate(I.serve_requests(k, rate))]
+
+    def server():
+        return serve.Server(capacity=256, hbm_budget=96 << 30, device=dev)
+
+    res = {"requests": count}
+    closed = server().run(reqs(0.0))
+    cap = closed["requests"] / closed["wall_s"]
+    res["closed_loop"] = {k: round(v, 4) if isinstance(v, float) else v for k, v in closed.items()}
+    res["capacity_req_per_s"] = round(cap, 2)
+    opened = server().run(reqs(0.7 * cap))
+    res["open_loop_0.7"] = {k: round(v, 4) if isinstance(v, float) else v
+                            for k, v in opened.items()}
+    torch.cuda.synchronize()
+    # one at a time, each request on its own launches, against the server
+    sub = reqs(0.0, sequential)
+    t0 = time.perf_counter()
+    for r in sub:
+        p = r.params
+        if r.kind == "gauss":
+            b = smc.Batch(1, graph=False, device=dev)
+            b.attach(0, r.n, r.d, p["mean"], p["chol"], seed=r.seed, sampler_id=r.sampler_id,
+                     rw_sd=p["rw_sd"], init_sd=p["init_sd"])
+            for _ in range(r.iters):
+                b.step(info=False, est=True)
+        else:
+            s_ = smc.Sampler(r.n, r.d, "logreg", seed=r.seed, sampler_id=r.sampler_id, X=p["X"],
+                             y=p["y"], prior_var=p["prior_var"], precision="bf16",
+                             rw_sd=p["rw_sd"], init_sd=p["prior_var"] ** 0.5, device=dev)
+            for _ in range(r.iters):
+                s_.step(info=False, est=True)
+        torch.cuda.synchronize()
+    seq_wall = time.perf_counter() - t0
+    seq_iters = sum(r.iters for r in sub)
+    batched = server().run(reqs(0.0, sequential))
+    res["subset"] = {"requests": sequential,
+                     "one_at_a_time_sampler_iters_per_s": round(seq_iters / seq_wall, 1),
+                     "server_sampler_iters_per_s": round(batched["sampler_iters_per_s"], 1),
+                     "speedup": round(batched["sampler_iters_per_s"] / (seq_iters / seq_wall), 2)}
+    return res
 
 
 def batch_metrics(dev, timed_steps):

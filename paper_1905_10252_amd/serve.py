@@ -62,22 +62,31 @@ def request_bytes(r: Request) -> int:
 
 class Server:
     """Admits requests into a batch of ``capacity`` slots under an HBM budget
-    (bytes) and advances all admitted requests one iteration per tick."""
+    (bytes) and advances all admitted requests one iteration per tick.
+
+    A finished request's estimates are copied into pinned host memory behind
+    an event and the request is retired once that event has completed, so
+    ticks never wait for the device; its slot is free for the next tick at
+    once (everything runs in order on one stream).  ``keep_particles`` also
+    copies the final particles back (synchronously)."""
 
     def __init__(self, capacity: int = 256, hbm_budget: int = 64 << 30, *, graph: bool = True,
-                 device=None):
+                 keep_particles: bool = False, device=None):
         self.device = torch.device(device or "cuda")
         self.batch = smc.Batch(capacity, graph=graph, device=self.device)
         self.capacity = capacity
         self.budget = int(hbm_budget)
+        self.keep = keep_particles
         self.used = 0
         self.free = list(range(capacity))[::-1]
         self.queue = collections.deque()
         self.gauss = {}    # slot -> [request, iterations left]
         self.logreg = {}   # rid -> [request, sampler, iterations left]
+        self.retiring = [] # [request, event, host estimates, particles or None, d]
         self.iters_done = 0
         self.peak_used = 0
         self.peak_active = 0
+        self.t_event = None
 
     # --------------------------------------------------------------- admission
     def submit(self, r: Request) -> None:
@@ -115,62 +124,89 @@ class Server:
 
     # -------------------------------------------------------------------- tick
     def busy(self) -> bool:
-        return bool(self.gauss or self.logreg)
+        return bool(self.gauss or self.logreg or self.retiring)
 
-    def tick(self, now_fn) -> list:
-        """Admits, advances every admitted request by one iteration, retires
-        the finished ones (their results are read back); returns them."""
+    def _retire(self, r, est_dev, d, x_dev) -> None:
+        host = torch.empty(est_dev.numel(), dtype=torch.float64, pin_memory=True)
+        host.copy_(est_dev, non_blocking=True)
+        x = x_dev.cpu().numpy() if (self.keep and x_dev is not None) else None
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record()
+        self.retiring.append([r, ev, host, x, d])
+
+    def _collect(self, finish_time) -> list:
+        out, keep = [], []
+        for ent in self.retiring:
+            r, ev, host, x, d = ent
+            if not ev.query():
+                keep.append(ent)
+                continue
+            e = host.numpy()
+            r.result = {"mean": e[:d].copy(), "m2": e[d:2 * d].copy(),
+                        "rec_mean": e[2 * d:3 * d].copy(), "rec_m2": e[3 * d:4 * d].copy()}
+            if x is not None:
+                r.result["x"] = x
+            r.finished = finish_time(ev)
+            out.append(r)
+        self.retiring = keep
+        return out
+
+    def tick(self, now_fn, finish_time) -> list:
+        """Admits, advances every admitted request by one iteration, starts
+        retiring the finished ones; returns the requests whose results have
+        arrived on the host."""
         self._admit(now_fn())
-        if not self.busy():
-            return []
         if self.gauss:
             self.batch.step(info=False, est=True)
             self.iters_done += len(self.gauss)
         for ent in self.logreg.values():
             ent[1].step(info=False, est=True)
             self.iters_done += 1
-        done = []
         for slot, ent in list(self.gauss.items()):
             ent[1] -= 1
             if ent[1] == 0:
-                done.append(("gauss", slot, ent[0]))
+                r = ent[0]
+                o = slot * L.BATCH_EST_STRIDE
+                self._retire(r, self.batch.est[o:o + 4 * r.d], r.d,
+                             self.batch.x(slot) if self.keep else None)
+                self.batch.detach(slot)
+                self.free.append(slot)
+                del self.gauss[slot]
+                self.used -= request_bytes(r)
         for rid, ent in list(self.logreg.items()):
             ent[2] -= 1
             if ent[2] == 0:
-                done.append(("logreg", rid, ent[0]))
-        if not done:
-            return []
-        torch.cuda.current_stream().synchronize()
-        t = now_fn()
-        out = []
-        for kind, key, r in done:
-            if kind == "gauss":
-                r.result = {"x": self.batch.x(key).cpu().numpy(), **self.batch.estimates(key)}
-                self.batch.detach(key)
-                self.free.append(key)
-                del self.gauss[key]
-            else:
-                s = self.logreg.pop(key)[1]
-                r.result = {"x": s.x.cpu().numpy(), **s.estimates()}
-            self.used -= request_bytes(r)
-            r.finished = t
-            out.append(r)
-        return out
+                r, s = ent[0], ent[1]
+                self._retire(r, s.est[:4 * r.d], r.d, s.x if self.keep else None)
+                del self.logreg[rid]
+                self.used -= request_bytes(r)
+        return self._collect(finish_time)
 
     # --------------------------------------------------------------------- run
     def run(self, requests: list, *, clock: str = "wall") -> dict:
         """Serves ``requests`` (arrival times in seconds, or in ticks with
-        clock="tick") to completion; returns latency and throughput figures."""
+        clock="tick") to completion; returns latency and throughput figures.
+        With the wall clock a request finishes when its results reach the
+        host (device event time); with the tick clock, at its last tick."""
         for r in sorted(requests, key=lambda q: (q.arrival, q.rid)):
             self.submit(r)
         ticks = [0]
+        torch.cuda.current_stream().synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        start.record()
         t0 = time.perf_counter()
         if clock == "tick":
             def now():
                 return float(ticks[0])
+
+            def finish_time(ev):
+                return float(ticks[0])
         else:
             def now():
                 return time.perf_counter() - t0
+
+            def finish_time(ev):
+                return start.elapsed_time(ev) / 1e3
         finished = []
         while len(finished) < len(requests):
             if not self.busy() and self.queue and self.queue[0].arrival > now():
@@ -179,7 +215,9 @@ class Server:
                 else:
                     time.sleep(min(1e-3, max(0.0, self.queue[0].arrival - now())))
                 continue
-            finished += self.tick(now)
+            if not (self.gauss or self.logreg) and self.retiring:
+                self.retiring[0][1].synchronize()
+            finished += self.tick(now, finish_time)
             ticks[0] += 1
         torch.cuda.current_stream().synchronize()
         wall = time.perf_counter() - t0

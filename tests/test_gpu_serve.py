@@ -57,7 +57,7 @@ def test_serving_admits_under_budget_and_matches_alone(dev):
     from paper_1905_10252_amd import serve, smc
     reqs = small_requests(serve)
     budget = max(serve.request_bytes(r) for r in reqs) * 3
-    srv = serve.Server(capacity=4, hbm_budget=budget, device=dev)
+    srv = serve.Server(capacity=4, hbm_budget=budget, keep_particles=True, device=dev)
     stats = srv.run(reqs, clock="tick")
     assert stats["requests"] == len(reqs)
     assert srv.peak_used <= budget
@@ -66,6 +66,14 @@ def test_serving_admits_under_budget_and_matches_alone(dev):
     for r in reqs:
         assert r.admitted >= r.arrival
         assert r.finished - r.admitted >= r.iters - 1
+    # wall-clock serving of the same stream gives the same estimates
+    again = small_requests(serve)
+    for r in again:
+        r.arrival *= 1e-3  # ticks read as milliseconds
+    serve.Server(capacity=4, hbm_budget=budget, device=dev).run(again)
+    for a, b in zip(reqs, again):
+        for k in ("mean", "m2", "rec_mean", "rec_m2"):
+            assert np.array_equal(bits(a.result[k]), bits(b.result[k])), (a.rid, k)
     for r in reqs:
         ref = alone(smc, r, dev)
         assert np.array_equal(bits(r.result["x"]), bits(ref["x"])), r.rid
