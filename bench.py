@@ -262,6 +262,42 @@ def batch_metrics(dev, timed_steps):
     return res
 
 
+def only_workload(name, steps, warmup):
+    """One sampler workload alone (a profiling target): the Student-t sampler
+    or the bearing-only filter at N = 2^24 with resampling every iteration, or
+    one batched step of the 256-sampler workload; prints ms per iteration."""
+    import torch
+    from paper_1905_10252_amd import inputs as I
+    from paper_1905_10252_amd import smc
+    dev = torch.device("cuda:0")
+    n = 1 << 24
+    if name == "student":
+        S = smc.Sampler(n, 1, "student", seed=1, rw_sd=0.5, nu=5.0, mu=1.0,
+                        mode=smc.L.MODE_FORCE, device=dev)
+    elif name == "bearing":
+        B = I.BEARING
+        _, ys = I.bearing_track(warmup + steps + 1, 7)
+        S = smc.Sampler(n, 4, "bearing", seed=2, mean=B["x0"], init_sd=B["init_sd"], obs=ys,
+                        delta=B["delta"], obs_var=B["obs_var"], mode=smc.L.MODE_FORCE, device=dev)
+    else:
+        specs = I.batch_specs()
+        S = smc.Batch(len(specs), graph=False, device=dev)
+        for k, sp in enumerate(specs):
+            S.attach(k, sp["n"], sp["d"], sp["mean"], sp["chol"], seed=sp["seed"],
+                     sampler_id=sp["sampler_id"], rw_sd=sp["rw_sd"], init_sd=sp["init_sd"])
+    for _ in range(warmup):
+        S.step(info=False, est=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        S.step(info=False, est=False)
+    e1.record()
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": name, "steps": steps,
+                      "ms_per_iter": round(e0.elapsed_time(e1) / steps, 4)}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -272,11 +308,16 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one plain device copy of the 1 GiB particle array "
                          "(reference for hardware byte counters)")
+    ap.add_argument("--only", choices=("student", "bearing", "batch"), default=None,
+                    help="run only --steps iterations of one sampler workload (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only (the resample hot path on one "
               "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        only_workload(args.only, args.steps, args.warmup)
+        return
 
     import numpy as np
     import torch
