@@ -512,6 +512,323 @@ __global__ __launch_bounds__(256) void k_post_est(const Ctrl *ctrl, i64 n, int d
                                    s_acc[3][c - 1];
 }
 
+
+// ------------------------------------------------- small-N fused iteration
+// One workgroup of 1024 threads runs a whole iteration of Alg 2 for N <= 2048
+// particles of a cheap target (Gaussian d <= 16, Student-t): proposal and
+// weights, exact max, fixed-point weights and their inclusive prefix in LDS,
+// FP64 sums, estimates, the integer decision, c_t and recycling, then the
+// redistribution (ancestor by binary search on the LDS prefix) and reset.
+// Same arithmetic per particle and same integers as the multi-kernel path;
+// only the order of the FP64 sums differs.  It keeps the control block as
+// the multi-kernel path does and clears the other parity's max slots.
+constexpr int kSmallN = 2048, kSmallD = 16, kSmallT = 1024, kSmallI = kSmallN / kSmallT;
+
+template <int CTRL>
+__device__ inline double sdpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// sum of each 16-lane row, in the row's last lane (DPP only, no LDS trips)
+__device__ inline double srow16(double v)
+{
+    v += sdpp_f64<0x111>(v);
+    v += sdpp_f64<0x112>(v);
+    v += sdpp_f64<0x114>(v);
+    v += sdpp_f64<0x118>(v);
+    return v;
+}
+
+template <int kKind>
+__global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t, u64 r, int K,
+                                                     int mode, int ess_num, int ess_den,
+                                                     double *__restrict__ x,
+                                                     double *__restrict__ logw,
+                                                     double *__restrict__ lp,
+                                                     double *__restrict__ x_scr,
+                                                     double *__restrict__ lp_scr, Ctrl *ctrl,
+                                                     u64 *slots_other, double *rec_num,
+                                                     smc_resample_info *info, double *est,
+                                                     double reset)
+{
+    constexpr int NR = kSmallT / 16;  // 16-lane rows of the block
+    __shared__ double s_e[kSmallN];
+    __shared__ u64 s_S[kSmallN];
+    __shared__ double s_col[NR][2 * kSmallD];
+    __shared__ double s_tot[2 * kSmallD];
+    __shared__ double s_z[16], s_z2[16];
+    __shared__ u64 s_key[16], s_wsum[16], s_lo[16], s_hi[16];
+    __shared__ unsigned s_bad[16];
+    __shared__ double s_bc[4];
+    __shared__ u64 s_bu[3];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int d = a.d;
+    for (int k = tid; k < kSlots * kSlotStride; k += kSmallT) slots_other[k] = 0;
+
+    // proposal and weights (items tid + 1024 j)
+    u64 key = 0;
+    unsigned bad = 0;
+    for (int j = 0; j < kSmallI; ++j) {
+        const i64 i = tid + (i64)kSmallT * j;
+        const bool act = i < n;
+        double *xi = x + i * d;
+        double acc = 0.0;
+        for (int k = 0; 2 * k < d; ++k) {
+            double z[2];
+            normal_pair_wave(a.seed, kTagPropose, a.sampler, t, (uint32_t)i, (uint32_t)k, act,
+                             z[0], z[1]);
+            if (!act) continue;
+            for (int h = 0; h < 2; ++h) {
+                const int kk = 2 * k + h;
+                if (kk >= d) break;
+                const double xk = xi[kk] + a.rw_sd * z[h];
+                xi[kk] = xk;
+                if (kKind == SMC_TARGET_GAUSS) {
+                    const double tt = xk - a.mean[kk];
+                    acc = acc + (tt * tt) * a.prec[kk];
+                }
+            }
+        }
+        if (!act) continue;
+        double lpn;
+        if (kKind == SMC_TARGET_GAUSS) {
+            lpn = a.log_norm - 0.5 * acc;
+        } else {
+            const double tt = xi[0] - a.mu;
+            lpn = a.log_norm - a.hnu1 * det_log(1.0 + (tt * tt) * a.inv_nu);
+        }
+        const double lw = logw[i] + (lpn - lp[i]);
+        lp[i] = lpn;
+        logw[i] = lw;
+        s_e[i] = lw;
+        bad |= (lw != lw) | (lw == __builtin_huge_val());
+        const u64 kk = okey(lw);
+        key = kk > key ? kk : key;
+    }
+    key = wave_max_u64(key);
+    bad = wave_or(bad);
+    if (lane == 0) {
+        s_key[wid] = key;
+        s_bad[wid] = bad;
+    }
+    __syncthreads();
+    key = s_key[0];
+    bad = s_bad[0];
+    for (int w = 1; w < 16; ++w) {
+        key = s_key[w] > key ? s_key[w] : key;
+        bad |= s_bad[w];
+    }
+    const double m = okey_inv(key);
+
+    // fixed-point weights of consecutive items per thread, FP64 sums, prefix
+    const u64 top = 1ull << K;
+    double z = 0.0, z2 = 0.0;
+    U128 q2{0, 0};
+    u64 loc[kSmallI];
+    u64 run = 0;
+    for (int j = 0; j < kSmallI; ++j) {
+        const i64 i = (i64)tid * kSmallI + j;
+        u64 q = 0;
+        double e = 0.0;
+        if (i < n) {
+            e = det_exp(s_e[i] - m);  // s_e holds l_i here, e_i after this loop
+            if (e >= 0.0) {
+                z += e;
+                z2 += e * e;
+                q = (u64)floor(ldexp(e, K));
+                q = q > top ? top : q;
+                q2 = add128(q2, mul64(q, q));
+            } else {
+                e = 0.0;
+            }
+        }
+        run += q;
+        loc[j] = run;
+        if (i < n) s_e[i] = e;  // the thread's own items: no hazard
+    }
+    const u64 incl = wave_incl_scan_u64(run);
+    if (lane == 63) s_wsum[wid] = incl;
+    z = wave_sum_f64(z);
+    z2 = wave_sum_f64(z2);
+    q2 = wave_sum_u128(q2);
+    __syncthreads();
+    u64 wpre = 0;
+    for (int w = 0; w < wid; ++w) wpre += s_wsum[w];
+    const u64 pre = wpre + incl - run;
+    for (int j = 0; j < kSmallI; ++j) {
+        const i64 i = (i64)tid * kSmallI + j;
+        if (i < n) s_S[i] = pre + loc[j];
+    }
+    if (lane == 0) {
+        s_z[wid] = z;
+        s_z2[wid] = z2;
+        s_lo[wid] = q2.lo;
+        s_hi[wid] = q2.hi;
+    }
+    __syncthreads();
+
+    // estimate sums: a DPP sum per 16-lane row, rows in order
+    {
+        double s1[kSmallD], s2[kSmallD];
+        for (int k = 0; k < kSmallD; ++k) s1[k] = s2[k] = 0.0;
+        for (int j = 0; j < kSmallI; ++j) {
+            const i64 i = tid + (i64)kSmallT * j;
+            if (i >= n) continue;
+            const double e = s_e[i];
+#pragma unroll
+            for (int k = 0; k < kSmallD; ++k) {
+                if (k < d) {
+                    const double xv = x[i * d + k];
+                    const double ex = e * xv;
+                    s1[k] += ex;
+                    s2[k] += ex * xv;
+                }
+            }
+        }
+        const int prow = tid >> 4;
+        const bool last = (lane & 15) == 15;
+#pragma unroll
+        for (int k = 0; k < kSmallD; ++k) {
+            if (k < d) {
+                const double a1 = srow16(s1[k]), a2 = srow16(s2[k]);
+                if (last) {
+                    s_col[prow][k] = a1;
+                    s_col[prow][kSmallD + k] = a2;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < 2 * d) {
+        const int c = tid < d ? tid : kSmallD + (tid - d);
+        double acc = 0.0;
+        for (int rr = 0; rr < NR; ++rr) acc += s_col[rr][c];
+        s_tot[tid] = acc;
+    }
+    __syncthreads();
+
+    // decision, offset, log Z, ESS, c_t and recycling (one thread)
+    if (tid == 0) {
+        double Z = s_z[0], Z2 = s_z2[0];
+        U128 Q2{s_lo[0], s_hi[0]};
+        for (int w = 1; w < 16; ++w) {
+            Z += s_z[w];
+            Z2 += s_z2[w];
+            Q2 = add128(Q2, U128{s_lo[w], s_hi[w]});
+        }
+        const u64 S = s_S[n - 1];
+        unsigned err = 0;
+        if (bad) err = kErrNonfinite;
+        else if (key <= okey(-__builtin_huge_val())) err = kErrDegenerate;
+        int resample;
+        if (mode == SMC_MODE_FORCE) {
+            resample = 1;
+        } else if (mode == SMC_MODE_NEVER) {
+            resample = 0;
+        } else {
+            const U128 lhs = mul128_small(mul64(S, S), (u64)ess_den);
+            const U128 rhs = mul128_small(mul128_small(Q2, (u64)n), (u64)ess_num);
+            resample = lt128(lhs, rhs) ? 1 : 0;
+        }
+        if (err) resample = 0;
+        const u64 U = mul64(r, S).hi;
+        const double logZ = m + log(Z);
+        const double ess = (Z * Z) / Z2;
+        ctrl->mkey = key;
+        ctrl->m = m;
+        ctrl->err_call = err;
+        ctrl->spin_fail = 0;
+        if (err && !ctrl->err_latch) ctrl->err_latch = err;
+        ctrl->S = S;
+        ctrl->U = U;
+        ctrl->Q2lo = Q2.lo;
+        ctrl->Q2hi = Q2.hi;
+        ctrl->Z = Z;
+        ctrl->Z2 = Z2;
+        ctrl->logZ = logZ;
+        ctrl->ess = ess;
+        ctrl->K = K;
+        ctrl->resample = (unsigned)resample;
+        ctrl->pending = 0;
+        const double logc = logZ - ctrl->logZ_prev;
+        double sc = 1.0, den = ctrl->rec_den;
+        if (logc > ctrl->lc_max) {
+            sc = ctrl->rec_steps ? exp(ctrl->lc_max - logc) : 0.0;
+            den *= sc;
+            ctrl->lc_max = logc;
+        }
+        const double wgt = exp(logc - ctrl->lc_max);
+        den += wgt;
+        ctrl->rec_den = den;
+        ctrl->rec_steps += 1;
+        ctrl->log_c = logc;
+        ctrl->logZ_prev = (resample && !err) ? 0.0 : logZ;
+        if (info) {
+            info->m = m;
+            info->logZ = logZ;
+            info->ess = ess;
+            info->Z = Z;
+            info->Z2 = Z2;
+            info->S = S;
+            info->U = U;
+            info->Q2_hi = Q2.hi;
+            info->Q2_lo = Q2.lo;
+            info->K = K;
+            info->resampled = resample;
+            info->err = (int)err;
+            info->pad = 0;
+            info->log_c = logc;
+        }
+        s_bc[0] = sc;
+        s_bc[1] = wgt;
+        s_bc[2] = den;
+        s_bc[3] = Z;
+        s_bu[0] = S;
+        s_bu[1] = U;
+        s_bu[2] = (u64)resample;
+    }
+    __syncthreads();
+    if (tid < 2 * d) {
+        const double f = s_tot[tid] / s_bc[3];
+        const double num = rec_num[tid] * s_bc[0] + s_bc[1] * f;
+        rec_num[tid] = num;
+        if (est) {
+            est[tid] = f;
+            est[2 * d + tid] = num / s_bc[2];
+        }
+    }
+    if (!s_bu[2]) return;
+
+    // redistribution: output p takes row anc(p), the first j with
+    // N S_j + U >= (p + 1) S; staged in the scratch rows, then back in place
+    const u64 S = s_bu[0], U = s_bu[1];
+    for (int j = 0; j < kSmallI; ++j) {
+        const i64 p = tid + (i64)kSmallT * j;
+        if (p >= n) continue;
+        const U128 rhs = mul64((u64)(p + 1), S);
+        i64 lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const i64 mid = (lo + hi) >> 1;
+            if (lt128(add128(mul64((u64)n, s_S[mid]), U), rhs)) lo = mid + 1;
+            else hi = mid;
+        }
+        for (int k = 0; k < d; ++k) x_scr[p * d + k] = x[lo * d + k];
+        lp_scr[p] = lp[lo];
+    }
+    __syncthreads();
+    for (int j = 0; j < kSmallI; ++j) {
+        const i64 p = tid + (i64)kSmallT * j;
+        if (p >= n) continue;
+        for (int k = 0; k < d; ++k) x[p * d + k] = x_scr[p * d + k];
+        lp[p] = lp_scr[p];
+        logw[p] = reset;
+    }
+}
+
 // ------------------------------------------------------ cheap log-targets
 __global__ __launch_bounds__(256) void k_lp_cheap(TArgs a, i64 n, const double *x, double *lp)
 {
@@ -854,6 +1171,23 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
                     double *logw, smc_resample_info *info, double *est, hipStream_t s)
 {
     const int64_t n = c.n;
+    if (n <= kSmallN && c.d <= kSmallD &&
+        (c.target == SMC_TARGET_GAUSS || c.target == SMC_TARGET_STUDENT)) {
+        // small population: the whole iteration in one workgroup
+        const TArgs a = targs(c, w, false);
+        const uint64_t r = resample_word(c.seed, c.sampler_id, t);
+        u64 *other = w.slots + ((par & 1) ^ 1) * kSlots * kSlotStride;
+        const double reset = -std::log((double)n);
+        if (c.target == SMC_TARGET_GAUSS)
+            hipLaunchKernelGGL(k_small_step<SMC_TARGET_GAUSS>, dim3(1), dim3(kSmallT), 0, s, a,
+                               (i64)n, t, (u64)r, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp,
+                               w.x_scr, w.lp_scr, w.ctrl, other, w.rec_num, info, est, reset);
+        else
+            hipLaunchKernelGGL(k_small_step<SMC_TARGET_STUDENT>, dim3(1), dim3(kSmallT), 0, s, a,
+                               (i64)n, t, (u64)r, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp,
+                               w.x_scr, w.lp_scr, w.ctrl, other, w.rec_num, info, est, reset);
+        return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+    }
     if (launch_is<false>(c, w, par, t, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
     if (launch_quant_scan(w, logw, n, K, par, s) != hipSuccess) return SMC_E_DEVICE;
     const uint64_t r = resample_word(c.seed, c.sampler_id, t);

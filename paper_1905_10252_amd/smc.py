@@ -65,9 +65,11 @@ class Resampler:
         self._lib = lib
 
     def __del__(self):
-        if getattr(self, "ctx", None) and self.ctx.value:
-            self._lib.smc_destroy(self.ctx)
-            self.ctx = C.c_void_p()
+        # the handle is dropped, not reset: module globals may already be gone
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            self._lib.smc_destroy(ctx)
+            self.ctx = None
 
     def resample(self, logw: torch.Tensor, r: int, mode: int = L.MODE_AUTO,
                  ncopies: torch.Tensor | None = None, info: bool = True):
@@ -190,9 +192,11 @@ class Sampler:
         self.t = 0
 
     def __del__(self):
-        if getattr(self, "ctx", None) and self.ctx.value:
-            self._lib.smc_destroy(self.ctx)
-            self.ctx = C.c_void_p()
+        # the handle is dropped, not reset: module globals may already be gone
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            self._lib.smc_destroy(ctx)
+            self.ctx = None
 
     def step(self, info: bool = True, est: bool = True) -> None:
         L.check(self._lib.smc_step(self.ctx, _ptr(self.x), _ptr(self.logw),
@@ -257,9 +261,10 @@ class Batch:
         self.slots = {}
 
     def __del__(self):
-        if getattr(self, "h", None) and self.h.value:
-            self._lib.smc_batch_destroy(self.h)
-            self.h = C.c_void_p()
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self._lib.smc_batch_destroy(h)
+            self.h = None
 
     def attach(self, slot: int, n: int, d: int, mean, chol, *, seed: int = 0,
                sampler_id: int = 0, rw_sd: float = 0.5, init_mean: float = 0.0,

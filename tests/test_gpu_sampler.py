@@ -219,3 +219,38 @@ def test_logreg_force_step_structure(smc, dev):
     assert np.all(g.logw.cpu().numpy() == -math.log(n))
     gx = g.x.cpu().numpy()
     assert np.array_equal(bits(gx), bits(o.x)) or set(map(tuple, gx)) <= set(map(tuple, o.x))
+
+
+@pytest.mark.parametrize("n,d", [(2048, 16), (2049, 16), (1500, 5)])
+def test_gauss_small_population_paths(smc, dev, n, d):
+    """N <= 2048 and d <= 16 run as one fused workgroup; 2049 takes the
+    multi-kernel path.  Both are bit-exact against the oracle."""
+    _say("gauss small n=%d d=%d" % (n, d))
+    rng = np.random.default_rng(n + d)
+    mean, var = rng.standard_normal(d), rng.uniform(0.5, 2.0, d)
+    G, Or = pair_gauss(smc, dev, n, mean, var, 23, O.MODE_AUTO, rw_sd=0.4)
+    run_and_compare(G, Or, 5)
+
+
+def test_resample_call_after_fused_steps(smc, dev):
+    """smc_resample on a context whose steps ran fused: the max slots it uses
+    were left clear, so its exact max and integers match the oracle."""
+    import ctypes as C
+    import torch
+    g = I.GAUSS1D
+    G, Or = pair_gauss(smc, dev, g["n"], g["mean"], g["var"], 3, O.MODE_AUTO)
+    for _ in range(3):
+        G.step()
+        Or.step()
+    lib = smc.L.load()
+    for k in range(3):
+        lw = torch.from_numpy(np.random.default_rng(k).standard_normal(g["n"]) * (k + 1)).to(dev)
+        info = torch.zeros(smc.L.INFO_BYTES, dtype=torch.uint8, device=dev)
+        r = 0x9E3779B97F4A7C15 * (k + 1) & (2**64 - 1)
+        smc.L.check(lib.smc_resample(G.ctx, C.c_void_p(lw.data_ptr()), g["n"], r, O.MODE_FORCE,
+                                     None, C.c_void_p(info.data_ptr()), smc._stream()),
+                    "smc_resample")
+        got = smc.decode_info(info)
+        ref = O.resample(lw.cpu().numpy(), r, O.MODE_FORCE)[1]
+        for key in ("m", "S", "U", "Q2_hi", "Q2_lo", "K", "err"):
+            assert got[key] == ref[key], (k, key)
