@@ -8,7 +8,8 @@ every admitted request by one iteration, and retires the finished ones:
   - Gaussian requests (any N and d <= 64, full-precision target) share one
     batched step of ``smc.Batch``: all of them advance in the same launches;
   - logistic-regression requests each advance by one ``smc_step`` of their
-    own context (BF16 MFMA likelihood), on the same stream.
+    own context (BF16 MFMA likelihood), on a second stream, so their kernels
+    overlap the batched step on the device.
 
 Particle state stays on the device from admission to retirement.  A request's
 result depends only on the request: the batch gives every sampler the same
@@ -86,7 +87,8 @@ class Server:
         self.iters_done = 0
         self.peak_used = 0
         self.peak_active = 0
-        self.t_event = None
+        self.main = torch.cuda.current_stream(self.device)
+        self.side = torch.cuda.Stream(device=self.device)  # default priority
 
     # --------------------------------------------------------------- admission
     def submit(self, r: Request) -> None:
@@ -111,11 +113,12 @@ class Server:
                                   init_sd=p.get("init_sd", 3.0), mode=p.get("mode", L.MODE_AUTO))
                 self.gauss[slot] = [r, r.iters]
             else:
-                s = smc.Sampler(r.n, r.d, "logreg", seed=r.seed, sampler_id=r.sampler_id,
-                                X=p["X"], y=p["y"], prior_var=p["prior_var"],
-                                precision=p.get("precision", "bf16"), rw_sd=p["rw_sd"],
-                                init_sd=math.sqrt(p["prior_var"]), mode=p.get("mode", L.MODE_AUTO),
-                                device=self.device)
+                with torch.cuda.stream(self.side):
+                    s = smc.Sampler(r.n, r.d, "logreg", seed=r.seed, sampler_id=r.sampler_id,
+                                    X=p["X"], y=p["y"], prior_var=p["prior_var"],
+                                    precision=p.get("precision", "bf16"), rw_sd=p["rw_sd"],
+                                    init_sd=math.sqrt(p["prior_var"]),
+                                    mode=p.get("mode", L.MODE_AUTO), device=self.device)
                 self.logreg[r.rid] = [r, s, r.iters]
             self.used += request_bytes(r)
             self.peak_used = max(self.peak_used, self.used)
@@ -126,12 +129,13 @@ class Server:
     def busy(self) -> bool:
         return bool(self.gauss or self.logreg or self.retiring)
 
-    def _retire(self, r, est_dev, d, x_dev) -> None:
-        host = torch.empty(est_dev.numel(), dtype=torch.float64, pin_memory=True)
-        host.copy_(est_dev, non_blocking=True)
-        x = x_dev.cpu().numpy() if (self.keep and x_dev is not None) else None
-        ev = torch.cuda.Event(enable_timing=True)
-        ev.record()
+    def _retire(self, r, est_dev, d, x_dev, stream) -> None:
+        with torch.cuda.stream(stream):
+            host = torch.empty(est_dev.numel(), dtype=torch.float64, pin_memory=True)
+            host.copy_(est_dev, non_blocking=True)
+            x = x_dev.cpu().numpy() if (self.keep and x_dev is not None) else None
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
         self.retiring.append([r, ev, host, x, d])
 
     def _collect(self, finish_time) -> list:
@@ -159,16 +163,18 @@ class Server:
         if self.gauss:
             self.batch.step(info=False, est=True)
             self.iters_done += len(self.gauss)
-        for ent in self.logreg.values():
-            ent[1].step(info=False, est=True)
-            self.iters_done += 1
+        if self.logreg:
+            with torch.cuda.stream(self.side):
+                for ent in self.logreg.values():
+                    ent[1].step(info=False, est=True)
+            self.iters_done += len(self.logreg)
         for slot, ent in list(self.gauss.items()):
             ent[1] -= 1
             if ent[1] == 0:
                 r = ent[0]
                 o = slot * L.BATCH_EST_STRIDE
                 self._retire(r, self.batch.est[o:o + 4 * r.d], r.d,
-                             self.batch.x(slot) if self.keep else None)
+                             self.batch.x(slot) if self.keep else None, self.main)
                 self.batch.detach(slot)
                 self.free.append(slot)
                 del self.gauss[slot]
@@ -177,7 +183,9 @@ class Server:
             ent[2] -= 1
             if ent[2] == 0:
                 r, s = ent[0], ent[1]
-                self._retire(r, s.est[:4 * r.d], r.d, s.x if self.keep else None)
+                self._retire(r, s.est[:4 * r.d], r.d, s.x if self.keep else None, self.side)
+                # its buffers were allocated on the side stream: freeing them
+                # with the sampler is ordered after its last use there
                 del self.logreg[rid]
                 self.used -= request_bytes(r)
         return self._collect(finish_time)
@@ -219,7 +227,7 @@ class Server:
                 self.retiring[0][1].synchronize()
             finished += self.tick(now, finish_time)
             ticks[0] += 1
-        torch.cuda.current_stream().synchronize()
+        torch.cuda.synchronize(self.device)
         wall = time.perf_counter() - t0
         lat = sorted(r.latency for r in finished)
         iters = sum(r.iters for r in finished)
