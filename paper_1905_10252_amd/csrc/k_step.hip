@@ -173,11 +173,14 @@ struct Online {
 // DT > 0: d == DT and the estimate sums are accumulated in one pass; DT == 0:
 // any d, sums in a second pass over the block's particles.  The particle filter
 // takes its estimate after resampling, so its update kernel skips them.
-template <int kKind, bool kInit, int DT>
+// kOut: the proposal and its log-target go to xo / lpo (the redistribution
+// then maps them back into x); otherwise they overwrite x / lp in place.
+template <int kKind, bool kInit, int DT, bool kOut>
 __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *__restrict__ x,
                                             double *__restrict__ logw, double *__restrict__ lp,
                                             u64 *slots_p, u64 *status, int n_status,
-                                            double *is_part)
+                                            double *is_part, double *__restrict__ xo,
+                                            double *__restrict__ lpo)
 {
     constexpr bool kEst = kKind != SMC_TARGET_BEARING;
     constexpr int DA = DT > 0 ? DT : 1;
@@ -198,6 +201,7 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
         const i64 i = base + (tid & 63);
         const bool act = i < n;
         double *xi = x + i * d;
+        double *xw = (kOut ? xo : x) + i * d;
         if (kKind == SMC_TARGET_BEARING) {
             double z[4];
             normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, 0u, act, z[0], z[1]);
@@ -217,10 +221,10 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
                 const double n1 = xi[1] + v1;
                 const double n2 = (xi[2] + a.delta * xi[3]) + v2;
                 const double n3 = xi[3] + v3;
-                xi[0] = n0;
-                xi[1] = n1;
-                xi[2] = n2;
-                xi[3] = n3;
+                xw[0] = n0;
+                xw[1] = n1;
+                xw[2] = n2;
+                xw[3] = n3;
                 const double e = a.obs[t - 1] - det_atan(n2 / n0);
                 lw = logw[i] + (a.obs_log_norm - 0.5 * ((e * e) * a.obs_prec));
             }
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
                 const int kk = 2 * k + h;
                 if (kk >= d) break;
                 const double xk = kInit ? a.init_mean + a.init_sd * z[h] : xi[kk] + a.rw_sd * z[h];
-                xi[kk] = xk;
+                xw[kk] = xk;
                 if (DT > 0 && kk < DT) xv[kk] = xk;
                 if (a.thb) a.thb[i * a.dp + kk] = to_bf16(xk);
                 if (kKind == SMC_TARGET_GAUSS) {
@@ -263,12 +267,12 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
         if (kKind == SMC_TARGET_GAUSS) {
             lpn = a.log_norm - 0.5 * acc;
         } else {
-            const double tt = xi[0] - a.mu;
+            const double tt = xw[0] - a.mu;
             const double w = 1.0 + (tt * tt) * a.inv_nu;
             lpn = a.log_norm - a.hnu1 * det_log(w);
         }
         const double lw = kInit ? lpn - lq0 : logw[i] + (lpn - lp[i]);
-        lp[i] = lpn;
+        (kOut ? lpo : lp)[i] = lpn;
         logw[i] = lw;
         bad |= (lw != lw) | (lw == __builtin_huge_val());
         const u64 kk = okey(lw);
@@ -282,7 +286,7 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
         slot_publish(slots_p, bk, bad);
         return;
     }
-    is_block_finish(n, d, x, logw, key, bad, slots_p, is_part);
+    is_block_finish(n, d, kOut ? xo : x, logw, key, bad, slots_p, is_part);
 }
 
 template <bool kInit>
@@ -464,6 +468,79 @@ __global__ __launch_bounds__(256) void k_copyback_est(const Ctrl *ctrl, i64 n,
     __syncthreads();
     double *part = is_part + (i64)blockIdx.x * (2 + 2 * DT);
     for (int c = tid; c < 2 + 2 * DT; c += 256)
+        part[c] = c == 0 ? m : ((s_acc[0][c - 1] + s_acc[1][c - 1]) + s_acc[2][c - 1]) +
+                                   s_acc[3][c - 1];
+}
+
+// After a redistribution straight into x: weights reset to 1/N when it
+// resampled; with DT > 0 (the particle filter) also the post-resampling sums
+// of Alg 1, equal weights when resampled, else the current ones.  A step that
+// found an error redistributes nothing: the proposal (and its log-target) is
+// copied into place instead, as the in-place update would have left it.
+template <int DT>
+__global__ __launch_bounds__(256) void k_reset_est(const Ctrl *ctrl, i64 n, int d,
+                                                   double *__restrict__ x,
+                                                   const double *__restrict__ x_scr,
+                                                   double *__restrict__ lp,
+                                                   const double *__restrict__ lp_scr,
+                                                   double *__restrict__ logw, double reset,
+                                                   double *is_part)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
+    if (ctrl->err_call) {
+        for (i64 e = gtid; e < n * d; e += gsz) x[e] = x_scr[e];
+        if (lp_scr)
+            for (i64 i = gtid; i < n; i += gsz) lp[i] = lp_scr[i];
+        if (DT > 0 && tid == 0) {  // no estimate for a failed step
+            double *part = is_part + (i64)blockIdx.x * (2 + 2 * DT);
+            part[0] = -__builtin_huge_val();
+            for (int c = 1; c < 2 + 2 * DT; ++c) part[c] = 0.0;
+        }
+        return;
+    }
+    const bool rs = ctrl->resample;
+    if (DT == 0) {
+        if (rs)
+            for (i64 i = gtid; i < n; i += gsz) logw[i] = reset;
+        return;
+    }
+    constexpr int DA = DT > 0 ? DT : 1;
+    __shared__ double s_acc[4][1 + 2 * DA];
+    const double m = rs ? reset : ctrl->m;
+    double e0 = 0.0, e1[DA], e2[DA];
+    for (int k = 0; k < DA; ++k) e1[k] = e2[k] = 0.0;
+    for (i64 i = gtid; i < n; i += gsz) {
+        double e;
+        if (rs) {
+            logw[i] = reset;
+            e = 1.0;
+        } else {
+            e = det_exp(logw[i] - m);
+        }
+        e0 += e;
+        for (int k = 0; k < DA; ++k) {
+            const double xk = x[i * DA + k];
+            const double ex = e * xk;
+            e1[k] += ex;
+            e2[k] += ex * xk;
+        }
+    }
+    e0 = wave_sum_f64(e0);
+    for (int k = 0; k < DA; ++k) {
+        e1[k] = wave_sum_f64(e1[k]);
+        e2[k] = wave_sum_f64(e2[k]);
+    }
+    if (lane == 0) {
+        s_acc[wid][0] = e0;
+        for (int k = 0; k < DA; ++k) {
+            s_acc[wid][1 + k] = e1[k];
+            s_acc[wid][1 + DA + k] = e2[k];
+        }
+    }
+    __syncthreads();
+    double *part = is_part + (i64)blockIdx.x * (2 + 2 * DA);
+    for (int c = tid; c < 2 + 2 * DA; c += 256)
         part[c] = c == 0 ? m : ((s_acc[0][c - 1] + s_acc[1][c - 1]) + s_acc[2][c - 1]) +
                                    s_acc[3][c - 1];
 }
@@ -1069,15 +1146,21 @@ hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_
 
 template <int kKind, bool kInit, int DT>
 void launch_is_k(dim3 g, hipStream_t s, const TArgs &a, i64 n, uint32_t t, double *x, double *logw,
-                 const Work &w, u64 *sp)
+                 const Work &w, u64 *sp, bool out)
 {
-    hipLaunchKernelGGL((k_is<kKind, kInit, DT>), g, dim3(256), 0, s, a, n, t, x, logw, w.lp, sp,
-                       w.status, w.n_tiles, w.is_part);
+    if (!kInit && out)
+        hipLaunchKernelGGL((k_is<kKind, false, DT, true>), g, dim3(256), 0, s, a, n, t, x, logw,
+                           w.lp, sp, w.status, w.n_tiles, w.is_part, w.x_scr, w.lp_scr);
+    else
+        hipLaunchKernelGGL((k_is<kKind, kInit, DT, false>), g, dim3(256), 0, s, a, n, t, x, logw,
+                           w.lp, sp, w.status, w.n_tiles, w.is_part, (double *)nullptr,
+                           (double *)nullptr);
 }
 
+// out: the proposal goes to the workspace copies (x_scr, lp_scr).
 template <bool kInit>
 hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, double *x,
-                     double *logw, hipStream_t s)
+                     double *logw, hipStream_t s, bool out = false)
 {
     const TArgs a = targs(c, w, is_bf16(c));
     const dim3 g(w.is_grid);
@@ -1085,18 +1168,19 @@ hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, do
     u64 *sp = w.slots + (par & 1) * kSlots * kSlotStride;
     switch (c.target) {
     case SMC_TARGET_GAUSS:
-        if (c.d == 1) launch_is_k<SMC_TARGET_GAUSS, kInit, 1>(g, s, a, n, t, x, logw, w, sp);
-        else if (c.d == 4) launch_is_k<SMC_TARGET_GAUSS, kInit, 4>(g, s, a, n, t, x, logw, w, sp);
-        else launch_is_k<SMC_TARGET_GAUSS, kInit, 0>(g, s, a, n, t, x, logw, w, sp);
+        if (c.d == 1) launch_is_k<SMC_TARGET_GAUSS, kInit, 1>(g, s, a, n, t, x, logw, w, sp, out);
+        else if (c.d == 4)
+            launch_is_k<SMC_TARGET_GAUSS, kInit, 4>(g, s, a, n, t, x, logw, w, sp, out);
+        else launch_is_k<SMC_TARGET_GAUSS, kInit, 0>(g, s, a, n, t, x, logw, w, sp, out);
         break;
     case SMC_TARGET_STUDENT:
-        launch_is_k<SMC_TARGET_STUDENT, kInit, 1>(g, s, a, n, t, x, logw, w, sp);
+        launch_is_k<SMC_TARGET_STUDENT, kInit, 1>(g, s, a, n, t, x, logw, w, sp, out);
         break;
     case SMC_TARGET_BEARING:
-        launch_is_k<SMC_TARGET_BEARING, kInit, 4>(g, s, a, n, t, x, logw, w, sp);
+        launch_is_k<SMC_TARGET_BEARING, kInit, 4>(g, s, a, n, t, x, logw, w, sp, out);
         break;
     case SMC_TARGET_LOGREG:
-        launch_is_k<SMC_TARGET_LOGREG, kInit, 0>(g, s, a, n, t, x, logw, w, sp);
+        launch_is_k<SMC_TARGET_LOGREG, kInit, 0>(g, s, a, n, t, x, logw, w, sp, false);
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
         if (logreg_lp(c, w, x, n, w.lp_new, true, s) != hipSuccess) return hipErrorLaunchFailure;
         hipLaunchKernelGGL(k_reweight<kInit>, g, dim3(256), 0, s, n, c.d, x, w.lp_new, logw,
@@ -1114,7 +1198,7 @@ template <int kKind, int DT>
 int resident_blocks()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_is<kKind, false, DT>, 256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_is<kKind, false, DT, false>, 256, 0) !=
         hipSuccess)
         return 0;
     return nb;
@@ -1188,22 +1272,43 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
                                w.x_scr, w.lp_scr, w.ctrl, other, w.rec_num, info, est, reset);
         return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
     }
-    if (launch_is<false>(c, w, par, t, x, logw, s) != hipSuccess) return SMC_E_DEVICE;
+    const bool pf = c.target == SMC_TARGET_BEARING;
+    // With resampling forced every iteration the proposal goes to the
+    // workspace copy and the redistribution writes straight into x (an
+    // identity copy if the step found an error): no copy back.  With the ESS
+    // rule it is updated in place, and only resampling steps move rows.
+    const bool fwd = c.mode == SMC_MODE_FORCE && c.target != SMC_TARGET_LOGREG;
+    if (launch_is<false>(c, w, par, t, x, logw, s, fwd) != hipSuccess) return SMC_E_DEVICE;
     if (launch_quant_scan(w, logw, n, K, par, s) != hipSuccess) return SMC_E_DEVICE;
     const uint64_t r = resample_word(c.seed, c.sampler_id, t);
     if (launch_decide(w, par, n, K, r, c.mode, c.ess_num, c.ess_den, info, s) != hipSuccess)
         return SMC_E_DEVICE;
-    const bool pf = c.target == SMC_TARGET_BEARING;
     if (!pf) {  // Alg 2 estimates come before resampling
         hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
                            w.is_grid, c.d, w.rec_num, est, info, 0);
         if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     }
-    // the particle filter carries no cached log-target
+    const double reset = -std::log((double)n);
+    if (fwd) {
+        // the particle filter carries no cached log-target
+        if (launch_expand(w, n, 0, w.x_scr, x, c.d * 8, pf ? nullptr : w.lp_scr,
+                          pf ? nullptr : w.lp, 8, nullptr, nullptr, s, false) != hipSuccess)
+            return SMC_E_DEVICE;
+        if (pf) {  // Alg 1 takes the mean after resampling
+            hipLaunchKernelGGL(k_reset_est<4>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)n,
+                               c.d, x, w.x_scr, (double *)nullptr, (const double *)nullptr,
+                               logw, reset, w.is_part);
+            hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
+                               w.is_grid, c.d, w.rec_num, est, info, 0);
+        } else {
+            hipLaunchKernelGGL(k_reset_est<0>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)n,
+                               c.d, x, w.x_scr, w.lp, w.lp_scr, logw, reset, w.is_part);
+        }
+        return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+    }
     if (launch_expand(w, n, 0, x, w.x_scr, c.d * 8, pf ? nullptr : w.lp,
                       pf ? nullptr : w.lp_scr, 8, nullptr, nullptr, s, true) != hipSuccess)
         return SMC_E_DEVICE;
-    const double reset = -std::log((double)n);
     if (pf) {  // Alg 1 takes the mean after resampling
         hipLaunchKernelGGL(k_copyback_est<4>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl,
                            (i64)n, x, w.x_scr, logw, reset, w.is_part);

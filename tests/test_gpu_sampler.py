@@ -254,3 +254,22 @@ def test_resample_call_after_fused_steps(smc, dev):
         ref = O.resample(lw.cpu().numpy(), r, O.MODE_FORCE)[1]
         for key in ("m", "S", "U", "Q2_hi", "Q2_lo", "K", "err"):
             assert got[key] == ref[key], (k, key)
+
+
+def test_forced_and_in_place_paths_agree_on_an_error_step(smc, dev):
+    """A target with zero density everywhere (variance 1e-320, so the
+    precision overflows) makes the step fail on the device: the forced path
+    (proposal written to the workspace copy) and the in-place path report the
+    same error, resample nothing and leave the same proposal in x."""
+    _say("degenerate step, forced vs in place")
+    n, d = 5000, 2
+    res = []
+    for mode in (O.MODE_FORCE, O.MODE_AUTO):
+        g = smc.Sampler(n, d, "gauss", seed=4, rw_sd=0.5, mean=[0.0, 0.0], var=[1e-320, 1e-320],
+                        mode=mode, device=dev)
+        g.sync_error()
+        g.step()
+        res.append((g.sync_error(), g.x.cpu().numpy().copy(), g.info()["resampled"]))
+    assert res[0][0] != 0 and res[0][0] == res[1][0]
+    assert res[0][2] == 0 and res[1][2] == 0
+    assert np.array_equal(bits(res[0][1]), bits(res[1][1]))
