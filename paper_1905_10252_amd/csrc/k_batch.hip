@@ -272,6 +272,7 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
     const int d = S.d;
     // a unit is one chunk of 256 particles and a group of G coordinate pairs
     // (all pairs at initialisation, where log q0 sums over the whole row)
+    __shared__ uint4 s_xch[4][64];  // normal generator exchange, one row per wave
     const int npair = (d + 1) / 2;
     const int ng = kInit ? 1 : (npair + G - 1) / G;
     const int chunk = unit / ng, grp = unit - chunk * ng;
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
         for (int k2 = kp0; k2 < kp1; ++k2) {
             double z[2];
             normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)i, (uint32_t)k2, act, z[0],
-                             z[1]);
+                             z[1], s_xch[tid >> 6]);
             const int c = 2 * k2 - k0;
             if (act) {
                 sx[tid][c] = sx[tid][c] + S.rw_sd * z[0];
@@ -318,7 +319,8 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
     for (int k2 = kp0; k2 < kp1; ++k2) {
         const int k0 = 2 * k2;
         double z[2];
-        normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)i, (uint32_t)k2, act, z[0], z[1]);
+        normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)i, (uint32_t)k2, act, z[0], z[1],
+                         s_xch[tid >> 6]);
         if (act) {
             for (int h = 0; h < 2; ++h) {
                 const int kk = k0 + h;

@@ -184,6 +184,7 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
 {
     constexpr bool kEst = kKind != SMC_TARGET_BEARING;
     constexpr int DA = DT > 0 ? DT : 1;
+    __shared__ uint4 s_xch[4][64];  // normal generator exchange, one row per wave
     const int tid = threadIdx.x;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
     if (kKind != SMC_TARGET_LOGREG)
@@ -204,8 +205,10 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
         double *xw = (kOut ? xo : x) + i * d;
         if (kKind == SMC_TARGET_BEARING) {
             double z[4];
-            normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, 0u, act, z[0], z[1]);
-            normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, 1u, act, z[2], z[3]);
+            normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, 0u, act, z[0], z[1],
+                             s_xch[tid >> 6]);
+            normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, 1u, act, z[2], z[3],
+                             s_xch[tid >> 6]);
             if (!act) continue;
             double lw;
             if (kInit) {
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
         for (int k = 0; 2 * k < d; ++k) {
             double z[2];
             normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, (uint32_t)k, act, z[0],
-                             z[1]);
+                             z[1], s_xch[tid >> 6]);
             if (!act) continue;
             for (int h = 0; h < 2; ++h) {
                 const int kk = 2 * k + h;
@@ -632,10 +635,11 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t,
                                                      smc_resample_info *info, double *est,
                                                      double reset)
 {
-    constexpr int NR = kSmallT / 16;  // 16-lane rows of the block
+    constexpr int NW = kSmallT / 64;  // waves of the block
     __shared__ double s_e[kSmallN];
     __shared__ u64 s_S[kSmallN];
-    __shared__ double s_col[NR][2 * kSmallD];
+    __shared__ double s_col[NW][2 * kSmallD];
+    __shared__ uint4 s_xch[NW][64];
     __shared__ double s_tot[2 * kSmallD];
     __shared__ double s_z[16], s_z2[16];
     __shared__ u64 s_key[16], s_wsum[16], s_lo[16], s_hi[16];
@@ -657,7 +661,7 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t,
         for (int k = 0; 2 * k < d; ++k) {
             double z[2];
             normal_pair_wave(a.seed, kTagPropose, a.sampler, t, (uint32_t)i, (uint32_t)k, act,
-                             z[0], z[1]);
+                             z[0], z[1], s_xch[wid]);
             if (!act) continue;
             for (int h = 0; h < 2; ++h) {
                 const int kk = 2 * k + h;
@@ -766,15 +770,18 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t,
                 }
             }
         }
-        const int prow = tid >> 4;
-        const bool last = (lane & 15) == 15;
+        // a DPP sum per 16-lane row, then the wave's four rows in order
 #pragma unroll
         for (int k = 0; k < kSmallD; ++k) {
             if (k < d) {
                 const double a1 = srow16(s1[k]), a2 = srow16(s2[k]);
-                if (last) {
-                    s_col[prow][k] = a1;
-                    s_col[prow][kSmallD + k] = a2;
+                const double w1 = ((__shfl(a1, 15) + __shfl(a1, 31)) + __shfl(a1, 47)) +
+                                  __shfl(a1, 63);
+                const double w2 = ((__shfl(a2, 15) + __shfl(a2, 31)) + __shfl(a2, 47)) +
+                                  __shfl(a2, 63);
+                if (lane == 0) {
+                    s_col[wid][k] = w1;
+                    s_col[wid][kSmallD + k] = w2;
                 }
             }
         }
@@ -783,7 +790,7 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t,
     if (tid < 2 * d) {
         const int c = tid < d ? tid : kSmallD + (tid - d);
         double acc = 0.0;
-        for (int rr = 0; rr < NR; ++rr) acc += s_col[rr][c];
+        for (int w = 0; w < NW; ++w) acc += s_col[w][c];
         s_tot[tid] = acc;
     }
     __syncthreads();

@@ -6,7 +6,8 @@
 // logarithm for every attempt in which some lane accepts.  Here every lane
 // first tries attempt 0 of its own pair; the pairs still pending are then
 // spread over the whole wave, L = floor(64 / pending) lanes per pair, each
-// lane trying one later attempt of its pair.  A pair takes the lowest attempt
+// lane trying one later attempt of its pair (jobs and results pass through a
+// per-wave LDS buffer).  A pair takes the lowest attempt
 // that accepted, which is the draw the sequential definition takes, and the
 // logarithm runs once per lane at the end.  All 64 lanes must call it in
 // convergent control flow; lanes without a pair pass active = false.
@@ -18,21 +19,6 @@
 #include "det.hpp"
 
 namespace smc {
-
-// Position of the n-th (0-based) set bit of m; requires n < popcount(m).
-__device__ inline int nth_set_bit(uint64_t m, int n)
-{
-    int pos = 0;
-#pragma unroll
-    for (int sh = 32; sh; sh >>= 1) {
-        const int c = __popcll((m >> pos) & ((1ull << sh) - 1ull));
-        if (n >= c) {
-            n -= c;
-            pos += sh;
-        }
-    }
-    return pos;
-}
 
 __device__ inline bool polar_uniforms(uint64_t seed, uint32_t tag, uint32_t sampler, uint32_t t,
                                       uint32_t idx, uint32_t sub, double &v1, double &v2)
@@ -46,9 +32,11 @@ __device__ inline bool polar_uniforms(uint64_t seed, uint32_t tag, uint32_t samp
     return s > 0.0 && s < 1.0;
 }
 
+// xch: this wave's 64-entry exchange buffer in LDS (16 bytes a lane).  Lanes
+// of one wave read and write it in program order, so no barrier is needed.
 __device__ inline void normal_pair_wave(uint64_t seed, uint32_t tag, uint32_t sampler, uint32_t t,
                                         uint32_t idx, uint32_t pair, bool active, double &z1,
-                                        double &z2)
+                                        double &z2, uint4 *xch)
 {
     constexpr uint32_t kAttempts = 32;
     const int lane = (int)__lane_id();
@@ -60,30 +48,37 @@ __device__ inline void normal_pair_wave(uint64_t seed, uint32_t tag, uint32_t sa
     while (pend) {
         const int r = __popcll(pend);
         const int L = 64 / r;
+        const bool own = (pend >> lane) & 1ull;
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+            (unsigned)(pend >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)pend, 0u));
+        // pending pair number `rank` is posted at entry `rank`; helpers of
+        // pair j (L lanes each) read entry j and try the next L attempts
+        if (own) xch[rank] = make_uint4(idx, pair, next, 0u);
+        __builtin_amdgcn_wave_barrier();
         const int j = lane / L, k = lane - j * L;
         const bool helper = j < r;
-        const int owner = helper ? nth_set_bit(pend, j) : lane;
-        const uint32_t o_idx = (uint32_t)__shfl((int)idx, owner);
-        const uint32_t o_pair = (uint32_t)__shfl((int)pair, owner);
-        const uint32_t a = (uint32_t)__shfl((int)next, owner) + (uint32_t)k;
+        const uint4 job = helper ? xch[j] : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t a = job.z + (uint32_t)k;
         double h1 = 0.0, h2 = 0.0;
         const bool hok = helper && a < kAttempts &&
-                         polar_uniforms(seed, tag, sampler, t, o_idx, (o_pair << 16) | a, h1, h2);
+                         polar_uniforms(seed, tag, sampler, t, job.x, (job.y << 16) | a, h1, h2);
         const uint64_t acc = __ballot(hok);
-        const bool own = (pend >> lane) & 1ull;
-        const int rank = __popcll(pend & ((1ull << lane) - 1ull));
+        __builtin_amdgcn_wave_barrier();
+        xch[lane] = make_uint4((uint32_t)__double2loint(h1), (uint32_t)__double2hiint(h1),
+                               (uint32_t)__double2loint(h2), (uint32_t)__double2hiint(h2));
+        __builtin_amdgcn_wave_barrier();
         const uint64_t seg = own ? (acc >> (rank * L)) & (L == 64 ? ~0ull : ((1ull << L) - 1ull))
                                  : 0ull;
-        const int src = seg ? rank * L + __ffsll((long long)seg) - 1 : lane;
-        const double f1 = __shfl(h1, src), f2 = __shfl(h2, src);
         if (seg) {
-            v1 = f1;
-            v2 = f2;
+            const uint4 h = xch[rank * L + __ffsll((long long)seg) - 1];
+            v1 = __hiloint2double((int)h.y, (int)h.x);
+            v2 = __hiloint2double((int)h.w, (int)h.z);
             ok = true;
         } else if (own) {
             next += (uint32_t)L;
             dead = next >= kAttempts;
         }
+        __builtin_amdgcn_wave_barrier();
         pend = __ballot(own && !ok && !dead);
     }
     if (ok) {
