@@ -13,8 +13,9 @@ every admitted request by one iteration, and retires the finished ones:
 
 Particle state stays on the device from admission to retirement.  A request's
 result depends only on the request: the batch gives every sampler the same
-bits alone and in a mix.  All device work is the library's; this module only
-schedules it and keeps time.
+bits alone and in a mix.  All device work is the library's (``DeviceBackend``);
+the scheduler (``Server``) only decides what runs in which tick and keeps time,
+and runs over any backend with the same methods.
 """
 from __future__ import annotations
 
@@ -61,34 +62,113 @@ def request_bytes(r: Request) -> int:
     return 8 * r.n * (2 * r.d + 16) + 2 * r.n * dp + 2 * m * dp + 8 * m * (r.d + 1) + (1 << 16)
 
 
-class Server:
-    """Admits requests into a batch of ``capacity`` slots under an HBM budget
-    (bytes) and advances all admitted requests one iteration per tick.
+class DeviceBackend:
+    """The device side of a server: one ``smc.Batch`` of ``capacity`` slots
+    for the Gaussian requests, one ``smc.Sampler`` context per
+    logistic-regression request on a second stream, and retirement of
+    results through pinned host memory behind events."""
 
-    A finished request's estimates are copied into pinned host memory behind
-    an event and the request is retired once that event has completed, so
-    ticks never wait for the device; its slot is free for the next tick at
-    once (everything runs in order on one stream).  ``keep_particles`` also
-    copies the final particles back (synchronously)."""
-
-    def __init__(self, capacity: int = 256, hbm_budget: int = 64 << 30, *, graph: bool = True,
-                 keep_particles: bool = False, device=None):
+    def __init__(self, capacity: int, *, graph: bool = True, keep_particles: bool = False,
+                 device=None):
         self.device = torch.device(device or "cuda")
         self.batch = smc.Batch(capacity, graph=graph, device=self.device)
+        self.keep = keep_particles
+        self.main = torch.cuda.current_stream(self.device)
+        self.side = torch.cuda.Stream(device=self.device)  # default priority
+        self.t0 = None
+
+    def attach(self, slot: int, r: Request) -> None:
+        p = r.params
+        self.batch.attach(slot, r.n, r.d, p["mean"], p["chol"], seed=r.seed,
+                          sampler_id=r.sampler_id, rw_sd=p["rw_sd"],
+                          init_mean=p.get("init_mean", 0.0), init_sd=p.get("init_sd", 3.0),
+                          mode=p.get("mode", L.MODE_AUTO))
+
+    def open(self, r: Request):
+        p = r.params
+        with torch.cuda.stream(self.side):
+            return smc.Sampler(r.n, r.d, "logreg", seed=r.seed, sampler_id=r.sampler_id,
+                               X=p["X"], y=p["y"], prior_var=p["prior_var"],
+                               precision=p.get("precision", "bf16"), rw_sd=p["rw_sd"],
+                               init_sd=math.sqrt(p["prior_var"]),
+                               mode=p.get("mode", L.MODE_AUTO), device=self.device)
+
+    def step(self, batch: bool, contexts) -> None:
+        if batch:
+            self.batch.step(info=False, est=True)
+        if contexts:
+            with torch.cuda.stream(self.side):
+                for s in contexts:
+                    s.step(info=False, est=True)
+
+    def _token(self, est_dev, x_dev, stream):
+        with torch.cuda.stream(stream):
+            host = torch.empty(est_dev.numel(), dtype=torch.float64, pin_memory=True)
+            host.copy_(est_dev, non_blocking=True)
+            x = x_dev.cpu().numpy() if (self.keep and x_dev is not None) else None
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+        return (ev, host, x)
+
+    def retire_slot(self, slot: int, r: Request):
+        o = slot * L.BATCH_EST_STRIDE
+        tok = self._token(self.batch.est[o:o + 4 * r.d],
+                          self.batch.x(slot) if self.keep else None, self.main)
+        self.batch.detach(slot)
+        return tok
+
+    def retire_context(self, s, r: Request):
+        # the context's buffers were allocated on the side stream: freeing
+        # them with the sampler is ordered after its last use there
+        return self._token(s.est[:4 * r.d], s.x if self.keep else None, self.side)
+
+    def ready(self, tok) -> bool:
+        return tok[0].query()
+
+    def wait(self, tok) -> None:
+        tok[0].synchronize()
+
+    def fetch(self, tok):
+        return tok[1].numpy(), tok[2]
+
+    def start(self) -> None:
+        torch.cuda.current_stream(self.device).synchronize()
+        self.t0 = torch.cuda.Event(enable_timing=True)
+        self.t0.record()
+
+    def elapsed(self, tok) -> float:
+        return self.t0.elapsed_time(tok[0]) / 1e3
+
+    def finish(self) -> None:
+        torch.cuda.synchronize(self.device)
+
+
+class Server:
+    """Admits requests into ``capacity`` batch slots under an HBM budget
+    (bytes), first come first served, and advances all admitted requests one
+    iteration per tick.
+
+    A finished request's slot and bytes are free for the next tick at once;
+    its results are retired through the backend (on the device: pinned host
+    memory behind an event) and the request is finished once they have
+    arrived, so ticks never wait for the device.  The default backend is the
+    library's (``DeviceBackend``); any object with the same methods serves."""
+
+    def __init__(self, capacity: int = 256, hbm_budget: int = 64 << 30, *, graph: bool = True,
+                 keep_particles: bool = False, device=None, backend=None):
+        self.be = backend if backend is not None else DeviceBackend(
+            capacity, graph=graph, keep_particles=keep_particles, device=device)
         self.capacity = capacity
         self.budget = int(hbm_budget)
-        self.keep = keep_particles
         self.used = 0
         self.free = list(range(capacity))[::-1]
         self.queue = collections.deque()
         self.gauss = {}    # slot -> [request, iterations left]
-        self.logreg = {}   # rid -> [request, sampler, iterations left]
-        self.retiring = [] # [request, event, host estimates, particles or None, d]
+        self.logreg = {}   # rid -> [request, context, iterations left]
+        self.retiring = [] # [request, backend token, d]
         self.iters_done = 0
         self.peak_used = 0
         self.peak_active = 0
-        self.main = torch.cuda.current_stream(self.device)
-        self.side = torch.cuda.Stream(device=self.device)  # default priority
 
     # --------------------------------------------------------------- admission
     def submit(self, r: Request) -> None:
@@ -104,22 +184,12 @@ class Server:
     def _admit(self, now: float) -> None:
         while self.queue and self.queue[0].arrival <= now and self._fits(self.queue[0]):
             r = self.queue.popleft()
-            p = r.params
             if r.kind == "gauss":
                 slot = self.free.pop()
-                self.batch.attach(slot, r.n, r.d, p["mean"], p["chol"], seed=r.seed,
-                                  sampler_id=r.sampler_id, rw_sd=p["rw_sd"],
-                                  init_mean=p.get("init_mean", 0.0),
-                                  init_sd=p.get("init_sd", 3.0), mode=p.get("mode", L.MODE_AUTO))
+                self.be.attach(slot, r)
                 self.gauss[slot] = [r, r.iters]
             else:
-                with torch.cuda.stream(self.side):
-                    s = smc.Sampler(r.n, r.d, "logreg", seed=r.seed, sampler_id=r.sampler_id,
-                                    X=p["X"], y=p["y"], prior_var=p["prior_var"],
-                                    precision=p.get("precision", "bf16"), rw_sd=p["rw_sd"],
-                                    init_sd=math.sqrt(p["prior_var"]),
-                                    mode=p.get("mode", L.MODE_AUTO), device=self.device)
-                self.logreg[r.rid] = [r, s, r.iters]
+                self.logreg[r.rid] = [r, self.be.open(r), r.iters]
             self.used += request_bytes(r)
             self.peak_used = max(self.peak_used, self.used)
             self.peak_active = max(self.peak_active, len(self.gauss) + len(self.logreg))
@@ -129,28 +199,19 @@ class Server:
     def busy(self) -> bool:
         return bool(self.gauss or self.logreg or self.retiring)
 
-    def _retire(self, r, est_dev, d, x_dev, stream) -> None:
-        with torch.cuda.stream(stream):
-            host = torch.empty(est_dev.numel(), dtype=torch.float64, pin_memory=True)
-            host.copy_(est_dev, non_blocking=True)
-            x = x_dev.cpu().numpy() if (self.keep and x_dev is not None) else None
-            ev = torch.cuda.Event(enable_timing=True)
-            ev.record(stream)
-        self.retiring.append([r, ev, host, x, d])
-
     def _collect(self, finish_time) -> list:
         out, keep = [], []
         for ent in self.retiring:
-            r, ev, host, x, d = ent
-            if not ev.query():
+            r, tok, d = ent
+            if not self.be.ready(tok):
                 keep.append(ent)
                 continue
-            e = host.numpy()
+            e, x = self.be.fetch(tok)
             r.result = {"mean": e[:d].copy(), "m2": e[d:2 * d].copy(),
                         "rec_mean": e[2 * d:3 * d].copy(), "rec_m2": e[3 * d:4 * d].copy()}
             if x is not None:
                 r.result["x"] = x
-            r.finished = finish_time(ev)
+            r.finished = finish_time(tok)
             out.append(r)
         self.retiring = keep
         return out
@@ -160,32 +221,22 @@ class Server:
         retiring the finished ones; returns the requests whose results have
         arrived on the host."""
         self._admit(now_fn())
-        if self.gauss:
-            self.batch.step(info=False, est=True)
-            self.iters_done += len(self.gauss)
-        if self.logreg:
-            with torch.cuda.stream(self.side):
-                for ent in self.logreg.values():
-                    ent[1].step(info=False, est=True)
-            self.iters_done += len(self.logreg)
+        if self.gauss or self.logreg:
+            self.be.step(bool(self.gauss), [ent[1] for ent in self.logreg.values()])
+            self.iters_done += len(self.gauss) + len(self.logreg)
         for slot, ent in list(self.gauss.items()):
             ent[1] -= 1
             if ent[1] == 0:
                 r = ent[0]
-                o = slot * L.BATCH_EST_STRIDE
-                self._retire(r, self.batch.est[o:o + 4 * r.d], r.d,
-                             self.batch.x(slot) if self.keep else None, self.main)
-                self.batch.detach(slot)
+                self.retiring.append([r, self.be.retire_slot(slot, r), r.d])
                 self.free.append(slot)
                 del self.gauss[slot]
                 self.used -= request_bytes(r)
         for rid, ent in list(self.logreg.items()):
             ent[2] -= 1
             if ent[2] == 0:
-                r, s = ent[0], ent[1]
-                self._retire(r, s.est[:4 * r.d], r.d, s.x if self.keep else None, self.side)
-                # its buffers were allocated on the side stream: freeing them
-                # with the sampler is ordered after its last use there
+                r = ent[0]
+                self.retiring.append([r, self.be.retire_context(ent[1], r), r.d])
                 del self.logreg[rid]
                 self.used -= request_bytes(r)
         return self._collect(finish_time)
@@ -195,26 +246,24 @@ class Server:
         """Serves ``requests`` (arrival times in seconds, or in ticks with
         clock="tick") to completion; returns latency and throughput figures.
         With the wall clock a request finishes when its results reach the
-        host (device event time); with the tick clock, at its last tick."""
+        host (device event time); with the tick clock, at the tick whose
+        collection found them there."""
         for r in sorted(requests, key=lambda q: (q.arrival, q.rid)):
             self.submit(r)
         ticks = [0]
-        torch.cuda.current_stream().synchronize()
-        start = torch.cuda.Event(enable_timing=True)
-        start.record()
+        self.be.start()
         t0 = time.perf_counter()
         if clock == "tick":
             def now():
                 return float(ticks[0])
 
-            def finish_time(ev):
+            def finish_time(tok):
                 return float(ticks[0])
         else:
             def now():
                 return time.perf_counter() - t0
 
-            def finish_time(ev):
-                return start.elapsed_time(ev) / 1e3
+            finish_time = self.be.elapsed
         finished = []
         while len(finished) < len(requests):
             if not self.busy() and self.queue and self.queue[0].arrival > now():
@@ -224,10 +273,10 @@ class Server:
                     time.sleep(min(1e-3, max(0.0, self.queue[0].arrival - now())))
                 continue
             if not (self.gauss or self.logreg) and self.retiring:
-                self.retiring[0][1].synchronize()
+                self.be.wait(self.retiring[0][1])
             finished += self.tick(now, finish_time)
             ticks[0] += 1
-        torch.cuda.synchronize(self.device)
+        self.be.finish()
         wall = time.perf_counter() - t0
         lat = sorted(r.latency for r in finished)
         iters = sum(r.iters for r in finished)

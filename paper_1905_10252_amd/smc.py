@@ -107,6 +107,42 @@ class Resampler:
         return self._lib.smc_sync_error(self.ctx, _stream())
 
 
+_RESAMPLERS: dict = {}
+
+
+def _resampler(n: int, device) -> Resampler:
+    """The Resampler kept for (N, device); module-level calls share it, so a
+    redistribute() without counts follows the last resample() of that N."""
+    dev = torch.device(device)
+    key = (int(n), dev.type, dev.index if dev.index is not None else torch.cuda.current_device())
+    rs = _RESAMPLERS.get(key)
+    if rs is None:
+        rs = _RESAMPLERS[key] = Resampler(n, device=dev)
+    return rs
+
+
+def resample(logw: torch.Tensor, r: int, mode: int = L.MODE_AUTO,
+             ncopies: torch.Tensor | None = None) -> torch.Tensor:
+    """Alg 4 on the log-weights ``logw`` (float64 [N], device) with the
+    systematic offset ``r`` (a 64-bit integer, U = floor(r S / 2^64)); returns
+    the copy counts (int64 [N], allocated when not given).  When the ESS rule
+    (``mode``) decides not to resample, every count is one."""
+    rs = _resampler(logw.shape[0], logw.device)
+    if ncopies is None:
+        ncopies = torch.empty(rs.n, dtype=torch.int64, device=logw.device)
+    return rs.resample(logw, r, mode, ncopies=ncopies, info=False)
+
+
+def redistribute(x: torch.Tensor, ncopies: torch.Tensor | None = None,
+                 x_out: torch.Tensor | None = None) -> torch.Tensor:
+    """Alg 5 semantics on the rows of ``x`` ([N][...], contiguous, device):
+    returns the new population (row p is a copy of row anc(p), ancestors in
+    non-decreasing order, source j copied ncopies_j times).  Without
+    ``ncopies`` the counts of the last ``resample`` on N rows on this device
+    are used."""
+    return _resampler(x.shape[0], x.device).redistribute(x, x_out=x_out, ncopies=ncopies)
+
+
 class Sampler:
     """One SMC sampler (Alg 2) driven through smc_init / smc_step.
 

@@ -83,3 +83,22 @@ def test_pf_large_population(smc, dev):
         o.step()
     assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x))
     assert np.array_equal(bits(g.logw.cpu().numpy()), bits(o.logw))
+
+
+@pytest.mark.parametrize("mode", [O.MODE_AUTO, O.MODE_FORCE])
+def test_pf_full_size(smc, dev, mode):
+    """The bearing-only filter as timed (N = 2^24, track seed 7, particle
+    seed 2; the ESS trigger takes the in-place path, forced resampling the
+    out-of-place one): initial population and one update bit for bit."""
+    print("pf n=2^24 mode %d (oracle about 12 s)" % mode, flush=True)
+    g, o = pair(smc, dev, 1 << 24, 60, mode, seed=2, track_seed=7)
+    assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x))
+    g.step()
+    out = o.step()
+    info = g.info()
+    for k in ("S", "U", "Q2_hi", "Q2_lo", "resampled", "err", "K"):
+        assert info[k] == out["info"][k], k
+    assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x))
+    assert np.array_equal(bits(g.logw.cpu().numpy()), bits(o.logw))
+    assert close(g.estimates()["mean"], out["mean"], 1e-11)
+    assert abs(info["log_c"] - out["log_c"]) <= 1e-10 * max(1.0, abs(out["log_c"]))

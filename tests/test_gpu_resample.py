@@ -204,3 +204,29 @@ def test_full_size_parity(smc, dev, s):
     x = I.particles(n, d, I.X_SEED)
     oinfo = compare(lw, x, I.offset_word(I.R_SEED), O.MODE_FORCE, smc, dev)
     _say("  unique survivors %d of %d" % (oinfo["unique"], n))
+
+
+def test_module_level_functions(smc, dev):
+    """smc.resample / smc.redistribute keep one context per N: a
+    redistribute without counts follows the last resample of the same N,
+    whatever was resampled at other sizes in between."""
+    import torch
+    _say("module-level resample/redistribute")
+    sizes = (3001, 70001)
+    xs = {n: I.particles(n, 3, 7 + n) for n in sizes}
+    lws = {n: I.logw_normal(n, 2.0, 11 + n) for n in sizes}
+    nc = {n: smc.resample(torch.from_numpy(lws[n]).to(dev), 99 + n, O.MODE_FORCE) for n in sizes}
+    for n in sizes[::-1]:
+        onc, _ = O.resample(lws[n], 99 + n, O.MODE_FORCE)
+        assert nc[n].dtype == torch.int64 and np.array_equal(nc[n].cpu().numpy(), onc)
+        xo = smc.redistribute(torch.from_numpy(xs[n]).to(dev))
+        assert np.array_equal(xo.cpu().numpy(), O.redistribute(onc, xs[n])[0])
+    # explicit counts, and the ESS rule declining to resample (all ones)
+    n = sizes[0]
+    onc, _ = O.resample(lws[sizes[1]][:n], 5, O.MODE_FORCE)
+    xo = smc.redistribute(torch.from_numpy(xs[n]).to(dev), torch.from_numpy(onc).to(dev))
+    assert np.array_equal(xo.cpu().numpy(), O.redistribute(onc, xs[n])[0])
+    flat = np.zeros(n)
+    ones = smc.resample(torch.from_numpy(flat).to(dev), 1, O.MODE_AUTO)
+    assert np.array_equal(ones.cpu().numpy(), np.ones(n, dtype=np.int64))
+    assert np.array_equal(O.resample(flat, 1, O.MODE_AUTO)[0], np.ones(n, dtype=np.int64))

@@ -273,3 +273,16 @@ def test_forced_and_in_place_paths_agree_on_an_error_step(smc, dev):
     assert res[0][0] != 0 and res[0][0] == res[1][0]
     assert res[0][2] == 0 and res[1][2] == 0
     assert np.array_equal(bits(res[0][1]), bits(res[1][1]))
+
+
+def test_student_t_full_size(smc, dev):
+    """The Student-t workload as timed (N = 2^24, nu = 5, mu = 1, resampling
+    every iteration): initial population and two iterations bit for bit."""
+    _say("student n=2^24 (oracle about 15 s)")
+    n = 1 << 24
+    g = smc.Sampler(n, 1, "student", seed=1, rw_sd=0.5, nu=5.0, mu=1.0, mode=O.MODE_FORCE,
+                    device=dev)
+    o = O.Sampler(n, 1, O.T_STUDENT, seed=1, rw_sd=0.5, nu=5.0, mu=1.0, mode=O.MODE_FORCE,
+                  log_norm=g.cfg.log_norm, init_log_norm=g.cfg.init_log_norm)
+    o.init()
+    run_and_compare(g, o, 2)
