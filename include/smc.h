@@ -134,8 +134,9 @@ smc_status smc_step(smc_ctx *ctx, void *x, double *logw, smc_resample_info *info
                     void *stream);
 
 /* Alg 4 up to ncopies on log-weights logw[n] (n = the configured N): exact
- * max, FP64 log-sum-exp and ESS, 64-bit fixed-point weights with a
- * decoupled-lookback prefix scan, the integer ESS decision (mode), and
+ * max, FP64 log-sum-exp and ESS, 64-bit fixed-point weights and their
+ * exact integer prefix sum (tile-local prefixes plus tile offsets), the
+ * integer ESS decision (mode), and
  * systematic ncopies with offset floor(r S / 2^64).  The prefix is kept in the
  * workspace for the next smc_redistribute; ncopies (nullable, int64[n]) is
  * also written when given.  When the decision is not to resample, ncopies is

@@ -25,8 +25,7 @@ constexpr unsigned kErrArg = 1, kErrNonfinite = 2, kErrDegenerate = 3;
 // sequence communicates through it; no host round trip is needed.
 struct Ctrl {
     u64 mkey;            // order key of the max log-weight (written by the fold)
-    unsigned spin_fail;  // a lookback exceeded its spin bound (never expected)
-    unsigned unused0;
+    u64 ctotal;          // total of caller-supplied counts (count scan)
     unsigned err_call;   // device error of the current call (0 = none)
     unsigned err_latch;  // sticky error, cleared by smc_sync_error
     unsigned resample;   // decision of the last resample (1 = resample)

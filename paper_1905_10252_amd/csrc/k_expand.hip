@@ -11,7 +11,8 @@
 //
 // A_j is computed from the fixed-point prefix as floor((N S_j + U) / S), or is
 // the prefix of caller-supplied counts, or j + 1 when the ESS rule decided not
-// to resample.  The segment boundaries are found by a 64-ary search run by one
+// to resample.  A prefix value is the scan's tile-local value plus the offset
+// of its tile of 4096.  The segment boundaries are found by a 64-ary search run by one
 // wavefront; the test A_j + j < k is evaluated as N S_j + U < (k - j) S in
 // 128-bit integers (no division).
 #include <hip/hip_runtime.h>
@@ -24,10 +25,13 @@ namespace smc {
 
 struct AFun {
     i64 n;
-    const u64 *pref;
-    int mode;  // 0: identity, 1: systematic from S_j, 2: caller counts (A_j = pref[j])
+    const u64 *pref;  // tile-local inclusive prefix
+    const u64 *tpre;  // exclusive prefix of the tile totals
+    int mode;  // 0: identity, 1: systematic from S_j, 2: caller counts (A_j = prefix)
     u64 S, U;
     double invS;
+
+    __device__ inline u64 at(i64 j) const { return pref[j] + tpre[j >> kTileShift]; }
 
     // A_j + j < k, given the prefix value pj of source j
     __device__ inline bool pred_at(i64 j, u64 pj, i64 k) const
@@ -43,14 +47,16 @@ struct AFun {
 
     __device__ inline bool pred(i64 j, i64 k) const
     {
-        return pred_at(j, mode == 0 ? 0ull : pref[j], k);
+        return pred_at(j, mode == 0 ? 0ull : at(j), k);
     }
 
-    __device__ inline u64 A(i64 j) const
+    __device__ inline u64 A(i64 j) const { return A_of(j, mode == 0 ? 0ull : at(j)); }
+
+    // A_j given the prefix value sj of source j
+    __device__ inline u64 A_of(i64 j, u64 sj) const
     {
         if (mode == 0) return (u64)(j + 1);
-        if (mode == 2) return pref[j];
-        const u64 sj = pref[j];
+        if (mode == 2) return sj;
         const U128 num = add128(mul64((u64)n, sj), U);
         const double est = ((double)n * (double)sj + (double)U) * invS;
         u64 a = est > 0.0 ? (u64)est : 0ull;
@@ -110,7 +116,9 @@ __device__ inline i64 wave_search(const AFun &f, const u64 *pref64, i64 k, i64 l
     ghi = ghi < G ? ghi : G;
     i64 g = glo;
     if (ghi > glo) {
-        auto ps = [&](i64 gg) { return f.pred_at(gg * 64 + 63, pref64[gg], k); };
+        auto ps = [&](i64 gg) {
+            return f.pred_at(gg * 64 + 63, pref64[gg] + f.tpre[gg >> (kTileShift - 6)], k);
+        };
         g = wave_first_false(ps, glo, ghi);
     }
     i64 lo2 = g * 64 > lo ? g * 64 : lo;
@@ -122,18 +130,19 @@ __device__ inline i64 wave_search(const AFun &f, const u64 *pref64, i64 k, i64 l
 }
 
 // Chooses the A function of this call; false if nothing may be written.
-__device__ inline bool make_afun(const Ctrl *ctrl, const u64 *pref, i64 n, int count_mode,
-                                 AFun &f, bool report)
+__device__ inline bool make_afun(const Ctrl *ctrl, const u64 *pref, const u64 *tpre, i64 n,
+                                 int count_mode, AFun &f, bool report)
 {
     f.n = n;
     f.pref = pref;
+    f.tpre = tpre;
     f.S = 1;
     f.U = 0;
     f.invS = 1.0;
     if (count_mode) {
-        if (ctrl->spin_fail || ctrl->ncopy_bad || pref[n - 1] != (u64)n) {
+        if (ctrl->ncopy_bad || ctrl->ctotal != (u64)n) {
             if (report) {
-                const unsigned err = ctrl->spin_fail ? (unsigned)SMC_E_DEVICE : kErrArg;
+                const unsigned err = kErrArg;
                 Ctrl *c = const_cast<Ctrl *>(ctrl);
                 c->err_call = err;
                 if (!c->err_latch) c->err_latch = err;
@@ -220,6 +229,7 @@ struct ExpandArgs {
     i64 n;
     const u64 *pref;
     const u64 *pref64;
+    const u64 *tpre;
     const Ctrl *ctrl;
     int count_mode;
     const unsigned char *x;
@@ -241,7 +251,8 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
     __shared__ i64 s_j[2];
     const int tid = threadIdx.x, wid = tid >> 6;
     AFun f;
-    if (!make_afun(a.ctrl, a.pref, a.n, a.count_mode, f, blockIdx.x == 0 && tid == 0)) return;
+    if (!make_afun(a.ctrl, a.pref, a.tpre, a.n, a.count_mode, f, blockIdx.x == 0 && tid == 0))
+        return;
     if (a.skip_identity && f.mode == 0) return;
 
     const i64 n = a.n;
@@ -259,9 +270,20 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
     const i64 p0 = k0 - j0;
     const int ns = (int)(j1 - j0), np = (int)((k1 - j1) - p0);
 
+    // sources j0 - 1 .. j1 - 1 (at most kSegLen + 1 < 4096) lie in at most two
+    // tiles: their offsets are read once
+    const i64 ta = (j0 > 0 ? j0 - 1 : 0) >> kTileShift;
+    const i64 ntl = (n + kTile - 1) >> kTileShift;
+    const u64 off_a = f.mode ? f.tpre[ta] : 0ull;
+    const u64 off_b = (f.mode && ta + 1 < ntl) ? f.tpre[ta + 1] : 0ull;
     for (int i = tid; i <= ns; i += kExpandThreads) {
         const i64 j = j0 - 1 + i;
-        sA[i] = j < 0 ? 0u : (unsigned)f.A(j);
+        if (j < 0) {
+            sA[i] = 0u;
+            continue;
+        }
+        const u64 sj = f.mode ? a.pref[j] + ((j >> kTileShift) == ta ? off_a : off_b) : 0ull;
+        sA[i] = (unsigned)f.A_of(j, sj);
     }
     __syncthreads();
     if (a.nc_out)
@@ -303,6 +325,7 @@ hipError_t launch_expand(const Work &w, int64_t n, int count_mode, const void *x
     a.n = n;
     a.pref = w.pref;
     a.pref64 = w.pref64;
+    a.tpre = w.tsum;
     a.ctrl = w.ctrl;
     a.count_mode = count_mode;
     a.x = reinterpret_cast<const unsigned char *>(x);
@@ -330,11 +353,11 @@ hipError_t launch_expand(const Work &w, int64_t n, int count_mode, const void *x
 }
 
 // ncopies_j = A_j - A_{j-1} for every source (elementwise).
-__global__ __launch_bounds__(256) void k_ncopies(const Ctrl *ctrl, const u64 *pref, i64 n,
-                                                 int count_mode, i64 *nc)
+__global__ __launch_bounds__(256) void k_ncopies(const Ctrl *ctrl, const u64 *pref,
+                                                 const u64 *tpre, i64 n, int count_mode, i64 *nc)
 {
     AFun f;
-    if (!make_afun(ctrl, pref, n, count_mode, f, false)) return;
+    if (!make_afun(ctrl, pref, tpre, n, count_mode, f, false)) return;
     const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
     for (i64 j = gtid; j < n; j += gsz) {
         const u64 a1 = f.A(j);
@@ -348,8 +371,8 @@ hipError_t launch_ncopies(const Work &w, int64_t n, int count_mode, int64_t *nco
 {
     int64_t blocks = (n + 255) / 256;
     blocks = blocks > 4096 ? 4096 : blocks;
-    hipLaunchKernelGGL(k_ncopies, dim3((unsigned)blocks), dim3(256), 0, s, w.ctrl, w.pref, (i64)n,
-                       count_mode, reinterpret_cast<i64 *>(ncopies));
+    hipLaunchKernelGGL(k_ncopies, dim3((unsigned)blocks), dim3(256), 0, s, w.ctrl, w.pref, w.tsum,
+                       (i64)n, count_mode, reinterpret_cast<i64 *>(ncopies));
     return hipGetLastError();
 }
 

@@ -1,23 +1,27 @@
 // Resampling kernels of Alg 4 (minimum variance resampling):
 //   k_max          exact FP64 max of the log-weights (the stability shift of
-//                  eq. normalise) and non-finite detection; clears the scan
-//                  state for the pass that follows.
+//                  eq. normalise) and non-finite detection.
 //   k_fold         combines the max slots, records the error of the call
 //                  (used where no scan follows the max pass).
 //   k_scan<true>   one pass over the log-weights: 64-bit fixed-point weights
 //                  q_i = min(2^K, floor(2^K det_exp(l_i - m))), FP64 sums for
 //                  log-sum-exp and ESS (eq. normalise, eq. neff), the exact
-//                  sum of q_i^2, and the inclusive prefix S_j (the Cumulative
-//                  Sum of MVR) by a single-pass decoupled-lookback scan.
-//   k_scan<false>  the same scan over caller-supplied int64 ncopies.
-//   k_decide       the error of the call, the exact integer ESS decision
-//                  (resample when ESS < N*, Alg 2), the systematic offset
-//                  U = floor(r S / 2^64), log Z and the FP64 ESS from the tile
-//                  partials; clears the other parity's max slots.
-// No kernel here uses a device-wide fence or a contended atomic: both
-// serialise across the chip.
-// Every 64th prefix value is also written to a sample array, a coarse index
-// for the merge-path searches of the expand kernel.
+//                  sum of q_i^2, and the prefix sums of q within each tile of
+//                  4096 weights, plus the tile's total.
+//   k_scan<false>  the same tile scan over caller-supplied int64 ncopies.
+//   k_decide       the exclusive prefix of the tile totals (so that the
+//                  inclusive prefix S_j of the Cumulative Sum of MVR is the
+//                  tile-local value plus its tile's offset), the error of the
+//                  call, the exact integer ESS decision (resample when
+//                  ESS < N*, Alg 2), the systematic offset U = floor(r S / 2^64),
+//                  log Z and the FP64 ESS from the tile partials; clears the
+//                  other parity's max slots.
+//   k_tile_prefix  the tile offsets alone, for caller-supplied counts.
+// No tile waits on another: the scan is split into tile-local prefixes and
+// one small scan over the tile totals, so no kernel here spins, and none uses
+// a device-wide fence or a contended atomic.
+// Every 64th tile-local prefix value is also written to a sample array, a
+// coarse index for the merge-path searches of the expand kernel.
 #include <hip/hip_runtime.h>
 
 #include "../../include/smc.h"
@@ -47,12 +51,11 @@ hipError_t launch_init_ctrl(const Work &w, hipStream_t s)
 // Grid-stride share per block, four 16-byte loads in flight per thread; each
 // block publishes its max order key into the slots of this call's parity.
 __global__ __launch_bounds__(256) void k_max(const double *__restrict__ lw, i64 n, int vec2,
-                                             u64 *slots_p, u64 *status, int n_status)
+                                             u64 *slots_p)
 {
     constexpr int U = 4;
     const int tid = threadIdx.x;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
-    for (i64 i = gtid; i < n_status; i += gsz) status[i] = 0;
 
     u64 key = 0;
     unsigned bad = 0;
@@ -90,7 +93,7 @@ hipError_t launch_max(const Work &w, const double *lw, int64_t n, int par, hipSt
 {
     const int vec2 = ((uintptr_t)lw & 15) == 0;
     hipLaunchKernelGGL(k_max, dim3(max_blocks_of(n)), dim3(256), 0, s, lw, (i64)n, vec2,
-                       w.slots + (par & 1) * kSlots * kSlotStride, w.status, w.n_tiles);
+                       w.slots + (par & 1) * kSlots * kSlotStride);
     return hipGetLastError();
 }
 
@@ -114,7 +117,6 @@ __global__ __launch_bounds__(64) void k_fold(u64 *slots, int par, Ctrl *ctrl)
         ctrl->m = okey_inv(key);
         ctrl->err_call = err;
         if (err && !ctrl->err_latch) ctrl->err_latch = err;
-        ctrl->spin_fail = 0;
         ctrl->pending = 0;
     }
 }
@@ -125,19 +127,17 @@ hipError_t launch_fold(const Work &w, int par, hipStream_t s)
     return hipGetLastError();
 }
 
-// -------------------------------------------------- decoupled-lookback scan
+// ------------------------------------------------------------ tile scan
 // Tile = 256 threads x 16 items; tile t is workgroup t.  Global loads and
 // stores are coalesced 16-byte accesses over rows of 512 elements; an LDS
 // transpose (one pad word per 16 entries against bank conflicts) gives each
 // thread 16 consecutive items for the sequential part of the scan.
-// A tile only ever waits on lower-numbered tiles, which the hardware
-// dispatches before it (workgroups are issued to each XCD in index order), so
-// the wait ends.  As a guarantee of termination whatever the dispatch order,
-// the spin is bounded: past kSpinLimit polls the tile gives up and flags the
-// call as a device error instead of hanging.
+// The prefix written is local to the tile; the tile's total goes to tsum[t],
+// which the following single-workgroup pass turns into tile offsets.  A
+// chained scan (each tile waiting for its predecessors' totals) costs a
+// round trip through the memory system per tile in flight; this split costs
+// one small pass over 8 bytes per 4096 weights instead.
 __host__ __device__ constexpr int kPad(int i) { return i + (i >> 4); }
-constexpr int kLookU = 1;  // 64-entry lookback windows loaded per round trip
-constexpr int kSpinLimit = 1 << 22;
 
 struct ScanArgs {
     const double *lw;   // quantise mode input
@@ -145,10 +145,10 @@ struct ScanArgs {
     i64 n;
     int K, vec2;
     Ctrl *ctrl;
-    u64 *status;
+    u64 *tsum;          // [n_tiles] tile totals
     TilePart *tpart;
-    u64 *out;           // [n] inclusive prefix
-    u64 *out64;         // [n / 64] every 64th prefix value
+    u64 *out;           // [n] tile-local inclusive prefix
+    u64 *out64;         // [n / 64] every 64th tile-local prefix value
     const u64 *slots_p; // max slots of this call's parity (quantise mode)
     int n_tiles;
 };
@@ -175,10 +175,8 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     __shared__ double s_z[4], s_z2[4];
     __shared__ u64 s_q2lo[4], s_q2hi[4];
     __shared__ unsigned s_bad[4];
-    __shared__ u64 s_prefix;
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    Ctrl *ctrl = a.ctrl;
     const i64 n = a.n;
     const unsigned tile = blockIdx.x;
     const i64 base = (i64)tile * kTile;
@@ -238,68 +236,6 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     }
     const u64 incl = wave_incl_scan_u64(run);
     if (lane == 63) s_wsum[wid] = incl;
-    __syncthreads();
-    u64 wpre = 0, agg = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        wpre += (i < wid) ? s_wsum[i] : 0;
-        agg += s_wsum[i];
-    }
-    const u64 texcl = wpre + incl - run;
-
-    // decoupled lookback by wave 0: kLookU x 64 predecessors per round trip,
-    // nearest first; aggregates are summed until the nearest inclusive prefix
-    if (wid == 0) {
-        u64 excl = 0;
-        if (tile == 0) {
-            if (lane == 0) st_relaxed(&a.status[0], kFlagInc | agg);
-        } else {
-            if (lane == 0) st_relaxed(&a.status[tile], kFlagAgg | agg);
-            i64 top_idx = (i64)tile - 1;
-            int spins = 0;
-            while (true) {
-                u64 sv[kLookU];
-#pragma unroll
-                for (int u = 0; u < kLookU; ++u) {
-                    const i64 idx = top_idx - 64 * u - lane;
-                    sv[u] = idx >= 0 ? ld_relaxed(&a.status[idx]) : kFlagInc;
-                }
-                u64 acc = 0;
-                int consumed = 0;
-                bool done = false, stall = false;
-#pragma unroll
-                for (int u = 0; u < kLookU; ++u) {
-                    if (done || stall) break;
-                    const u64 flag = sv[u] >> 62;
-                    const u64 inc_mask = __ballot(flag == 2);
-                    const u64 zero_mask = __ballot(flag == 0);
-                    const int first_inc = inc_mask ? __ffsll((long long)inc_mask) - 1 : 64;
-                    const u64 need = first_inc >= 64 ? ~0ull : ((1ull << first_inc) - 1);
-                    if (zero_mask & need) {
-                        stall = true;
-                        break;
-                    }
-                    acc += lane <= first_inc ? (sv[u] & kValMask) : 0;
-                    consumed = u + 1;
-                    if (first_inc < 64) done = true;
-                }
-                for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, kWave);
-                excl += acc;
-                if (done) break;
-                top_idx -= 64 * consumed;
-                if (stall) {
-                    if (++spins > kSpinLimit) {
-                        if (lane == 0) ctrl->spin_fail = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-            if (lane == 0) st_relaxed(&a.status[tile], kFlagInc | (excl + agg));
-        }
-        if (lane == 0) s_prefix = excl;
-    }
-
     // tile partial sums (fixed reduction order: reproducible)
     if (kQuant) {
         z = wave_sum_f64(z);
@@ -316,13 +252,35 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
         if (lane == 0) s_bad[wid] = bad;
     }
     __syncthreads();
-    const u64 pre = s_prefix + texcl;
+    u64 wpre = 0, agg = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        wpre += (i < wid) ? s_wsum[i] : 0;
+        agg += s_wsum[i];
+    }
+    // each thread rewrites only the 16 entries it read above
+    const u64 pre = wpre + incl - run;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) sq[kPad(tid * kScanItems + j)] = pre + loc[j];
     // every 64th prefix value (items 64g + 63 sit at the end of threads 4h + 3)
     if ((tid & 3) == 3) {
         const i64 gi = base + tid * kScanItems + (kScanItems - 1);
         if (gi < n) a.out64[gi >> 6] = pre + loc[kScanItems - 1];
+    }
+    if (tid == 0) {
+        a.tsum[tile] = agg;
+        if (kQuant) {
+            TilePart p;
+            p.Z = ((s_z[0] + s_z[1]) + s_z[2]) + s_z[3];
+            p.Z2 = ((s_z2[0] + s_z2[1]) + s_z2[2]) + s_z2[3];
+            U128 t{s_q2lo[0], s_q2hi[0]};
+            for (int i = 1; i < 4; ++i) t = add128(t, U128{s_q2lo[i], s_q2hi[i]});
+            p.q2lo = t.lo;
+            p.q2hi = t.hi;
+            a.tpart[tile] = p;
+        } else if (s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]) {
+            atomicOr(&a.ctrl->ncopy_bad, 1u);
+        }
     }
     __syncthreads();
     if (full) {
@@ -341,37 +299,62 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
             if (base + s0 < n) a.out[base + s0] = sq[kPad(s0)];
         }
     }
+}
 
-    if (tid == 0) {
-        if (kQuant) {
-            TilePart p;
-            p.Z = ((s_z[0] + s_z[1]) + s_z[2]) + s_z[3];
-            p.Z2 = ((s_z2[0] + s_z2[1]) + s_z2[2]) + s_z2[3];
-            U128 t{s_q2lo[0], s_q2hi[0]};
-            for (int i = 1; i < 4; ++i) t = add128(t, U128{s_q2lo[i], s_q2hi[i]});
-            p.q2lo = t.lo;
-            p.q2hi = t.hi;
-            a.tpart[tile] = p;
-        } else if (s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]) {
-            atomicOr(&ctrl->ncopy_bad, 1u);
-        }
+// Exclusive prefix of the tile totals, in place, by one workgroup of 1024
+// threads (each a contiguous run of tiles); returns the grand total to every
+// thread.
+__device__ inline u64 tile_offsets(u64 *tsum, int n_tiles, u64 *s_w)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int per = (n_tiles + 1023) / 1024;
+    const int t0 = tid * per;
+    u64 run = 0;
+    for (int i = 0; i < per; ++i)
+        if (t0 + i < n_tiles) run += tsum[t0 + i];
+    const u64 incl = wave_incl_scan_u64(run);
+    if (lane == 63) s_w[wid] = incl;
+    __syncthreads();
+    u64 pre = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        pre += (i < wid) ? s_w[i] : 0;
+        total += s_w[i];
     }
+    pre += incl - run;
+    for (int i = 0; i < per; ++i)
+        if (t0 + i < n_tiles) {
+            const u64 v = tsum[t0 + i];
+            tsum[t0 + i] = pre;
+            pre += v;
+        }
+    return total;
+}
+
+// Caller-supplied counts: tile offsets and their total (checked against N by
+// the expand).
+__global__ __launch_bounds__(1024) void k_tile_prefix(Ctrl *ctrl, u64 *tsum, int n_tiles)
+{
+    __shared__ u64 s_w[16];
+    const u64 total = tile_offsets(tsum, n_tiles, s_w);
+    if (threadIdx.x == 0) ctrl->ctotal = total;
 }
 
 // ---------------------------------------------------------------- decision
-// One workgroup: tile partials summed in a fixed order (reproducible FP64);
-// exact integer decision and offset.
+// One workgroup: tile offsets; tile partials summed in a fixed order
+// (reproducible FP64); exact integer decision and offset.
 __global__ __launch_bounds__(1024) void k_decide(Ctrl *ctrl, u64 *slots, int par,
-                                                 const TilePart *tpart, const u64 *status,
+                                                 const TilePart *tpart, u64 *tsum,
                                                  int n_tiles, i64 n, int K, u64 r, int mode,
                                                  int ess_num, int ess_den,
                                                  smc_resample_info *info)
 {
     __shared__ double s_z[16], s_z2[16];
     __shared__ u64 s_lo[16], s_hi[16];
-    __shared__ u64 s_key;
+    __shared__ u64 s_key, s_w[16];
     __shared__ unsigned s_badf;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const u64 S = tile_offsets(tsum, n_tiles, s_w);
     if (wid == 0) {
         u64 *cur = slots + (par & 1) * kSlots * kSlotStride;
         u64 *nxt = slots + ((par & 1) ^ 1) * kSlots * kSlotStride;
@@ -419,17 +402,14 @@ __global__ __launch_bounds__(1024) void k_decide(Ctrl *ctrl, u64 *slots, int par
         Z2 += s_z2[i];
         Q2 = add128(Q2, U128{s_lo[i], s_hi[i]});
     }
-    const u64 S = status[n_tiles - 1] & kValMask;
     const u64 key = s_key;
     const double m = okey_inv(key);
     unsigned err = 0;
     if (s_badf) err = kErrNonfinite;
     else if (key <= okey(-__builtin_huge_val())) err = kErrDegenerate;
-    else if (ctrl->spin_fail) err = SMC_E_DEVICE;
     ctrl->mkey = key;
     ctrl->m = m;
     ctrl->err_call = err;
-    ctrl->spin_fail = 0;
     if (err && !ctrl->err_latch) ctrl->err_latch = err;
     int resample;
     if (mode == SMC_MODE_FORCE) {
@@ -479,7 +459,7 @@ hipError_t launch_decide(const Work &w, int par, int64_t n, int K, uint64_t r, i
                          int ess_num, int ess_den, void *info, hipStream_t s)
 {
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, w.ctrl, w.slots, par, w.tpart,
-                       w.status, w.n_tiles, (i64)n, K, (u64)r, mode, ess_num, ess_den,
+                       w.tsum, w.n_tiles, (i64)n, K, (u64)r, mode, ess_num, ess_den,
                        reinterpret_cast<smc_resample_info *>(info));
     return hipGetLastError();
 }
@@ -494,7 +474,7 @@ hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, 
     a.K = K;
     a.vec2 = ((uintptr_t)lw & 15) == 0;
     a.ctrl = w.ctrl;
-    a.status = w.status;
+    a.tsum = w.tsum;
     a.tpart = w.tpart;
     a.out = w.pref;
     a.out64 = w.pref64;
@@ -504,24 +484,17 @@ hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, 
     return hipGetLastError();
 }
 
-// Resets the scan state before a scan that no max pass precedes.
-__global__ __launch_bounds__(256) void k_clear_scan(Ctrl *ctrl, u64 *status, int n_status)
+// Resets the per-call flags before a scan of caller-supplied counts.
+__global__ void k_clear_scan(Ctrl *ctrl)
 {
-    const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
-    for (i64 i = gtid; i < n_status; i += gsz) status[i] = 0;
-    if (gtid == 0) {
-        ctrl->spin_fail = 0;
-        ctrl->ncopy_bad = 0;
-        ctrl->err_call = 0;
-        ctrl->pending = 0;
-    }
+    ctrl->ncopy_bad = 0;
+    ctrl->err_call = 0;
+    ctrl->pending = 0;
 }
 
 hipError_t launch_clear_scan(const Work &w, hipStream_t s)
 {
-    int blocks = (w.n_tiles + 255) / 256;
-    blocks = blocks < 1 ? 1 : (blocks > kMaxBlocks ? kMaxBlocks : blocks);
-    hipLaunchKernelGGL(k_clear_scan, dim3(blocks), dim3(256), 0, s, w.ctrl, w.status, w.n_tiles);
+    hipLaunchKernelGGL(k_clear_scan, dim3(1), dim3(1), 0, s, w.ctrl);
     return hipGetLastError();
 }
 
@@ -534,13 +507,15 @@ hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, h
     a.K = 0;
     a.vec2 = 0;
     a.ctrl = w.ctrl;
-    a.status = w.status;
+    a.tsum = w.tsum;
     a.tpart = w.tpart;
     a.out = w.pref;
     a.out64 = w.pref64;
     a.slots_p = nullptr;
     a.n_tiles = w.n_tiles;
     hipLaunchKernelGGL(k_scan<false>, dim3(w.n_tiles), dim3(256), 0, s, a);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    hipLaunchKernelGGL(k_tile_prefix, dim3(1), dim3(1024), 0, s, w.ctrl, w.tsum, w.n_tiles);
     return hipGetLastError();
 }
 

@@ -178,8 +178,8 @@ struct Online {
 template <int kKind, bool kInit, int DT, bool kOut>
 __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *__restrict__ x,
                                             double *__restrict__ logw, double *__restrict__ lp,
-                                            u64 *slots_p, u64 *status, int n_status,
-                                            double *is_part, double *__restrict__ xo,
+                                            u64 *slots_p, double *is_part,
+                                            double *__restrict__ xo,
                                             double *__restrict__ lpo)
 {
     constexpr bool kEst = kKind != SMC_TARGET_BEARING;
@@ -187,8 +187,6 @@ __global__ __launch_bounds__(256) void k_is(TArgs a, i64 n, uint32_t t, double *
     __shared__ uint4 s_xch[4][64];  // normal generator exchange, one row per wave
     const int tid = threadIdx.x;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
-    if (kKind != SMC_TARGET_LOGREG)
-        for (i64 i = gtid; i < n_status; i += gsz) status[i] = 0;
     const int d = a.d;
     const uint32_t tag = kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose;
     const uint32_t tt_ = kInit ? 0u : t;
@@ -297,11 +295,10 @@ __global__ __launch_bounds__(256) void k_reweight(i64 n, int d, const double *__
                                                   const double *__restrict__ lp_new,
                                                   double *__restrict__ logw,
                                                   double *__restrict__ lp, u64 *slots_p,
-                                                  u64 *status, int n_status, double *is_part)
+                                                  double *is_part)
 {
     const int tid = threadIdx.x;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
-    for (i64 i = gtid; i < n_status; i += gsz) status[i] = 0;
     u64 key = 0;
     unsigned bad = 0;
     for (i64 i = gtid; i < n; i += gsz) {
@@ -825,7 +822,6 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t,
         ctrl->mkey = key;
         ctrl->m = m;
         ctrl->err_call = err;
-        ctrl->spin_fail = 0;
         if (err && !ctrl->err_latch) ctrl->err_latch = err;
         ctrl->S = S;
         ctrl->U = U;
@@ -1157,10 +1153,10 @@ void launch_is_k(dim3 g, hipStream_t s, const TArgs &a, i64 n, uint32_t t, doubl
 {
     if (!kInit && out)
         hipLaunchKernelGGL((k_is<kKind, false, DT, true>), g, dim3(256), 0, s, a, n, t, x, logw,
-                           w.lp, sp, w.status, w.n_tiles, w.is_part, w.x_scr, w.lp_scr);
+                           w.lp, sp, w.is_part, w.x_scr, w.lp_scr);
     else
         hipLaunchKernelGGL((k_is<kKind, kInit, DT, false>), g, dim3(256), 0, s, a, n, t, x, logw,
-                           w.lp, sp, w.status, w.n_tiles, w.is_part, (double *)nullptr,
+                           w.lp, sp, w.is_part, (double *)nullptr,
                            (double *)nullptr);
 }
 
@@ -1191,7 +1187,7 @@ hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, do
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
         if (logreg_lp(c, w, x, n, w.lp_new, true, s) != hipSuccess) return hipErrorLaunchFailure;
         hipLaunchKernelGGL(k_reweight<kInit>, g, dim3(256), 0, s, n, c.d, x, w.lp_new, logw,
-                           w.lp, sp, w.status, w.n_tiles, w.is_part);
+                           w.lp, sp, w.is_part);
         break;
     default:
         return hipErrorInvalidValue;

@@ -12,10 +12,13 @@ namespace smc {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kTile = kScanThreads * kScanItems;  // 4096 elements per scan tile
+constexpr int kTileShift = 12;
+static_assert(kTile == 1 << kTileShift, "tile size");
 constexpr int kMaxBlocks = 1024;                  // grid of the max / reweight passes
 constexpr int kIsBlocks = 2048;                   // max grid of the sampler kernels
 constexpr int kExpandThreads = 256;
 constexpr int kSegLen = 2048;                     // merge-path steps per expand workgroup
+static_assert(kSegLen + 1 <= kTile, "an expand segment spans at most two scan tiles");
 constexpr int kLogregSplit = 8;                   // row blocks of the likelihood contraction
 
 struct TilePart {
@@ -27,10 +30,10 @@ struct TilePart {
 struct Work {
     Ctrl *ctrl;
     u64 *slots;         // [2][64][16] max / non-finite slots, double-buffered by parity
-    u64 *status;        // [n_tiles] lookback words
+    u64 *tsum;          // [n_tiles] tile totals, then their exclusive prefix
     TilePart *tpart;    // [n_tiles]
-    u64 *pref;          // [n] inclusive prefix (S_j, or A_j for foreign counts)
-    u64 *pref64;        // [n / 64 + 1] every 64th prefix value (search index)
+    u64 *pref;          // [n] tile-local inclusive prefix (of q, or of foreign counts)
+    u64 *pref64;        // [n / 64 + 1] every 64th tile-local prefix value
     // sampler state (NULL when no target)
     double *lp;         // [n] cached log-target of the current particles
     double *lp_new;     // [n] proposal log-target (costly targets)

@@ -31,7 +31,7 @@ struct smc_ctx {
 namespace {
 
 struct Layout {
-    size_t ctrl, slots, status, tpart, pref, pref64;
+    size_t ctrl, slots, tsum, tpart, pref, pref64;
     size_t lp, lp_new, x_scr, lp_scr, is_part, rec_num;
     size_t xs, thb, lpart;
     int64_t mpad, npad;
@@ -78,7 +78,7 @@ Layout layout_of(const smc_config *c)
     const size_t nt = (size_t)n_tiles_of(c->n);
     L.ctrl = take(sizeof(Ctrl));
     L.slots = take(8 * (size_t)kSlotWords);
-    L.status = take(8 * nt);
+    L.tsum = take(8 * nt);
     L.tpart = take(sizeof(TilePart) * nt);
     L.pref = take(8 * n);
     L.pref64 = take(8 * (n / 64 + 1));
@@ -164,7 +164,7 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
     Work &w = ctx->w;
     w.ctrl = reinterpret_cast<Ctrl *>(b + L.ctrl);
     w.slots = reinterpret_cast<u64 *>(b + L.slots);
-    w.status = reinterpret_cast<u64 *>(b + L.status);
+    w.tsum = reinterpret_cast<u64 *>(b + L.tsum);
     w.tpart = reinterpret_cast<TilePart *>(b + L.tpart);
     w.pref = reinterpret_cast<u64 *>(b + L.pref);
     w.pref64 = reinterpret_cast<u64 *>(b + L.pref64);
