@@ -34,6 +34,12 @@ def particles(n: int, d: int, seed: int, dtype=np.float32) -> np.ndarray:
                                ).astype(dtype, copy=False)
 
 
+# Largest N the library takes; its log-weights repeat a seeded pattern so the
+# exact prefix of the fixed-point weights has a closed form at any index.
+MAX_N = (1 << 31) - 1
+MAX_PERIOD = 1000
+
+
 def offset_word(seed: int) -> int:
     """One 64-bit word used as the systematic offset source."""
     rng = np.random.default_rng(seed)

@@ -230,3 +230,71 @@ def test_module_level_functions(smc, dev):
     ones = smc.resample(torch.from_numpy(flat).to(dev), 1, O.MODE_AUTO)
     assert np.array_equal(ones.cpu().numpy(), np.ones(n, dtype=np.int64))
     assert np.array_equal(O.resample(flat, 1, O.MODE_AUTO)[0], np.ones(n, dtype=np.int64))
+
+
+def test_maximum_size(smc, dev):
+    """N = 2^31 - 1, the largest N the library takes (its last tile ragged),
+    rows of one int32 holding their own source index.  The log-weights repeat
+    a seeded pattern of P values, so the exact prefix has a closed form at any
+    index: S_j = (j div P) Q + C[j mod P], with q of the pattern from the
+    oracle's quantiser.  Exact checks: S, U, sum q^2 and K; sum ncopies = N;
+    sampled counts (both outputs) and sampled output rows against the
+    systematic definition evaluated on that prefix."""
+    import torch
+    n, P = I.MAX_N, I.MAX_PERIOD
+    _say("maximum size N = 2^31 - 1 (about 80 GB of device memory)")
+    base = I.logw_normal(P, 2.0, 404)
+    K = O.quant_bits(n)
+    q = [int(v) for v in O.quantise(base, K, float(base.max()))]
+    C = np.cumsum(np.array(q, dtype=object))
+    Q = int(C[-1])
+    full, rem = divmod(n, P)
+
+    def S_at(j):
+        return (j // P) * Q + int(C[j % P])
+
+    S = S_at(n - 1)
+    q2 = full * sum(v * v for v in q) + sum(v * v for v in q[:rem])
+    r = I.offset_word(I.R_SEED)
+    U = (r * S) >> 64
+
+    def A(j):
+        return (n * S_at(j) + U) // S if j >= 0 else 0
+
+    def anc(p):
+        lo, hi = 0, n - 1          # first j with A_j > p
+        while lo < hi:
+            mid = (lo + hi) // 2
+            if A(mid) > p:
+                hi = mid
+            else:
+                lo = mid + 1
+        return lo
+
+    R = smc.Resampler(n, device=dev)
+    lw = torch.from_numpy(base).to(dev).repeat(full + 1)[:n]
+    x = torch.arange(n, dtype=torch.int32, device=dev)
+    nc1 = torch.empty(n, dtype=torch.int64, device=dev)
+    nc2 = torch.empty(n, dtype=torch.int64, device=dev)
+    R.resample(lw, r, O.MODE_FORCE, ncopies=nc1)
+    xo = R.redistribute(x, ncopies_out=nc2)
+    info = R.info()
+    assert info["err"] == 0 and info["resampled"] == 1 and info["K"] == K
+    assert info["S"] == S and info["U"] == U
+    assert (info["Q2_hi"] << 64) | info["Q2_lo"] == q2
+    assert int(nc1.sum().item()) == n and int(nc2.sum().item()) == n
+    rng = np.random.default_rng(5)
+    js = sorted(set(rng.integers(0, n, 1500).tolist()) |
+                {0, 1, 4095, 4096, P - 1, P, n // 2, n - 4096, n - 2, n - 1})
+    idx = torch.tensor(js, dtype=torch.int64, device=dev)
+    got1, got2 = nc1[idx].cpu().tolist(), nc2[idx].cpu().tolist()
+    for j, a1, a2 in zip(js, got1, got2):
+        want = A(j) - A(j - 1)
+        assert a1 == want and a2 == want, (j, a1, a2, want)
+    ps = sorted(set(rng.integers(0, n, 1500).tolist()) | {0, 1, n // 2, n - 2, n - 1})
+    rows = xo[torch.tensor(ps, dtype=torch.int64, device=dev)].cpu().tolist()
+    for p, row in zip(ps, rows):
+        assert row == anc(p), (p, row)
+    assert R.sync_error() == 0
+    del R, lw, x, nc1, nc2, xo, idx
+    torch.cuda.empty_cache()
