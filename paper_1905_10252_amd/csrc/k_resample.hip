@@ -133,16 +133,23 @@ hipError_t launch_fold(const Work &w, int par, hipStream_t s)
 }
 
 // ------------------------------------------------------------ tile scan
-// Tile = 256 threads x 16 items; tile t is workgroup t.  Global loads and
-// stores are coalesced 16-byte accesses over rows of 512 elements; an LDS
-// transpose (one pad word per 16 entries against bank conflicts) gives each
-// thread 16 consecutive items for the sequential part of the scan.
+// Tile = kScanThreads threads x kScanItems items; tile t is workgroup t.
+// Global loads and stores are coalesced 16-byte accesses over rows of
+// 2 kScanThreads elements; an LDS transpose gives each thread kScanItems
+// consecutive items for the sequential part of the scan.  Entry i of the
+// transpose sits at slot (i ^ (i >> 5)) & 15 of its 16-entry block (a
+// bijection): in both the striped and the per-thread accesses at most two
+// lanes of a wave meet on a bank pair, the minimum for 8-byte accesses, with
+// no pad words.
 // The prefix written is local to the tile; the tile's total goes to tsum[t],
 // which the following single-workgroup pass turns into tile offsets.  A
 // chained scan (each tile waiting for its predecessors' totals) costs a
 // round trip through the memory system per tile in flight; this split costs
 // one small pass over 8 bytes per 4096 weights instead.
-__host__ __device__ constexpr int kPad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int kPad(int i) { return (i & ~15) | ((i ^ (i >> 5)) & 15); }
+constexpr int kScanWaves = kScanThreads / 64;
+constexpr int kScanRow = 2 * kScanThreads;  // elements per striped row
+static_assert(kScanItems % 2 == 0 && 64 % kScanItems == 0, "scan tile shape");
 
 struct ScanArgs {
     const double *lw;   // quantise mode input
@@ -173,13 +180,13 @@ __device__ inline u64 quant_one(double v, double m, int K, u64 top, double &z, d
 }
 
 template <bool kQuant>
-__global__ __launch_bounds__(256) void k_scan(ScanArgs a)
+__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a)
 {
-    __shared__ u64 sq[kTile + kTile / 16];
-    __shared__ u64 s_wsum[4];
-    __shared__ double s_z[4], s_z2[4];
-    __shared__ u64 s_q2lo[4], s_q2hi[4];
-    __shared__ unsigned s_bad[4];
+    __shared__ u64 sq[kTile];
+    __shared__ u64 s_wsum[kScanWaves];
+    __shared__ double s_z[kScanWaves], s_z2[kScanWaves];
+    __shared__ u64 s_q2lo[kScanWaves], s_q2hi[kScanWaves];
+    __shared__ unsigned s_bad[kScanWaves];
 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const i64 n = a.n;
@@ -190,7 +197,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     double z = 0.0, z2 = 0.0;
     U128 q2{0, 0};
     unsigned bad = 0;
-    u64 q[kScanItems];  // striped: q[2r + h] is element base + 512 r + 2 tid + h
+    u64 q[kScanItems];  // striped: q[2r + h] is element base + kScanRow r + 2 tid + h
     if (kQuant) {
         // every wave folds the 64 max slots itself (cached lines; no barrier)
         const double m = okey_inv(wave_max_u64(a.slots_p[lane * kSlotStride]));
@@ -199,16 +206,16 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
         double v[kScanItems];
         if (full && a.vec2) {
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const f64x2_t t =
-                    __builtin_nontemporal_load(reinterpret_cast<const f64x2_t *>(a.lw + base + r * 512 + 2 * tid));
+            for (int r = 0; r < kScanItems / 2; ++r) {
+                const f64x2_t t = __builtin_nontemporal_load(
+                    reinterpret_cast<const f64x2_t *>(a.lw + base + r * kScanRow + 2 * tid));
                 v[2 * r] = t.x;
                 v[2 * r + 1] = t.y;
             }
         } else {
 #pragma unroll
             for (int e = 0; e < kScanItems; ++e) {
-                const i64 i = base + (e >> 1) * 512 + 2 * tid + (e & 1);
+                const i64 i = base + (e >> 1) * kScanRow + 2 * tid + (e & 1);
                 v[e] = i < n ? a.lw[i] : -__builtin_huge_val();
             }
         }
@@ -218,7 +225,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
         i64 c[kScanItems];
 #pragma unroll
         for (int e = 0; e < kScanItems; ++e) {
-            const i64 i = base + (e >> 1) * 512 + 2 * tid + (e & 1);
+            const i64 i = base + (e >> 1) * kScanRow + 2 * tid + (e & 1);
             c[e] = i < n ? a.nc[i] : 0;
         }
 #pragma unroll
@@ -229,7 +236,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
         }
     }
 #pragma unroll
-    for (int e = 0; e < kScanItems; ++e) sq[kPad((e >> 1) * 512 + 2 * tid + (e & 1))] = q[e];
+    for (int e = 0; e < kScanItems; ++e) sq[kPad((e >> 1) * kScanRow + 2 * tid + (e & 1))] = q[e];
     __syncthreads();
 
     // sequential inclusive scan of this thread's 16 consecutive items
@@ -260,7 +267,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     __syncthreads();
     u64 wpre = 0, agg = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kScanWaves; ++i) {
         wpre += (i < wid) ? s_wsum[i] : 0;
         agg += s_wsum[i];
     }
@@ -268,8 +275,8 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     const u64 pre = wpre + incl - run;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) sq[kPad(tid * kScanItems + j)] = pre + loc[j];
-    // every 64th prefix value (items 64g + 63 sit at the end of threads 4h + 3)
-    if ((tid & 3) == 3) {
+    // every 64th prefix value (item 64g + 63 is the last item of its thread)
+    if (((tid + 1) * kScanItems) % 64 == 0) {
         const i64 gi = base + tid * kScanItems + (kScanItems - 1);
         if (gi < n) a.out64[gi >> 6] = pre + loc[kScanItems - 1];
     }
@@ -277,22 +284,29 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
         a.tsum[tile] = agg;
         if (kQuant) {
             TilePart p;
-            p.Z = ((s_z[0] + s_z[1]) + s_z[2]) + s_z[3];
-            p.Z2 = ((s_z2[0] + s_z2[1]) + s_z2[2]) + s_z2[3];
+            double Z = s_z[0], Z2 = s_z2[0];
             U128 t{s_q2lo[0], s_q2hi[0]};
-            for (int i = 1; i < 4; ++i) t = add128(t, U128{s_q2lo[i], s_q2hi[i]});
+            for (int i = 1; i < kScanWaves; ++i) {
+                Z += s_z[i];
+                Z2 += s_z2[i];
+                t = add128(t, U128{s_q2lo[i], s_q2hi[i]});
+            }
+            p.Z = Z;
+            p.Z2 = Z2;
             p.q2lo = t.lo;
             p.q2hi = t.hi;
             a.tpart[tile] = p;
-        } else if (s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3]) {
-            atomicOr(&a.ctrl->ncopy_bad, 1u);
+        } else {
+            unsigned b = 0;
+            for (int i = 0; i < kScanWaves; ++i) b |= s_bad[i];
+            if (b) atomicOr(&a.ctrl->ncopy_bad, 1u);
         }
     }
     __syncthreads();
     if (full) {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int s0 = r * 512 + 2 * tid;
+        for (int r = 0; r < kScanItems / 2; ++r) {
+            const int s0 = r * kScanRow + 2 * tid;
             ulonglong2 v;
             v.x = sq[kPad(s0)];
             v.y = sq[kPad(s0 + 1)];
@@ -301,7 +315,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a)
     } else {
 #pragma unroll
         for (int e = 0; e < kScanItems; ++e) {
-            const int s0 = (e >> 1) * 512 + 2 * tid + (e & 1);
+            const int s0 = (e >> 1) * kScanRow + 2 * tid + (e & 1);
             if (base + s0 < n) a.out[base + s0] = sq[kPad(s0)];
         }
     }
@@ -486,7 +500,7 @@ hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, 
     a.out64 = w.pref64;
     a.slots_p = w.slots + (par & 1) * kSlots * kSlotStride;
     a.n_tiles = w.n_tiles;
-    hipLaunchKernelGGL(k_scan<true>, dim3(w.n_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_scan<true>, dim3(w.n_tiles), dim3(kScanThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -519,7 +533,7 @@ hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, h
     a.out64 = w.pref64;
     a.slots_p = nullptr;
     a.n_tiles = w.n_tiles;
-    hipLaunchKernelGGL(k_scan<false>, dim3(w.n_tiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_scan<false>, dim3(w.n_tiles), dim3(kScanThreads), 0, s, a);
     if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     hipLaunchKernelGGL(k_tile_prefix, dim3(1), dim3(1024), 0, s, w.ctrl, w.tsum, w.n_tiles);
     return hipGetLastError();

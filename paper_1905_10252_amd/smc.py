@@ -112,7 +112,9 @@ _RESAMPLERS: dict = {}
 
 def _resampler(n: int, device) -> Resampler:
     """The Resampler kept for (N, device); module-level calls share it, so a
-    redistribute() without counts follows the last resample() of that N."""
+    redistribute() without counts follows the last resample() of that N.  Its
+    workspace is shared too: module-level calls of one N on one device must
+    not overlap on different streams (use a Resampler each instead)."""
     dev = torch.device(device)
     key = (int(n), dev.type, dev.index if dev.index is not None else torch.cuda.current_device())
     rs = _RESAMPLERS.get(key)
