@@ -183,11 +183,25 @@ struct VecT<4> {
 // stores is non-temporal: the new population is not read again by this call,
 // and keeping it out of the caches spares the next resample the write-back
 // of a cache full of dirty rows (about 5 us per call at N = 2^24 on MI355X).
-template <int VEC>
+// kSum (VEC = 16, rows of four FP64 values): the thread also adds up the two
+// values of every chunk it copies, and their squares, into acc; its chunks all
+// sit in the same half of a row (the lane stride is a multiple of two chunks).
+__device__ inline void add_chunk(const u32x4 &v, double *acc)
+{
+    const double lo = __hiloint2double((int)v.y, (int)v.x);
+    const double hi = __hiloint2double((int)v.w, (int)v.z);
+    acc[0] += lo;
+    acc[1] += hi;
+    acc[2] += lo * lo;
+    acc[3] += hi * hi;
+}
+
+template <int VEC, bool kSum = false>
 __device__ inline void copy_rows(const unsigned char *__restrict__ src,
                                  unsigned char *__restrict__ dst, int row_bytes, int cpr_shift,
-                                 const unsigned *sAnc, i64 p0, int np)
+                                 const unsigned *sAnc, i64 p0, int np, double *acc = nullptr)
 {
+    static_assert(!kSum || VEC == 16, "row sums take 16-byte chunks");
     typedef typename VecT<VEC>::T V;
     const int cpr = row_bytes / VEC;
     const int total = np * cpr;
@@ -213,6 +227,10 @@ __device__ inline void copy_rows(const unsigned char *__restrict__ src,
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) __builtin_nontemporal_store(v[u], reinterpret_cast<V *>(dst + doff[u]));
+        if constexpr (kSum) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) add_chunk(v[u], acc);
+        }
     }
     for (; c < total; c += kExpandThreads) {
         int r, col;
@@ -225,6 +243,34 @@ __device__ inline void copy_rows(const unsigned char *__restrict__ src,
         }
         const V v = *reinterpret_cast<const V *>(src + (i64)sAnc[r] * row_bytes + col * VEC);
         *reinterpret_cast<V *>(dst + (p0 + r) * (i64)row_bytes + col * VEC) = v;
+        if constexpr (kSum) add_chunk(v, acc);
+    }
+}
+
+// Sums of the rows one workgroup wrote (rows of four FP64 values, two 16-byte
+// chunks each): lanes of equal parity hold the same half of a row; their sums
+// are combined in a fixed order and written in the filter's estimate layout
+// (column 0 unused here, 1 the row count, 2 + k the sum of value k, 6 + k the
+// sum of its square).
+__device__ inline void store_row_sums(double *acc, int np, double *out)
+{
+    __shared__ double s_acc[kExpandThreads / 64][2][4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int o = 2; o < 64; o <<= 1) acc[k] += __shfl_xor(acc[k], o, 64);
+    if (lane < 2)
+        for (int k = 0; k < 4; ++k) s_acc[wid][lane][k] = acc[k];
+    __syncthreads();
+    if (tid < kEstCols) {
+        double v = tid == 1 ? (double)np : 0.0;
+        if (tid >= 2) {
+            const int k = (tid - 2) & 3;                  // value k = 2 h + half
+            const int j = (tid >= 6 ? 2 : 0) + (k & 1);   // its sum, or its square's
+            v = s_acc[0][k >> 1][j];
+            for (int w = 1; w < kExpandThreads / 64; ++w) v += s_acc[w][k >> 1][j];
+        }
+        out[tid] = v;
     }
 }
 
@@ -244,9 +290,10 @@ struct ExpandArgs {
     i64 *nc_out;
     i64 *anc_out;
     int skip_identity;  // when the decision is "no resample", write nothing
+    double *est_part;   // kSum: [segments][kEstCols] sums of the rows written
 };
 
-template <int VEC>
+template <int VEC, bool kSum = false>
 __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
 {
     __shared__ unsigned sA[kSegLen + 1];
@@ -306,7 +353,13 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
         if (a.anc_out) a.anc_out[p0 + i] = anc;
     }
     __syncthreads();
-    copy_rows<VEC>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np);
+    if constexpr (kSum) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        copy_rows<VEC, true>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np, acc);
+        store_row_sums(acc, np, a.est_part + (i64)blockIdx.x * kEstCols);
+    } else {
+        copy_rows<VEC>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np);
+    }
     if (a.aux) copy_rows<8>(a.aux, a.auxo, a.aux_bytes, a.aux_shift, sAnc, p0, np);
 }
 
@@ -321,7 +374,7 @@ static int shift_of(int v)
 hipError_t launch_expand(const Work &w, int64_t n, int count_mode, const void *x, void *x_out,
                          int row_bytes, const void *aux, void *aux_out, int aux_bytes,
                          int64_t *ncopies_out, int64_t *anc_out, hipStream_t s,
-                         bool skip_identity)
+                         bool skip_identity, double *est_part)
 {
     ExpandArgs a;
     a.skip_identity = skip_identity ? 1 : 0;
@@ -340,9 +393,15 @@ hipError_t launch_expand(const Work &w, int64_t n, int count_mode, const void *x
     a.aux_shift = shift_of(aux_bytes / 8);
     a.nc_out = reinterpret_cast<i64 *>(ncopies_out);
     a.anc_out = reinterpret_cast<i64 *>(anc_out);
+    a.est_part = est_part;
     const uintptr_t al = (uintptr_t)x | (uintptr_t)x_out | (uintptr_t)row_bytes;
-    const int64_t segs = (2 * n + kSegLen - 1) / kSegLen;
-    if ((al & 15) == 0) {
+    const int64_t segs = expand_segments(n);
+    if (est_part) {
+        if ((al & 15) != 0 || row_bytes != 32) return hipErrorInvalidValue;
+        a.cpr_shift = 1;
+        hipLaunchKernelGGL((k_expand<16, true>), dim3((unsigned)segs), dim3(kExpandThreads), 0, s,
+                           a);
+    } else if ((al & 15) == 0) {
         a.cpr_shift = shift_of(row_bytes / 16);
         hipLaunchKernelGGL(k_expand<16>, dim3((unsigned)segs), dim3(kExpandThreads), 0, s, a);
     } else if ((al & 7) == 0) {

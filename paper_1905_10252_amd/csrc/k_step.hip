@@ -9,12 +9,15 @@
 //   k_step_stats        estimates f_t (eq. estimation_at_t), c_t
 //                       (eq. normconst) and the recycled estimate
 //                       (eq. recycling).
-//   k_copyback          after redistribute: particles and cached log-target
-//                       back in place, weights reset to 1/N (Alg 4 Reset).
+//   k_copyback          after an in-place update and redistribute: particles
+//                       and cached log-target back in place, weights reset to
+//                       1/N (Alg 4 Reset).
+//   k_reset_est         after a redistribution straight into x: the reset,
+//                       and for the filter the post-resampling sums.
 //   k_is<BEARING>       one SIR particle-filter update (Alg 1, Sec. 5.2.2):
 //                       constant-velocity transition as proposal, bearing
-//                       likelihood as weight; k_copyback_est then forms the
-//                       weighted mean of the resampled population.
+//                       likelihood as weight; the expand then adds up the rows
+//                       it writes for the mean of the resampled population.
 //   k_logreg_f64 / k_logreg_bf16 + k_logreg_sum
 //                       Bayesian logistic regression log-likelihood
 //                       sum_m [y_m z_m - softplus(z_m)], z = X theta, in FP64 or
@@ -415,68 +418,15 @@ __global__ __launch_bounds__(256) void k_copyback(const Ctrl *ctrl, i64 n, int d
     }
 }
 
-// Particle filter: copies the resampled rows back in place (when resampling
-// ran; the weights are then equal, exp(0) = 1 each) and forms the sums of the
-// post-resampling estimate (Alg 1) from the rows it already holds; without
-// resampling the sums use the current weights against the exact max.  Same
-// block-partial layout as is_block_finish.
-template <int DT>
-__global__ __launch_bounds__(256) void k_copyback_est(const Ctrl *ctrl, i64 n,
-                                                      double *__restrict__ x,
-                                                      const double *__restrict__ x_scr,
-                                                      double *__restrict__ logw, double reset,
-                                                      double *is_part)
-{
-    __shared__ double s_acc[4][1 + 2 * DT];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
-    const bool rs = ctrl->resample && !ctrl->err_call;
-    const double m = rs ? reset : ctrl->m;
-    double e0 = 0.0, e1[DT], e2[DT];
-    for (int k = 0; k < DT; ++k) e1[k] = e2[k] = 0.0;
-    for (i64 i = gtid; i < n; i += gsz) {
-        double xk[DT];
-        double e;
-        if (rs) {
-            for (int k = 0; k < DT; ++k) xk[k] = x_scr[i * DT + k];
-            for (int k = 0; k < DT; ++k) x[i * DT + k] = xk[k];
-            logw[i] = reset;
-            e = 1.0;
-        } else {
-            for (int k = 0; k < DT; ++k) xk[k] = x[i * DT + k];
-            e = det_exp(logw[i] - m);
-        }
-        e0 += e;
-        for (int k = 0; k < DT; ++k) {
-            const double ex = e * xk[k];
-            e1[k] += ex;
-            e2[k] += ex * xk[k];
-        }
-    }
-    e0 = wave_sum_f64(e0);
-    for (int k = 0; k < DT; ++k) {
-        e1[k] = wave_sum_f64(e1[k]);
-        e2[k] = wave_sum_f64(e2[k]);
-    }
-    if (lane == 0) {
-        s_acc[wid][0] = e0;
-        for (int k = 0; k < DT; ++k) {
-            s_acc[wid][1 + k] = e1[k];
-            s_acc[wid][1 + DT + k] = e2[k];
-        }
-    }
-    __syncthreads();
-    double *part = is_part + (i64)blockIdx.x * (2 + 2 * DT);
-    for (int c = tid; c < 2 + 2 * DT; c += 256)
-        part[c] = c == 0 ? m : ((s_acc[0][c - 1] + s_acc[1][c - 1]) + s_acc[2][c - 1]) +
-                                   s_acc[3][c - 1];
-}
-
 // After a redistribution straight into x: weights reset to 1/N when it
 // resampled; with DT > 0 (the particle filter) also the post-resampling sums
-// of Alg 1, equal weights when resampled, else the current ones.  A step that
-// found an error redistributes nothing: the proposal (and its log-target) is
-// copied into place instead, as the in-place update would have left it.
+// of Alg 1: when resampled, the equal-weight sums the expand formed from the
+// rows it wrote (epart, one row per expand workgroup; NULL when x was not
+// 16-byte aligned for it), gathered into block b's row from workgroups
+// b, b + grid, ... in that order; else read from x, with equal weights when
+// resampled and the current ones against the exact max otherwise.  A step that found an error
+// redistributes nothing: the proposal (and its log-target) is copied into
+// place instead, as the in-place update would have left it.
 template <int DT>
 __global__ __launch_bounds__(256) void k_reset_est(const Ctrl *ctrl, i64 n, int d,
                                                    double *__restrict__ x,
@@ -484,7 +434,8 @@ __global__ __launch_bounds__(256) void k_reset_est(const Ctrl *ctrl, i64 n, int 
                                                    double *__restrict__ lp,
                                                    const double *__restrict__ lp_scr,
                                                    double *__restrict__ logw, double reset,
-                                                   double *is_part)
+                                                   double *is_part, const double *epart,
+                                                   i64 nseg)
 {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
@@ -506,18 +457,24 @@ __global__ __launch_bounds__(256) void k_reset_est(const Ctrl *ctrl, i64 n, int 
         return;
     }
     constexpr int DA = DT > 0 ? DT : 1;
+    if (rs && epart) {
+        static_assert(DT == 0 || 2 + 2 * DA == kEstCols, "filter row layout");
+        for (i64 i = gtid; i < n; i += gsz) logw[i] = reset;
+        if (tid < kEstCols) {
+            double v = 0.0;
+            for (i64 g = blockIdx.x; g < nseg; g += gridDim.x) v += epart[g * kEstCols + tid];
+            is_part[(i64)blockIdx.x * kEstCols + tid] = tid == 0 ? reset : v;
+        }
+        return;
+    }
     __shared__ double s_acc[4][1 + 2 * DA];
     const double m = rs ? reset : ctrl->m;
     double e0 = 0.0, e1[DA], e2[DA];
     for (int k = 0; k < DA; ++k) e1[k] = e2[k] = 0.0;
     for (i64 i = gtid; i < n; i += gsz) {
-        double e;
-        if (rs) {
-            logw[i] = reset;
-            e = 1.0;
-        } else {
-            e = det_exp(logw[i] - m);
-        }
+        double e = 1.0;
+        if (rs) logw[i] = reset;
+        else e = det_exp(logw[i] - m);
         e0 += e;
         for (int k = 0; k < DA; ++k) {
             const double xk = x[i * DA + k];
@@ -1278,9 +1235,12 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
     const bool pf = c.target == SMC_TARGET_BEARING;
     // With resampling forced every iteration the proposal goes to the
     // workspace copy and the redistribution writes straight into x (an
-    // identity copy if the step found an error): no copy back.  With the ESS
-    // rule it is updated in place, and only resampling steps move rows.
-    const bool fwd = c.mode == SMC_MODE_FORCE && c.target != SMC_TARGET_LOGREG;
+    // identity copy if the step found an error or kept the weights): no copy
+    // back.  The particle filter always takes this path (its weights collapse
+    // almost every update, and the expand forms its post-resampling sums from
+    // the rows it writes).  With the ESS rule a sampler is updated in place,
+    // and only resampling steps move rows.
+    const bool fwd = (c.mode == SMC_MODE_FORCE && c.target != SMC_TARGET_LOGREG) || pf;
     if (launch_is<false>(c, w, par, t, x, logw, s, fwd) != hipSuccess) return SMC_E_DEVICE;
     if (launch_quant_scan(w, logw, n, K, par, s) != hipSuccess) return SMC_E_DEVICE;
     const uint64_t r = resample_word(c.seed, c.sampler_id, t);
@@ -1294,33 +1254,30 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
     const double reset = -std::log((double)n);
     if (fwd) {
         // the particle filter carries no cached log-target
+        // the filter's row sums ride on 16-byte chunks of its 32-byte rows
+        double *ep = (pf && ((uintptr_t)x & 15) == 0) ? w.epart : nullptr;
         if (launch_expand(w, n, 0, w.x_scr, x, c.d * 8, pf ? nullptr : w.lp_scr,
-                          pf ? nullptr : w.lp, 8, nullptr, nullptr, s, false) != hipSuccess)
+                          pf ? nullptr : w.lp, 8, nullptr, nullptr, s, false, ep) != hipSuccess)
             return SMC_E_DEVICE;
         if (pf) {  // Alg 1 takes the mean after resampling
             hipLaunchKernelGGL(k_reset_est<4>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)n,
                                c.d, x, w.x_scr, (double *)nullptr, (const double *)nullptr,
-                               logw, reset, w.is_part);
+                               logw, reset, w.is_part, (const double *)ep,
+                               (i64)expand_segments(n));
             hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
                                w.is_grid, c.d, w.rec_num, est, info, 0);
         } else {
             hipLaunchKernelGGL(k_reset_est<0>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)n,
-                               c.d, x, w.x_scr, w.lp, w.lp_scr, logw, reset, w.is_part);
+                               c.d, x, w.x_scr, w.lp, w.lp_scr, logw, reset, w.is_part,
+                               (const double *)nullptr, (i64)0);
         }
         return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
     }
-    if (launch_expand(w, n, 0, x, w.x_scr, c.d * 8, pf ? nullptr : w.lp,
-                      pf ? nullptr : w.lp_scr, 8, nullptr, nullptr, s, true) != hipSuccess)
+    if (launch_expand(w, n, 0, x, w.x_scr, c.d * 8, w.lp, w.lp_scr, 8, nullptr, nullptr, s,
+                      true) != hipSuccess)
         return SMC_E_DEVICE;
-    if (pf) {  // Alg 1 takes the mean after resampling
-        hipLaunchKernelGGL(k_copyback_est<4>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl,
-                           (i64)n, x, w.x_scr, logw, reset, w.is_part);
-        hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
-                           w.is_grid, c.d, w.rec_num, est, info, 0);
-    } else {
-        hipLaunchKernelGGL(k_copyback, dim3(grid_for(n * c.d)), dim3(256), 0, s, w.ctrl, (i64)n,
-                           c.d, x, w.x_scr, w.lp, w.lp_scr, logw, reset);
-    }
+    hipLaunchKernelGGL(k_copyback, dim3(grid_for(n * c.d)), dim3(256), 0, s, w.ctrl, (i64)n, c.d,
+                       x, w.x_scr, w.lp, w.lp_scr, logw, reset);
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
 

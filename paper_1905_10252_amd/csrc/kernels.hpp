@@ -18,6 +18,7 @@ constexpr int kMaxBlocks = 1024;                  // grid of the max / reweight 
 constexpr int kIsBlocks = 2048;                   // max grid of the sampler kernels
 constexpr int kExpandThreads = 256;
 constexpr int kSegLen = 2048;                     // merge-path steps per expand workgroup
+constexpr int kEstCols = 10;                      // 2 + 2 d sums of a filter row (d = 4)
 static_assert(kSegLen + 1 <= kTile, "an expand segment spans at most two scan tiles");
 constexpr int kLogregSplit = 8;                   // row blocks of the likelihood contraction
 
@@ -41,6 +42,8 @@ struct Work {
     double *lp_scr;     // [n]
     double *is_part;    // [kIsBlocks * (2 + 2d)] per-block estimate sums
     double *rec_num;    // [2d] recycled estimate sums
+    double *epart;      // particle filter: [expand segments][kEstCols] row sums of the
+                        // redistributed rows (NULL otherwise)
     // logistic regression (NULL otherwise)
     unsigned short *xs;   // [mpad][dp] bf16 rows of X times (1 - 2 y)
     unsigned short *thb;  // [npad][dp] bf16 copy of the particles
@@ -74,9 +77,12 @@ hipError_t launch_clear_scan(const Work &w, hipStream_t s);
 hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, hipStream_t s);
 hipError_t launch_ncopies(const Work &w, int64_t n, int count_mode, int64_t *ncopies,
                           hipStream_t s);
+// est_part (nullable; rows of four FP64 values only): per workgroup, the
+// count, sums and sums of squares of the rows it wrote, kEstCols doubles.
 hipError_t launch_expand(const Work &w, int64_t n, int count_mode, const void *x, void *x_out,
                          int row_bytes, const void *aux, void *aux_out, int aux_bytes,
                          int64_t *ncopies_out, int64_t *anc_out, hipStream_t s,
-                         bool skip_identity);
+                         bool skip_identity, double *est_part = nullptr);
+inline int64_t expand_segments(int64_t n) { return (2 * n + kSegLen - 1) / kSegLen; }
 
 }  // namespace smc

@@ -32,7 +32,7 @@ namespace {
 
 struct Layout {
     size_t ctrl, slots, tsum, tpart, pref, pref64;
-    size_t lp, lp_new, x_scr, lp_scr, is_part, rec_num;
+    size_t lp, lp_new, x_scr, lp_scr, is_part, rec_num, epart;
     size_t xs, thb, lpart;
     int64_t mpad, npad;
     int dp;
@@ -82,7 +82,7 @@ Layout layout_of(const smc_config *c)
     L.tpart = take(sizeof(TilePart) * nt);
     L.pref = take(8 * n);
     L.pref64 = take(8 * (n / 64 + 1));
-    L.lp = L.lp_new = L.x_scr = L.lp_scr = L.is_part = L.rec_num = 0;
+    L.lp = L.lp_new = L.x_scr = L.lp_scr = L.is_part = L.rec_num = L.epart = 0;
     L.xs = L.thb = L.lpart = 0;
     L.dp = (int)((d + 15) / 16 * 16);
     L.mpad = (c->m_rows + 31) / 32 * 32;
@@ -94,6 +94,8 @@ Layout layout_of(const smc_config *c)
         L.lp_scr = take(8 * n);
         L.is_part = take(8 * (size_t)kIsBlocks * (2 + 2 * d));
         L.rec_num = take(8 * 2 * d);
+        if (c->target == SMC_TARGET_BEARING)
+            L.epart = take(8 * (size_t)kEstCols * (size_t)expand_segments(c->n));
         if (c->target == SMC_TARGET_LOGREG) {
             L.lpart = take(8 * (size_t)kLogregSplit * n);
             if (c->loglik_precision == SMC_PREC_BF16) {
@@ -176,6 +178,7 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
     w.lp_scr = samp ? reinterpret_cast<double *>(b + L.lp_scr) : nullptr;
     w.is_part = samp ? reinterpret_cast<double *>(b + L.is_part) : nullptr;
     w.rec_num = samp ? reinterpret_cast<double *>(b + L.rec_num) : nullptr;
+    w.epart = L.epart ? reinterpret_cast<double *>(b + L.epart) : nullptr;
     w.lpart = L.lpart ? reinterpret_cast<double *>(b + L.lpart) : nullptr;
     w.xs = L.xs ? reinterpret_cast<unsigned short *>(b + L.xs) : nullptr;
     w.thb = L.thb ? reinterpret_cast<unsigned short *>(b + L.thb) : nullptr;

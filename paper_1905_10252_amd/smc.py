@@ -123,6 +123,11 @@ def _resampler(n: int, device) -> Resampler:
     return rs
 
 
+def release() -> None:
+    """Drops the contexts (and workspaces) kept by the module-level calls."""
+    _RESAMPLERS.clear()
+
+
 def resample(logw: torch.Tensor, r: int, mode: int = L.MODE_AUTO,
              ncopies: torch.Tensor | None = None) -> torch.Tensor:
     """Alg 4 on the log-weights ``logw`` (float64 [N], device) with the

@@ -102,3 +102,28 @@ def test_pf_full_size(smc, dev, mode):
     assert np.array_equal(bits(g.logw.cpu().numpy()), bits(o.logw))
     assert close(g.estimates()["mean"], out["mean"], 1e-11)
     assert abs(info["log_c"] - out["log_c"]) <= 1e-10 * max(1.0, abs(out["log_c"]))
+
+
+def test_pf_rows_not_16_byte_aligned(smc, dev):
+    """A caller's particle array that is only 8-byte aligned: the expand cannot
+    add up its 32-byte rows in 16-byte chunks on the way, so the
+    post-resampling sums are read back from the rows instead; same results."""
+    import ctypes as C
+    import torch
+    print("pf unaligned rows", flush=True)
+    n = 5000
+    g, o = pair(smc, dev, n, 8, O.MODE_FORCE)
+    buf = torch.empty(n * 4 + 1, dtype=torch.float64, device=dev)
+    xm = buf[1:].view(n, 4)
+    assert xm.data_ptr() % 16 == 8
+    xm.copy_(g.x)
+    for t in range(4):
+        rc = g._lib.smc_step(g.ctx, C.c_void_p(xm.data_ptr()), C.c_void_p(g.logw.data_ptr()),
+                             C.c_void_p(g.info_buf.data_ptr()), C.c_void_p(g.est.data_ptr()),
+                             smc._stream())
+        assert rc == 0
+        out = o.step()
+        assert np.array_equal(bits(xm.cpu().numpy()), bits(o.x)), t
+        assert np.array_equal(bits(g.logw.cpu().numpy()), bits(o.logw)), t
+        assert close(g.estimates()["mean"], out["mean"], 1e-11), t
+        assert close(g.estimates()["m2"], out["m2"], 1e-11), t

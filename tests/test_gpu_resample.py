@@ -230,6 +230,9 @@ def test_module_level_functions(smc, dev):
     ones = smc.resample(torch.from_numpy(flat).to(dev), 1, O.MODE_AUTO)
     assert np.array_equal(ones.cpu().numpy(), np.ones(n, dtype=np.int64))
     assert np.array_equal(O.resample(flat, 1, O.MODE_AUTO)[0], np.ones(n, dtype=np.int64))
+    smc.release()
+    with pytest.raises(smc.L.SmcError):
+        smc.redistribute(torch.from_numpy(xs[n]).to(dev))   # a new context has nothing pending
 
 
 def test_maximum_size(smc, dev):
