@@ -247,6 +247,40 @@ __device__ inline void copy_rows(const unsigned char *__restrict__ src,
     }
 }
 
+// Rows of 8 bytes with an 8-byte side row each (a 1-D sampler's particle and
+// its cached log-target): both copies in one loop, twice the loads in flight.
+__device__ inline void copy_rows_8x2(const unsigned char *__restrict__ src,
+                                     unsigned char *__restrict__ dst,
+                                     const unsigned char *__restrict__ src2,
+                                     unsigned char *__restrict__ dst2, const unsigned *sAnc,
+                                     i64 p0, int np)
+{
+    typedef unsigned long long V;
+    const V *s1 = reinterpret_cast<const V *>(src), *s2 = reinterpret_cast<const V *>(src2);
+    V *d1 = reinterpret_cast<V *>(dst) + p0, *d2 = reinterpret_cast<V *>(dst2) + p0;
+    constexpr int U = 4;
+    int r = threadIdx.x;
+    for (; r + (U - 1) * kExpandThreads < np; r += U * kExpandThreads) {
+        V v[U], w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const unsigned j = sAnc[r + u * kExpandThreads];
+            v[u] = s1[j];
+            w[u] = s2[j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            __builtin_nontemporal_store(v[u], d1 + r + u * kExpandThreads);
+            __builtin_nontemporal_store(w[u], d2 + r + u * kExpandThreads);
+        }
+    }
+    for (; r < np; r += kExpandThreads) {
+        const unsigned j = sAnc[r];
+        d1[r] = s1[j];
+        d2[r] = s2[j];
+    }
+}
+
 // Sums of the rows one workgroup wrote (rows of four FP64 values, two 16-byte
 // chunks each): lanes of equal parity hold the same half of a row; their sums
 // are combined in a fixed order and written in the filter's estimate layout
@@ -357,6 +391,9 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         copy_rows<VEC, true>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np, acc);
         store_row_sums(acc, np, a.est_part + (i64)blockIdx.x * kEstCols);
+    } else if (VEC == 8 && a.row_bytes == 8 && a.aux && a.aux_bytes == 8) {
+        copy_rows_8x2(a.x, a.xo, a.aux, a.auxo, sAnc, p0, np);
+        return;
     } else {
         copy_rows<VEC>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np);
     }
