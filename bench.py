@@ -101,10 +101,23 @@ def sampler_metrics(dev):
         if rep >= 2:
             tot += ms
             lat += per
+    # the launch floor: one trivial kernel per step, timed the same way
+    one = torch.zeros(1, device=dev)
+    for _ in range(20):
+        one.add_(1.0)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(201)]
+    ev[0].record()
+    for i in range(200):
+        one.add_(1.0)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    floor = [ev[i].elapsed_time(ev[i + 1]) for i in range(200)]
     out["gauss1d_N1024"] = {"iters_per_s": round(runs * g["iters"] / (tot / 1e3), 1),
                             "us_per_iter": round(1e3 * tot / (runs * g["iters"]), 2),
                             "p50_us": round(1e3 * pctl(lat, 50), 2),
-                            "p99_us": round(1e3 * pctl(lat, 99), 2)}
+                            "p99_us": round(1e3 * pctl(lat, 99), 2),
+                            "one_trivial_launch_p50_us": round(1e3 * pctl(floor, 50), 2)}
     # Student-t (nu = 5, mu = 1), N = 2^24, resampling every iteration, 100 iterations
     n = 1 << 24
     S = smc.Sampler(n, 1, "student", seed=1, rw_sd=0.5, nu=5.0, mu=1.0, mode=smc.L.MODE_FORCE,
