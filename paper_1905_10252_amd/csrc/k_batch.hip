@@ -137,6 +137,28 @@ __device__ inline double row16_sum(double v)
 }
 
 // Position of block b in a prefix table: slot and index within the slot.
+// Rows [0, cnt) x columns [0, w) of a row-major block (row stride d, w <= 16)
+// into LDS as whole lines: 16 lanes a row, 16 rows per pass.  Every load of a
+// thread is issued before the first wait (its address is clamped into the
+// block, so the loads need no branch); a loop that waits for each load in
+// turn spends most of a wave's life on memory latency.
+__device__ inline void stage_rows(double (*sx)[17], const GLB(double) *xb, int d, int cnt, int w)
+{
+    const int tid = threadIdx.x, lc = tid & 15, lr = tid >> 4;
+    const int cc = lc < w ? lc : w - 1;
+    double v[kBChunk / 16];
+#pragma unroll
+    for (int j = 0; j < kBChunk / 16; ++j) {
+        const int r = lr + 16 * j;
+        v[j] = xb[(i64)(r < cnt ? r : cnt - 1) * d + cc];
+    }
+#pragma unroll
+    for (int j = 0; j < kBChunk / 16; ++j) {
+        const int r = lr + 16 * j;
+        if (r < cnt && lc < w) sx[r][lc] = v[j];
+    }
+}
+
 __device__ inline bool locate(const int *pref, const int *act, int nact, int b, int &slot,
                               int &local)
 {
@@ -297,8 +319,7 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
         const int cnt = (int)((n - base) < kBChunk ? (n - base) : kBChunk);
         const int lc = tid & 15, lr = tid >> 4;
         GLB(double) *xb = glb(S.ctrl->cur ? S.x_scr : S.x) + base * d + k0;
-        for (int r = lr; r < cnt; r += 16)
-            if (lc < w) sx[r][lc] = xb[(i64)r * d + lc];
+        stage_rows(sx, xb, d, cnt, w);
         __syncthreads();
         for (int k2 = kp0; k2 < kp1; ++k2) {
             double z[2];
@@ -383,8 +404,7 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         if (q * PW < d) {
-            for (int r = lr; r < cnt; r += 16)
-                if (lc < PW && q * PW + lc < d) sx[r][lc] = xb[(i64)r * d + q * PW + lc];
+            stage_rows(sx, xb + q * PW, d, cnt, d - q * PW < PW ? d - q * PW : PW);
             __syncthreads();
 #pragma unroll
             for (int c = 0; c < PW; ++c) {
