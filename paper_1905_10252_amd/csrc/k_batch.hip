@@ -856,13 +856,29 @@ __global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *
     const int R = 64 / dp2;
     const int col = lane & (dp2 - 1), rsub = lane / dp2;
     const i64 pw = (i64)ch * kBChunk + wid * 64;
-    for (int o0 = 0; o0 < 64; o0 += R) {
-        const int o = o0 + rsub;
-        const int lo32 = __shfl((int)(anc & 0xffffffff), o, kWave);
-        const int hi32 = __shfl((int)(anc >> 32), o, kWave);
-        const i64 src = ((i64)hi32 << 32) | (i64)(unsigned)lo32;
-        const i64 pp = pw + o;
-        if (col < d && pp < n) glb(xd)[pp * d + col] = glb(xs)[src * d + col];
+    // a wave copies its 64 rows R at a time; UB such steps' loads are issued
+    // before the first wait (addresses clamped into the array, so no branch)
+    constexpr int UB = 8;
+    const int cc = col < d ? col : d - 1;
+    for (int o0 = 0; o0 < 64; o0 += R * UB) {
+        double v[UB];
+        i64 dst[UB];
+        bool ok[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const int o = o0 + u * R + rsub;
+            const int oc = o < 64 ? o : 63;
+            const int lo32 = __shfl((int)(anc & 0xffffffff), oc, kWave);
+            const int hi32 = __shfl((int)(anc >> 32), oc, kWave);
+            const i64 src = ((i64)hi32 << 32) | (i64)(unsigned)lo32;
+            const i64 pp = pw + o;
+            ok[u] = o < 64 && col < d && pp < n;
+            dst[u] = pp * d + col;
+            v[u] = glb(xs)[src * d + cc];
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u)
+            if (ok[u]) glb(xd)[dst[u]] = v[u];
     }
 }
 
