@@ -15,6 +15,11 @@ from . import _lib as L
 
 
 def _stream():
+    # torch's current HIP stream; the raw getter skips building a Stream
+    # object (about 0.3 instead of 4 us a call)
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return C.c_void_p(raw(torch.cuda.current_device()))
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
