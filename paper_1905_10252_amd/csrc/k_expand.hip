@@ -12,9 +12,9 @@
 // A_j is computed from the fixed-point prefix as floor((N S_j + U) / S), or is
 // the prefix of caller-supplied counts, or j + 1 when the ESS rule decided not
 // to resample.  A prefix value is the scan's tile-local value plus the offset
-// of its tile of 4096.  The segment boundaries are found by a 64-ary search run by one
-// wavefront; the test A_j + j < k is evaluated as N S_j + U < (k - j) S in
-// 128-bit integers (no division).
+// of its tile of 4096.  The segment boundaries are found by a 64-ary search
+// run by one wavefront; the test A_j + j < k is evaluated as
+// N S_j + U < (k - j) S in 128-bit integers (no division).
 #include <hip/hip_runtime.h>
 
 #include "../../include/smc.h"
