@@ -397,7 +397,6 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
     constexpr int PW = DB < 16 ? DB : 16;
     const i64 base = (i64)chunk * kBChunk;
     const int cnt = (int)((n - base) < kBChunk ? (n - base) : kBChunk);
-    const int lc = tid & 15, lr = tid >> 4;
     const GLB(double) *xb = glb(alt ? S.x_scr : S.x) + base * d;
     constexpr int NQ = (DB + PW - 1) / PW;
     double tv[DB];
