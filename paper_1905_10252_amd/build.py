@@ -17,6 +17,9 @@ ARCH = "gfx950"
 FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results land in VGPRs (gfx950 allows it): the likelihood epilogue
+    # reads them without an accumulator-register move per element
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 

@@ -933,12 +933,13 @@ __global__ __launch_bounds__(256) void k_logreg_f64(const double *__restrict__ t
 // One wavefront owns 32 particles (MFMA columns) and streams 32-row tiles of X
 // (MFMA rows) through v_mfma_f32_32x32x16_bf16; the softplus epilogue runs on
 // the FP32 accumulators and sums per particle.
-__device__ inline float softplus_f32(float t)
+// softplus(t) = max(t, 0) + ln 2 log2(1 + 2^(-|t| log2 e)); the caller keeps
+// the two sums apart and scales the second by ln 2 once per particle.
+__device__ inline void softplus_acc(float t, float &pos, float &lg)
 {
-    const float a = fabsf(t);
-    const float e = __builtin_amdgcn_exp2f(-a * 1.4426950408889634f);
-    const float l = __builtin_amdgcn_logf(1.0f + e) * 0.6931471805599453f;
-    return fmaxf(t, 0.0f) + l;
+    const float e = __builtin_amdgcn_exp2f(fabsf(t) * -1.4426950408889634f);
+    lg += __builtin_amdgcn_logf(1.0f + e);
+    pos += fmaxf(t, 0.0f);
 }
 
 template <int KS>
@@ -959,7 +960,7 @@ __global__ __launch_bounds__(256) void k_logreg_bf16(const unsigned short *__res
     const i64 per = (tiles + gridDim.y - 1) / gridDim.y;
     const i64 t0 = (i64)blockIdx.y * per;
     const i64 t1 = t0 + per < tiles ? t0 + per : tiles;
-    float sp = 0.0f;
+    float pos = 0.0f, lg = 0.0f;
     for (i64 tt = t0; tt < t1; ++tt) {
         const i64 m0 = tt * 32;
         f32x16 acc = {};
@@ -971,15 +972,16 @@ __global__ __launch_bounds__(256) void k_logreg_bf16(const unsigned short *__res
         }
         if (m0 + 32 <= m_rows) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) sp += softplus_f32(acc[r]);
+            for (int r = 0; r < 16; ++r) softplus_acc(acc[r], pos, lg);
         } else {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const i64 row = m0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                if (row < m_rows) sp += softplus_f32(acc[r]);
+                if (row < m_rows) softplus_acc(acc[r], pos, lg);
             }
         }
     }
+    float sp = pos + lg * 0.6931471805599453f;
     sp += __shfl_xor(sp, 32, kWave);
     if (lane < 32 && p0 + lane < n) lpart[(i64)blockIdx.y * n + p0 + lane] = -(double)sp;
 }
