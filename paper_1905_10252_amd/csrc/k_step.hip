@@ -933,13 +933,16 @@ __global__ __launch_bounds__(256) void k_logreg_f64(const double *__restrict__ t
 // One wavefront owns 32 particles (MFMA columns) and streams 32-row tiles of X
 // (MFMA rows) through v_mfma_f32_32x32x16_bf16; the softplus epilogue runs on
 // the FP32 accumulators and sums per particle.
-// softplus(t) = max(t, 0) + ln 2 log2(1 + 2^(-|t| log2 e)); the caller keeps
-// the two sums apart and scales the second by ln 2 once per particle.
-__device__ inline void softplus_acc(float t, float &pos, float &lg)
+// softplus(t) = (t + |t|) / 2 + ln(1 + e^(-|t|)).  A lane's 16 accumulator
+// values of one tile each give a factor 1 + 2^(-|t| log2 e) in (1, 2]; their
+// product (at most 2^16) takes one log2 per tile.  The sums of t, |t| and the
+// log2 terms are kept apart and combined once per particle.
+__device__ inline void softplus_acc(float t, float &st, float &sa, float &prod)
 {
     const float e = __builtin_amdgcn_exp2f(fabsf(t) * -1.4426950408889634f);
-    lg += __builtin_amdgcn_logf(1.0f + e);
-    pos += fmaxf(t, 0.0f);
+    prod = fmaf(prod, e, prod);
+    st += t;
+    sa += fabsf(t);
 }
 
 template <int KS>
@@ -960,7 +963,7 @@ __global__ __launch_bounds__(256) void k_logreg_bf16(const unsigned short *__res
     const i64 per = (tiles + gridDim.y - 1) / gridDim.y;
     const i64 t0 = (i64)blockIdx.y * per;
     const i64 t1 = t0 + per < tiles ? t0 + per : tiles;
-    float pos = 0.0f, lg = 0.0f;
+    float st = 0.0f, sa = 0.0f, lg = 0.0f;
     for (i64 tt = t0; tt < t1; ++tt) {
         const i64 m0 = tt * 32;
         f32x16 acc = {};
@@ -970,18 +973,20 @@ __global__ __launch_bounds__(256) void k_logreg_bf16(const unsigned short *__res
                 *reinterpret_cast<const bf16x8 *>(xs + (m0 + col) * dp + 16 * s + 8 * kh);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(afr, bfr[s], acc, 0, 0, 0);
         }
+        float prod = 1.0f;
         if (m0 + 32 <= m_rows) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) softplus_acc(acc[r], pos, lg);
+            for (int r = 0; r < 16; ++r) softplus_acc(acc[r], st, sa, prod);
         } else {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const i64 row = m0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                if (row < m_rows) softplus_acc(acc[r], pos, lg);
+                if (row < m_rows) softplus_acc(acc[r], st, sa, prod);
             }
         }
+        lg += __builtin_amdgcn_logf(prod);
     }
-    float sp = pos + lg * 0.6931471805599453f;
+    float sp = 0.5f * (st + sa) + lg * 0.6931471805599453f;
     sp += __shfl_xor(sp, 32, kWave);
     if (lane < 32 && p0 + lane < n) lpart[(i64)blockIdx.y * n + p0 + lane] = -(double)sp;
 }
