@@ -46,7 +46,7 @@ struct TArgs {
     double init_mean, init_sd, init_prec, init_log_norm, rw_sd;
     uint64_t seed;
     uint32_t sampler;
-    unsigned short *thb;  // bf16 copy of the particles [npad][dp] (nullable)
+    unsigned short *thb;  // bf16 copy of the particles times log2 e [npad][dp] (nullable)
     // bearing-only particle filter
     const double *obs;    // measurements, y_t = obs[t - 1]
     double delta, l11, l21, l22, obs_prec, obs_log_norm, reset;
@@ -59,6 +59,13 @@ __device__ inline unsigned short to_bf16(double v)
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (unsigned short)(u >> 16);
 }
+
+__device__ inline double from_bf16(unsigned short h) { return (double)__uint_as_float((unsigned)h << 16); }
+
+// The BF16 likelihood works in base 2: the bf16 particles hold theta log2 e, so
+// that the MFMA yields t log2 e and the epilogue's exponentials need no scaling.
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
 
 // ------------------------------------------------------------------ partials
 // Per-block sums for the estimates with the block's own max (rescaled later):
@@ -252,7 +259,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 const double xk = kInit ? a.init_mean + a.init_sd * z[h] : xi[kk] + a.rw_sd * z[h];
                 xw[kk] = xk;
                 if (DT > 0 && kk < DT) xv[kk] = xk;
-                if (a.thb) a.thb[i * a.dp + kk] = to_bf16(xk);
+                if (a.thb) a.thb[i * a.dp + kk] = to_bf16(xk * kLog2e);
                 if (kKind == SMC_TARGET_GAUSS) {
                     const double tt = xk - a.mean[kk];
                     acc = acc + (tt * tt) * a.prec[kk];
@@ -932,17 +939,17 @@ __global__ __launch_bounds__(256) void k_logreg_f64(const double *__restrict__ t
 // y_m z_m - softplus(z_m) = -softplus(s_m z_m) and the epilogue needs no labels.
 // One wavefront owns 32 particles (MFMA columns) and streams 32-row tiles of X
 // (MFMA rows) through v_mfma_f32_32x32x16_bf16; the softplus epilogue runs on
-// the FP32 accumulators and sums per particle.
-// softplus(t) = (t + |t|) / 2 + ln(1 + e^(-|t|)).  A lane's 16 accumulator
-// values of one tile each give a factor 1 + 2^(-|t| log2 e) in (1, 2]; their
-// product (at most 2^16) takes one log2 per tile.  The sums of t, |t| and the
-// log2 terms are kept apart and combined once per particle.
-__device__ inline void softplus_acc(float t, float &st, float &sa, float &prod)
+// the FP32 accumulators, which hold u = t log2 e for t = s_m z_m.
+// softplus(t) = ln 2 [(u + |u|) / 2 + log2(1 + 2^(-|u|))].  A lane's 16
+// accumulator values of one tile each give a factor 1 + 2^(-|u|) in (1, 2];
+// their product (at most 2^16) takes one log2 per tile.  The kernel sums |u|
+// and the log2 terms; the sum of u over all rows is theta . (sum_m x_m s_m)
+// log2 e, added once per particle by k_logreg_sum from the column sums of X.
+__device__ inline void softplus_acc(float u, float &sa, float &prod)
 {
-    const float e = __builtin_amdgcn_exp2f(fabsf(t) * -1.4426950408889634f);
+    const float e = __builtin_amdgcn_exp2f(-fabsf(u));
     prod = fmaf(prod, e, prod);
-    st += t;
-    sa += fabsf(t);
+    sa += fabsf(u);
 }
 
 template <int KS>
@@ -963,7 +970,7 @@ __global__ __launch_bounds__(256) void k_logreg_bf16(const unsigned short *__res
     const i64 per = (tiles + gridDim.y - 1) / gridDim.y;
     const i64 t0 = (i64)blockIdx.y * per;
     const i64 t1 = t0 + per < tiles ? t0 + per : tiles;
-    float st = 0.0f, sa = 0.0f, lg = 0.0f;
+    float sa = 0.0f, lg = 0.0f;
     for (i64 tt = t0; tt < t1; ++tt) {
         const i64 m0 = tt * 32;
         f32x16 acc = {};
@@ -976,25 +983,43 @@ __global__ __launch_bounds__(256) void k_logreg_bf16(const unsigned short *__res
         float prod = 1.0f;
         if (m0 + 32 <= m_rows) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) softplus_acc(acc[r], st, sa, prod);
+            for (int r = 0; r < 16; ++r) softplus_acc(acc[r], sa, prod);
         } else {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const i64 row = m0 + 8 * (r >> 2) + 4 * kh + (r & 3);
-                if (row < m_rows) softplus_acc(acc[r], st, sa, prod);
+                if (row < m_rows) softplus_acc(acc[r], sa, prod);
             }
         }
         lg += __builtin_amdgcn_logf(prod);
     }
-    float sp = 0.5f * (st + sa) + lg * 0.6931471805599453f;
+    float sp = 0.5f * sa + lg;
     sp += __shfl_xor(sp, 32, kWave);
-    if (lane < 32 && p0 + lane < n) lpart[(i64)blockIdx.y * n + p0 + lane] = -(double)sp;
+    if (lane < 32 && p0 + lane < n) lpart[(i64)blockIdx.y * n + p0 + lane] = -kLn2 * (double)sp;
 }
 
+// Column sums of the stored bf16 X s (rows below m_rows; padding is zero), one
+// workgroup per column, FP64 in a fixed order.
+__global__ __launch_bounds__(256) void k_xs_colsum(const unsigned short *xs, i64 m_rows, int dp,
+                                                   double *csum)
+{
+    __shared__ double red[4];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    double v = 0.0;
+    for (i64 m = tid; m < m_rows; m += 256) v += from_bf16(xs[m * dp + k]);
+    v = wave_sum_f64(v);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) csum[k] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// log pi = log_norm - prior_prec |theta|^2 / 2 + the partial likelihoods; with
+// csum (the BF16 path), also - ln 2 / 2 times the sum over all rows of u.
 __global__ __launch_bounds__(256) void k_logreg_sum(const double *theta, i64 n, int d,
                                                     const double *lpart, int msplit,
                                                     double log_norm, double prior_prec,
-                                                    double *lp)
+                                                    const unsigned short *thb, int dp,
+                                                    const double *csum, double *lp)
 {
     const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
     for (i64 i = gtid; i < n; i += gsz) {
@@ -1002,6 +1027,11 @@ __global__ __launch_bounds__(256) void k_logreg_sum(const double *theta, i64 n, 
         for (int k = 0; k < d; ++k) pr += theta[i * d + k] * theta[i * d + k];
         double s = 0.0;
         for (int j = 0; j < msplit; ++j) s += lpart[(i64)j * n + i];
+        if (csum) {
+            double su = 0.0;
+            for (int k = 0; k < d; ++k) su += from_bf16(thb[i * dp + k]) * csum[k];
+            s -= 0.5 * kLn2 * su;
+        }
         lp[i] = log_norm - 0.5 * prior_prec * pr + s;
     }
 }
@@ -1028,7 +1058,7 @@ __global__ __launch_bounds__(256) void k_theta_bf16(const double *x, i64 n, int 
     for (i64 e = gtid; e < n * d; e += gsz) {
         const i64 i = e / d;
         const int k = (int)(e - i * d);
-        thb[i * dp + k] = to_bf16(x[e]);
+        thb[i * dp + k] = to_bf16(x[e] * kLog2e);
     }
 }
 
@@ -1084,7 +1114,7 @@ bool is_bf16(const smc_config &c)
 hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_t n, double *lp,
                      bool theta_ready, hipStream_t s)
 {
-    if (c.target != SMC_TARGET_LOGREG || !w.lpart || (is_bf16(c) && (!w.xs || !w.thb)))
+    if (c.target != SMC_TARGET_LOGREG || !w.lpart || (is_bf16(c) && (!w.xs || !w.thb || !w.csum)))
         return hipErrorInvalidValue;
     const int msplit = kLogregSplit;
     if (is_bf16(c)) {
@@ -1108,8 +1138,10 @@ hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_
         else if (c.d <= 32) hipLaunchKernelGGL(k_logreg_f64<32>, grid, dim3(256), 0, s, x, (i64)n, c.d, X, c.y, c.m_rows, w.lpart);
         else hipLaunchKernelGGL(k_logreg_f64<64>, grid, dim3(256), 0, s, x, (i64)n, c.d, X, c.y, c.m_rows, w.lpart);
     }
+    const bool bf = is_bf16(c);
     hipLaunchKernelGGL(k_logreg_sum, dim3(grid_for(n)), dim3(256), 0, s, x, (i64)n, c.d, w.lpart,
-                       msplit, c.log_norm, c.prior_prec, lp);
+                       msplit, c.log_norm, c.prior_prec, bf ? w.thb : nullptr, w.dp,
+                       bf ? w.csum : nullptr, lp);
     return hipGetLastError();
 }
 
@@ -1209,6 +1241,8 @@ smc_status step_init(const smc_config &c, const Work &w, int par, double *x, dou
         hipLaunchKernelGGL(k_prep_x, dim3(grid_for(w.mpad * w.dp)), dim3(256), 0, s,
                            reinterpret_cast<const double *>(c.X), c.y, (i64)c.m_rows, c.d,
                            (i64)w.mpad, w.dp, w.xs, w.thb, (i64)thb_elems);
+        hipLaunchKernelGGL(k_xs_colsum, dim3(c.d), dim3(256), 0, s, w.xs, (i64)c.m_rows, w.dp,
+                           w.csum);
         if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     }
     if (launch_is<true>(c, w, par, 0u, x, logw, s) != hipSuccess) return SMC_E_DEVICE;

@@ -46,7 +46,8 @@ struct Work {
                         // redistributed rows (NULL otherwise)
     // logistic regression (NULL otherwise)
     unsigned short *xs;   // [mpad][dp] bf16 rows of X times (1 - 2 y)
-    unsigned short *thb;  // [npad][dp] bf16 copy of the particles
+    unsigned short *thb;  // [npad][dp] bf16 copy of the particles times log2 e
+    double *csum;         // [dp] column sums of xs (rows below m_rows)
     double *lpart;        // [kLogregSplit][n] partial log-likelihoods
     int64_t mpad, npad;
     int dp;
