@@ -896,6 +896,11 @@ __global__ __launch_bounds__(256) void k_lp_cheap(TArgs a, i64 n, const double *
 }
 
 // --------------------------------------------- logistic regression, FP64
+// With s_m = 1 - 2 y_m and u = s_m z_m, y_m z_m - softplus(z_m) = -softplus(u),
+// and softplus(u) = (u + |u|) / 2 + log1p(e^(-|u|)).  Per 64-row block the
+// factors 1 + e^(-|u|) in (1, 2] are multiplied (at most 2^64) and one log is
+// taken; the kernel sums |u| and those logs, and the sum of u over all rows,
+// theta . (sum_m s_m x_m), is added once per particle by k_logreg_sum.
 constexpr int kLrRows = 64;
 
 template <int DB>
@@ -905,7 +910,6 @@ __global__ __launch_bounds__(256) void k_logreg_f64(const double *__restrict__ t
                                                     double *__restrict__ lpart)
 {
     __shared__ double sX[kLrRows][DB];
-    __shared__ double sy[kLrRows];
     const i64 i = (i64)blockIdx.x * 256 + threadIdx.x;
     double th[DB];
 #pragma unroll
@@ -913,25 +917,50 @@ __global__ __launch_bounds__(256) void k_logreg_f64(const double *__restrict__ t
     const i64 per = (m_rows + gridDim.y - 1) / gridDim.y;
     const i64 r0 = (i64)blockIdx.y * per;
     const i64 r1 = r0 + per < m_rows ? r0 + per : m_rows;
-    double acc = 0.0;
+    double sa = 0.0, lg = 0.0;
     for (i64 rb = r0; rb < r1; rb += kLrRows) {
         const int nr = (int)(r1 - rb < kLrRows ? r1 - rb : kLrRows);
         __syncthreads();
         for (int e = threadIdx.x; e < kLrRows * DB; e += 256) {
             const int r = e / DB, k = e - r * DB;
-            sX[r][k] = (r < nr && k < d) ? X[(rb + r) * d + k] : 0.0;
+            double v = 0.0;
+            if (r < nr && k < d) {
+                v = X[(rb + r) * d + k];
+                if (y[rb + r] != 0.0) v = -v;
+            }
+            sX[r][k] = v;
         }
-        if (threadIdx.x < kLrRows) sy[threadIdx.x] = (int)threadIdx.x < nr ? y[rb + threadIdx.x] : 0.0;
         __syncthreads();
+        double prod = 1.0;
         for (int r = 0; r < nr; ++r) {
-            double z = 0.0;
+            double u = 0.0;
 #pragma unroll
-            for (int k = 0; k < DB; ++k) z = fma(sX[r][k], th[k], z);
-            const double sp = z > 0.0 ? z + log1p(exp(-z)) : log1p(exp(z));
-            acc += sy[r] * z - sp;
+            for (int k = 0; k < DB; ++k) u = fma(sX[r][k], th[k], u);
+            const double au = fabs(u);
+            prod = fma(prod, exp(-au), prod);
+            sa += au;
         }
+        lg += log(prod);
     }
-    if (i < n) lpart[(i64)blockIdx.y * n + i] = acc;
+    if (i < n) lpart[(i64)blockIdx.y * n + i] = -(0.5 * sa + lg);
+}
+
+// Column sums of X s (rows below m_rows), one workgroup per column, FP64 in
+// a fixed order.
+__global__ __launch_bounds__(256) void k_x_colsum(const double *X, const double *y, i64 m_rows,
+                                                  int d, double *csum)
+{
+    __shared__ double red[4];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    double v = 0.0;
+    for (i64 m = tid; m < m_rows; m += 256) {
+        const double xv = X[m * d + k];
+        v += y[m] != 0.0 ? -xv : xv;
+    }
+    v = wave_sum_f64(v);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) csum[k] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // ------------------------------------ logistic regression, BF16 MFMA (gfx950)
@@ -1013,13 +1042,14 @@ __global__ __launch_bounds__(256) void k_xs_colsum(const unsigned short *xs, i64
     if (tid == 0) csum[k] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// log pi = log_norm - prior_prec |theta|^2 / 2 + the partial likelihoods; with
-// csum (the BF16 path), also - ln 2 / 2 times the sum over all rows of u.
+// log pi = log_norm - prior_prec |theta|^2 / 2 + the partial likelihoods
+// - usc (theta' . csum), where theta' is the bf16 copy thb when given (it holds
+// theta log2 e) and theta otherwise.
 __global__ __launch_bounds__(256) void k_logreg_sum(const double *theta, i64 n, int d,
                                                     const double *lpart, int msplit,
                                                     double log_norm, double prior_prec,
                                                     const unsigned short *thb, int dp,
-                                                    const double *csum, double *lp)
+                                                    const double *csum, double usc, double *lp)
 {
     const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
     for (i64 i = gtid; i < n; i += gsz) {
@@ -1027,12 +1057,10 @@ __global__ __launch_bounds__(256) void k_logreg_sum(const double *theta, i64 n, 
         for (int k = 0; k < d; ++k) pr += theta[i * d + k] * theta[i * d + k];
         double s = 0.0;
         for (int j = 0; j < msplit; ++j) s += lpart[(i64)j * n + i];
-        if (csum) {
-            double su = 0.0;
-            for (int k = 0; k < d; ++k) su += from_bf16(thb[i * dp + k]) * csum[k];
-            s -= 0.5 * kLn2 * su;
-        }
-        lp[i] = log_norm - 0.5 * prior_prec * pr + s;
+        double su = 0.0;
+        for (int k = 0; k < d; ++k)
+            su += (thb ? from_bf16(thb[i * dp + k]) : theta[i * d + k]) * csum[k];
+        lp[i] = log_norm - 0.5 * prior_prec * pr + (s - usc * su);
     }
 }
 
@@ -1114,7 +1142,7 @@ bool is_bf16(const smc_config &c)
 hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_t n, double *lp,
                      bool theta_ready, hipStream_t s)
 {
-    if (c.target != SMC_TARGET_LOGREG || !w.lpart || (is_bf16(c) && (!w.xs || !w.thb || !w.csum)))
+    if (c.target != SMC_TARGET_LOGREG || !w.lpart || !w.csum || (is_bf16(c) && (!w.xs || !w.thb)))
         return hipErrorInvalidValue;
     const int msplit = kLogregSplit;
     if (is_bf16(c)) {
@@ -1140,8 +1168,8 @@ hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_
     }
     const bool bf = is_bf16(c);
     hipLaunchKernelGGL(k_logreg_sum, dim3(grid_for(n)), dim3(256), 0, s, x, (i64)n, c.d, w.lpart,
-                       msplit, c.log_norm, c.prior_prec, bf ? w.thb : nullptr, w.dp,
-                       bf ? w.csum : nullptr, lp);
+                       msplit, c.log_norm, c.prior_prec, bf ? w.thb : nullptr, w.dp, w.csum,
+                       bf ? 0.5 * kLn2 : 0.5, lp);
     return hipGetLastError();
 }
 
@@ -1243,6 +1271,10 @@ smc_status step_init(const smc_config &c, const Work &w, int par, double *x, dou
                            (i64)w.mpad, w.dp, w.xs, w.thb, (i64)thb_elems);
         hipLaunchKernelGGL(k_xs_colsum, dim3(c.d), dim3(256), 0, s, w.xs, (i64)c.m_rows, w.dp,
                            w.csum);
+        if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
+    } else if (c.target == SMC_TARGET_LOGREG) {
+        hipLaunchKernelGGL(k_x_colsum, dim3(c.d), dim3(256), 0, s,
+                           reinterpret_cast<const double *>(c.X), c.y, (i64)c.m_rows, c.d, w.csum);
         if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     }
     if (launch_is<true>(c, w, par, 0u, x, logw, s) != hipSuccess) return SMC_E_DEVICE;

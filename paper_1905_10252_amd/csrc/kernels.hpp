@@ -47,7 +47,7 @@ struct Work {
     // logistic regression (NULL otherwise)
     unsigned short *xs;   // [mpad][dp] bf16 rows of X times (1 - 2 y)
     unsigned short *thb;  // [npad][dp] bf16 copy of the particles times log2 e
-    double *csum;         // [dp] column sums of xs (rows below m_rows)
+    double *csum;         // [dp] column sums of X (1 - 2 y) (of xs for BF16)
     double *lpart;        // [kLogregSplit][n] partial log-likelihoods
     int64_t mpad, npad;
     int dp;

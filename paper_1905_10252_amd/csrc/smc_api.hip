@@ -98,10 +98,10 @@ Layout layout_of(const smc_config *c)
             L.epart = take(8 * (size_t)kEstCols * (size_t)expand_segments(c->n));
         if (c->target == SMC_TARGET_LOGREG) {
             L.lpart = take(8 * (size_t)kLogregSplit * n);
+            L.csum = take(8 * (size_t)L.dp);
             if (c->loglik_precision == SMC_PREC_BF16) {
                 L.xs = take(2 * (size_t)L.mpad * L.dp);
                 L.thb = take(2 * (size_t)L.npad * L.dp);
-                L.csum = take(8 * (size_t)L.dp);
             }
         }
     }
