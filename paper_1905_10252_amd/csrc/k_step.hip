@@ -897,52 +897,105 @@ __global__ __launch_bounds__(256) void k_lp_cheap(TArgs a, i64 n, const double *
 
 // --------------------------------------------- logistic regression, FP64
 // With s_m = 1 - 2 y_m and u = s_m z_m, y_m z_m - softplus(z_m) = -softplus(u),
-// and softplus(u) = (u + |u|) / 2 + log1p(e^(-|u|)).  Per 64-row block the
-// factors 1 + e^(-|u|) in (1, 2] are multiplied (at most 2^64) and one log is
-// taken; the kernel sums |u| and those logs, and the sum of u over all rows,
-// theta . (sum_m s_m x_m), is added once per particle by k_logreg_sum.
-constexpr int kLrRows = 64;
+// and softplus(u) = (u + |u|) / 2 + log1p(e^(-|u|)).  The kernel sums |u| and
+// the logs of products of 64 factors 1 + e^(-|u|) in (1, 2] (at most 2^64);
+// the sum of u over all rows, theta . (sum_m s_m x_m), is added once per
+// particle by k_logreg_sum.
+//
+// u = (X s) theta runs on v_mfma_f64_16x16x4_f64, so the matrix unit takes the
+// contraction while the vector ALU runs the exponentials.  One wavefront owns
+// 16 particles (MFMA columns) and streams 16-row tiles of X s (MFMA rows) from
+// xf, where each tile is stored in the order the MFMA A operand is read:
+// xf[tile][lane][s] = s_m x_{m,k}, m = 16 tile + lane % 16, k = 4 s + lane / 16
+// (zero beyond M and d), so a lane's KS values are contiguous and a tile is
+// one contiguous 512 KS-byte read per wavefront.  The epilogue relies only on
+// each lane's accumulators belonging to column lane % 16: it sums a column's
+// rows whatever their order across lanes.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2v __attribute__((ext_vector_type(2)));
 
-template <int DB>
-__global__ __launch_bounds__(256) void k_logreg_f64(const double *__restrict__ theta, i64 n, int d,
-                                                    const double *__restrict__ X,
-                                                    const double *__restrict__ y, i64 m_rows,
-                                                    double *__restrict__ lpart)
+__device__ inline void softplus_acc64(double u, double &sa, double &prod)
 {
-    __shared__ double sX[kLrRows][DB];
-    const i64 i = (i64)blockIdx.x * 256 + threadIdx.x;
-    double th[DB];
+    const double au = fabs(u);
+    prod = fma(prod, exp(-au), prod);
+    sa += au;
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_logreg_f64(const double *__restrict__ theta, i64 n, int d,
+                                                    const double *__restrict__ xf, i64 m_rows,
+                                                    i64 mpad, double *__restrict__ lpart)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const i64 p0 = ((i64)blockIdx.x * 4 + wid) * 16;
+    if (p0 >= n) return;
+    const int col = lane & 15, kq = lane >> 4;
+    const i64 p = p0 + col;
+    double b[KS];
 #pragma unroll
-    for (int k = 0; k < DB; ++k) th[k] = (i < n && k < d) ? theta[i * d + k] : 0.0;
-    const i64 per = (m_rows + gridDim.y - 1) / gridDim.y;
-    const i64 r0 = (i64)blockIdx.y * per;
-    const i64 r1 = r0 + per < m_rows ? r0 + per : m_rows;
-    double sa = 0.0, lg = 0.0;
-    for (i64 rb = r0; rb < r1; rb += kLrRows) {
-        const int nr = (int)(r1 - rb < kLrRows ? r1 - rb : kLrRows);
-        __syncthreads();
-        for (int e = threadIdx.x; e < kLrRows * DB; e += 256) {
-            const int r = e / DB, k = e - r * DB;
-            double v = 0.0;
-            if (r < nr && k < d) {
-                v = X[(rb + r) * d + k];
-                if (y[rb + r] != 0.0) v = -v;
-            }
-            sX[r][k] = v;
-        }
-        __syncthreads();
-        double prod = 1.0;
-        for (int r = 0; r < nr; ++r) {
-            double u = 0.0;
-#pragma unroll
-            for (int k = 0; k < DB; ++k) u = fma(sX[r][k], th[k], u);
-            const double au = fabs(u);
-            prod = fma(prod, exp(-au), prod);
-            sa += au;
-        }
-        lg += log(prod);
+    for (int s = 0; s < KS; ++s) {
+        const int k = 4 * s + kq;
+        b[s] = (p < n && k < d) ? theta[p * d + k] : 0.0;
     }
-    if (i < n) lpart[(i64)blockIdx.y * n + i] = -(0.5 * sa + lg);
+    const i64 tiles = mpad / 16;
+    const i64 per = (tiles + gridDim.y - 1) / gridDim.y;
+    const i64 t0 = (i64)blockIdx.y * per;
+    const i64 t1 = t0 + per < tiles ? t0 + per : tiles;
+    double sa = 0.0, lg = 0.0, prod = 1.0;
+    int cnt = 0;
+    for (i64 tt = t0; tt < t1; ++tt) {
+        const double *ap = xf + (tt * 64 + lane) * KS;
+        double a[KS];
+        if constexpr (KS == 1) {
+            a[0] = ap[0];
+        } else {
+#pragma unroll
+            for (int s = 0; s < KS; s += 2) {
+                const f64x2v v = *reinterpret_cast<const f64x2v *>(ap + s);
+                a[s] = v[0];
+                a[s + 1] = v[1];
+            }
+        }
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) softplus_acc64(acc[v], sa, prod);
+        if (++cnt == 16) {
+            lg += log(prod);
+            prod = 1.0;
+            cnt = 0;
+        }
+    }
+    double sp = 0.5 * sa + (lg + log(prod));
+    sp += __shfl_xor(sp, 16, kWave);
+    sp += __shfl_xor(sp, 32, kWave);
+    // Rows of the last tile beyond M are zero: u = 0 there, and each added a
+    // factor of exactly 2 (and nothing to |u|), whichever lane held it.
+    const i64 lo = t0 * 16 > m_rows ? t0 * 16 : m_rows, hi = t1 * 16;
+    if (hi > lo) sp -= (double)(hi - lo) * kLn2;
+    if (lane < 16 && p < n) lpart[(i64)blockIdx.y * n + p] = -sp;
+}
+
+// xf (above) from the caller's X and y.
+__global__ __launch_bounds__(256) void k_prep_xf(const double *X, const double *y, i64 m_rows,
+                                                 int d, i64 mpad, int ks, double *xf)
+{
+    const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
+    const i64 per_tile = 64 * (i64)ks;
+    for (i64 e = gtid; e < mpad * 4 * ks; e += gsz) {
+        const i64 t = e / per_tile;
+        const int rem = (int)(e - t * per_tile);
+        const int lane = rem / ks, sidx = rem - lane * ks;
+        const i64 m = 16 * t + (lane & 15);
+        const int k = 4 * sidx + (lane >> 4);
+        double v = 0.0;
+        if (m < m_rows && k < d) {
+            v = X[m * d + k];
+            if (y[m] != 0.0) v = -v;
+        }
+        xf[e] = v;
+    }
 }
 
 // Column sums of X s (rows below m_rows), one workgroup per column, FP64 in
@@ -1142,7 +1195,8 @@ bool is_bf16(const smc_config &c)
 hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_t n, double *lp,
                      bool theta_ready, hipStream_t s)
 {
-    if (c.target != SMC_TARGET_LOGREG || !w.lpart || !w.csum || (is_bf16(c) && (!w.xs || !w.thb)))
+    if (c.target != SMC_TARGET_LOGREG || !w.lpart || !w.csum || (is_bf16(c) && (!w.xs || !w.thb)) ||
+        (!is_bf16(c) && !w.xf))
         return hipErrorInvalidValue;
     const int msplit = kLogregSplit;
     if (is_bf16(c)) {
@@ -1159,12 +1213,15 @@ hipError_t logreg_lp(const smc_config &c, const Work &w, const double *x, int64_
         default: hipLaunchKernelGGL(k_logreg_bf16<4>, grid, dim3(256), 0, s, w.thb, (i64)n, xs, c.m_rows, w.mpad, w.dp, w.lpart); break;
         }
     } else {
-        const dim3 grid((unsigned)((n + 255) / 256), msplit);
-        const double *X = reinterpret_cast<const double *>(c.X);
-        if (c.d <= 8) hipLaunchKernelGGL(k_logreg_f64<8>, grid, dim3(256), 0, s, x, (i64)n, c.d, X, c.y, c.m_rows, w.lpart);
-        else if (c.d <= 16) hipLaunchKernelGGL(k_logreg_f64<16>, grid, dim3(256), 0, s, x, (i64)n, c.d, X, c.y, c.m_rows, w.lpart);
-        else if (c.d <= 32) hipLaunchKernelGGL(k_logreg_f64<32>, grid, dim3(256), 0, s, x, (i64)n, c.d, X, c.y, c.m_rows, w.lpart);
-        else hipLaunchKernelGGL(k_logreg_f64<64>, grid, dim3(256), 0, s, x, (i64)n, c.d, X, c.y, c.m_rows, w.lpart);
+        const dim3 grid((unsigned)((n + 63) / 64), msplit);
+        const double *xf = w.xf;
+        switch (lr_ks(c.d)) {
+        case 1: hipLaunchKernelGGL(k_logreg_f64<1>, grid, dim3(256), 0, s, x, (i64)n, c.d, xf, c.m_rows, w.mpad, w.lpart); break;
+        case 2: hipLaunchKernelGGL(k_logreg_f64<2>, grid, dim3(256), 0, s, x, (i64)n, c.d, xf, c.m_rows, w.mpad, w.lpart); break;
+        case 4: hipLaunchKernelGGL(k_logreg_f64<4>, grid, dim3(256), 0, s, x, (i64)n, c.d, xf, c.m_rows, w.mpad, w.lpart); break;
+        case 8: hipLaunchKernelGGL(k_logreg_f64<8>, grid, dim3(256), 0, s, x, (i64)n, c.d, xf, c.m_rows, w.mpad, w.lpart); break;
+        default: hipLaunchKernelGGL(k_logreg_f64<16>, grid, dim3(256), 0, s, x, (i64)n, c.d, xf, c.m_rows, w.mpad, w.lpart); break;
+        }
     }
     const bool bf = is_bf16(c);
     hipLaunchKernelGGL(k_logreg_sum, dim3(grid_for(n)), dim3(256), 0, s, x, (i64)n, c.d, w.lpart,
@@ -1273,6 +1330,10 @@ smc_status step_init(const smc_config &c, const Work &w, int par, double *x, dou
                            w.csum);
         if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     } else if (c.target == SMC_TARGET_LOGREG) {
+        const int ks = lr_ks(c.d);
+        hipLaunchKernelGGL(k_prep_xf, dim3(grid_for(w.mpad * 4 * ks)), dim3(256), 0, s,
+                           reinterpret_cast<const double *>(c.X), c.y, (i64)c.m_rows, c.d,
+                           (i64)w.mpad, ks, w.xf);
         hipLaunchKernelGGL(k_x_colsum, dim3(c.d), dim3(256), 0, s,
                            reinterpret_cast<const double *>(c.X), c.y, (i64)c.m_rows, c.d, w.csum);
         if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;

@@ -48,6 +48,7 @@ struct Work {
     unsigned short *xs;   // [mpad][dp] bf16 rows of X times (1 - 2 y)
     unsigned short *thb;  // [npad][dp] bf16 copy of the particles times log2 e
     double *csum;         // [dp] column sums of X (1 - 2 y) (of xs for BF16)
+    double *xf;           // FP64: [mpad / 16][64][lr_ks(d)] X (1 - 2 y) in MFMA operand order
     double *lpart;        // [kLogregSplit][n] partial log-likelihoods
     int64_t mpad, npad;
     int dp;
@@ -55,6 +56,8 @@ struct Work {
     int is_grid;        // blocks of the sampler kernels (rows of is_part)
 };
 
+// FP64 likelihood: MFMA k-steps of four columns, d padded to a power of two.
+inline int lr_ks(int d) { return d <= 4 ? 1 : d <= 8 ? 2 : d <= 16 ? 4 : d <= 32 ? 8 : 16; }
 inline int n_tiles_of(int64_t n) { return (int)((n + kTile - 1) / kTile); }
 inline int max_blocks_of(int64_t n)
 {

@@ -33,7 +33,7 @@ namespace {
 struct Layout {
     size_t ctrl, slots, tsum, tpart, pref, pref64;
     size_t lp, lp_new, x_scr, lp_scr, is_part, rec_num, epart;
-    size_t xs, thb, csum, lpart;
+    size_t xs, thb, csum, xf, lpart;
     int64_t mpad, npad;
     int dp;
     size_t total;
@@ -83,7 +83,7 @@ Layout layout_of(const smc_config *c)
     L.pref = take(8 * n);
     L.pref64 = take(8 * (n / 64 + 1));
     L.lp = L.lp_new = L.x_scr = L.lp_scr = L.is_part = L.rec_num = L.epart = 0;
-    L.xs = L.thb = L.csum = L.lpart = 0;
+    L.xs = L.thb = L.csum = L.xf = L.lpart = 0;
     L.dp = (int)((d + 15) / 16 * 16);
     L.mpad = (c->m_rows + 31) / 32 * 32;
     L.npad = (int64_t)((n + 31) / 32 * 32);
@@ -102,6 +102,8 @@ Layout layout_of(const smc_config *c)
             if (c->loglik_precision == SMC_PREC_BF16) {
                 L.xs = take(2 * (size_t)L.mpad * L.dp);
                 L.thb = take(2 * (size_t)L.npad * L.dp);
+            } else {
+                L.xf = take(8 * (size_t)L.mpad * 4 * lr_ks(c->d));
             }
         }
     }
@@ -184,6 +186,7 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
     w.xs = L.xs ? reinterpret_cast<unsigned short *>(b + L.xs) : nullptr;
     w.thb = L.thb ? reinterpret_cast<unsigned short *>(b + L.thb) : nullptr;
     w.csum = L.csum ? reinterpret_cast<double *>(b + L.csum) : nullptr;
+    w.xf = L.xf ? reinterpret_cast<double *>(b + L.xf) : nullptr;
     w.mpad = L.mpad;
     w.npad = L.npad;
     w.dp = L.dp;
