@@ -146,7 +146,7 @@ def sampler_metrics(dev):
     # Bayesian logistic regression: M = 65536, D = 32, N = 2^16
     c = I.LOGREG
     X, y, _ = I.logreg_data(c["m_rows"], c["d"], 200)
-    for prec, k in (("bf16", 6), ("f64", 2)):
+    for prec, k in (("bf16", 20), ("f64", 6)):
         S = smc.Sampler(c["n"], c["d"], "logreg", X=X.astype(np.float64), y=y,
                         prior_var=c["prior_var"], precision=prec, rw_sd=c["rw_sd"],
                         init_sd=math.sqrt(c["prior_var"]), device=dev)
@@ -275,8 +275,12 @@ def batch_metrics(dev, timed_steps):
 
 def only_workload(name, steps, warmup):
     """One sampler workload alone (a profiling target): the Student-t sampler
-    or the bearing-only filter at N = 2^24 with resampling every iteration, or
-    one batched step of the 256-sampler workload; prints ms per iteration."""
+    or the bearing-only filter at N = 2^24 with resampling every iteration,
+    the logistic-regression sampler (N = 2^16, M = 65536, D = 32) with a BF16 or
+    FP64 likelihood, or one batched step of the 256-sampler workload; prints ms
+    per iteration."""
+    import math
+    import numpy as np
     import torch
     from paper_1905_10252_amd import inputs as I
     from paper_1905_10252_amd import smc
@@ -285,6 +289,12 @@ def only_workload(name, steps, warmup):
     if name == "student":
         S = smc.Sampler(n, 1, "student", seed=1, rw_sd=0.5, nu=5.0, mu=1.0,
                         mode=smc.L.MODE_FORCE, device=dev)
+    elif name.startswith("logreg"):
+        c = I.LOGREG
+        X, y, _ = I.logreg_data(c["m_rows"], c["d"], 200)
+        S = smc.Sampler(c["n"], c["d"], "logreg", X=X.astype(np.float64), y=y,
+                        prior_var=c["prior_var"], precision=name.split("_")[1], rw_sd=c["rw_sd"],
+                        init_sd=math.sqrt(c["prior_var"]), device=dev)
     elif name == "bearing":
         B = I.BEARING
         _, ys = I.bearing_track(warmup + steps + 1, 7)
@@ -319,7 +329,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one plain device copy of the 1 GiB particle array "
                          "(reference for hardware byte counters)")
-    ap.add_argument("--only", choices=("student", "bearing", "batch"), default=None,
+    ap.add_argument("--only", choices=("student", "bearing", "batch", "logreg_bf16", "logreg_f64"), default=None,
                     help="run only --steps iterations of one sampler workload (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
