@@ -70,6 +70,38 @@ def cpu_baseline(budget_s: float = 10.0, max_calls: int = 12):
                       % (calls, "/".join("%g" % s for s in I.RESAMPLE_SCALES), spent)}
 
 
+def cpu_openmp(budget_s: float = 4.0, max_calls: int = 30):
+    """The same resample + redistribute on every host core (OpenMP build of the
+    exact-integer systematic path, ``baseline/``), full-size inputs cycling
+    over the scales; a comparison point beside the single-core oracle."""
+    import baseline as B
+    from paper_1905_10252_amd import inputs as I
+    n, d = I.RESAMPLE_N, I.RESAMPLE_D
+    x = I.particles(n, d, I.X_SEED)
+    r = I.offset_word(I.R_SEED)
+    lws = {s: I.logw_normal(n, s, I.LOGW_SEEDS[s]) for s in I.RESAMPLE_SCALES}
+    ws = B.Workspace(n, x.shape[1:], x.dtype)
+    B.resample_redistribute(lws[I.RESAMPLE_SCALES[0]], r, x, ws)  # first touch of the outputs
+    done, spent, calls = 0, 0.0, 0
+    while spent < budget_s and calls < max_calls:
+        s = I.RESAMPLE_SCALES[calls % len(I.RESAMPLE_SCALES)]
+        t0 = time.perf_counter()
+        B.resample_redistribute(lws[s], r, x, ws)
+        spent += time.perf_counter() - t0
+        done += n
+        calls += 1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": done / spent, "unit": "resampled particles/s", "cores": B.threads(),
+            "kind": "openmp", "cpu": model, "nproc": os.cpu_count(),
+            "sample": "%d full-size calls (N=2^24, d=16, s cycled over %s), %.2f s"
+                      % (calls, "/".join("%g" % s for s in I.RESAMPLE_SCALES), spent)}
+
+
 def sampler_metrics(dev):
     """SMC iterations per second of whole smc_step iterations (Alg 2) on three
     workloads; each timed with events around whole runs after warm-up."""
@@ -324,7 +356,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baselines (oracle and OpenMP)")
     ap.add_argument("--no-samplers", action="store_true", help="skip the smc_step workloads")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one plain device copy of the 1 GiB particle array "
@@ -460,6 +492,7 @@ def main():
         out["smc_iters"] = sampler_metrics(dev)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
+        out["cpu_openmp"] = cpu_openmp()
     print(json.dumps(out))
 
 
