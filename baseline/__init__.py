@@ -38,6 +38,9 @@ def load():
         lib.omp_resample_redistribute.argtypes = [
             C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
             C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.omp_logreg_loglik.restype = C.c_int
+        lib.omp_logreg_loglik.argtypes = [C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
+                                          C.c_int64, C.c_void_p]
         _lib = lib
     return _lib
 
@@ -78,3 +81,18 @@ def resample_redistribute(lw: np.ndarray, r: int, x: np.ndarray, ws: Workspace |
             "Q2_lo": int(ws.res[3]), "K": int(ws.res[4]), "Z": float(ws.zres[0]),
             "Z2": float(ws.zres[1]), "m": float(ws.zres[2])}
     return ws.ncopies, ws.x_out, info
+
+
+def logreg_loglik(theta: np.ndarray, X: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """sum_r y_r z - softplus(z), z = X_r . theta_i, for every row theta_i."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    n, d = theta.shape
+    if X.shape[1] != d or y.shape[0] != X.shape[0]:
+        raise ValueError("shapes of theta, X and y do not match")
+    out = np.empty(n, dtype=np.float64)
+    if load().omp_logreg_loglik(theta.ctypes.data, n, d, X.ctypes.data, y.ctypes.data,
+                                X.shape[0], out.ctypes.data) != 0:
+        raise MemoryError("omp_logreg_loglik: no memory for the transposed X")
+    return out

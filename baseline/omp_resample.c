@@ -196,3 +196,46 @@ int omp_resample_redistribute(const double *lw, int64_t n, uint64_t r, const voi
     free(soff);
     return 0;
 }
+
+/* Logistic-regression log-likelihood on every host core: for each of the n
+ * particles theta_i (rows of d values), the sum over the m rows of X of
+ * y_r z - softplus(z), z = X_r . theta_i, softplus in the overflow-safe form
+ * max(z, 0) + log1p(exp(-|z|)).  The particles are split over the threads;
+ * X is transposed once so that z for 64 rows at a time is a vector loop. */
+enum { LR_ROWS = 64 };
+
+__attribute__((target_clones("avx2", "default")))
+static void logreg_one(const double *th, int d, const double *Xt, const double *y, int64_t m,
+                       double *out)
+{
+    double acc = 0.0;
+    double z[LR_ROWS];
+    for (int64_t r0 = 0; r0 < m; r0 += LR_ROWS) {
+        const int nr = m - r0 < LR_ROWS ? (int)(m - r0) : LR_ROWS;
+        for (int j = 0; j < LR_ROWS; ++j) z[j] = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double *xk = Xt + (int64_t)k * m + r0;
+            const double t = th[k];
+            for (int j = 0; j < nr; ++j) z[j] += xk[j] * t;
+        }
+        for (int j = 0; j < nr; ++j) {
+            const double sp = (z[j] > 0.0 ? z[j] : 0.0) + log1p(exp(-fabs(z[j])));
+            acc += y[r0 + j] * z[j] - sp;
+        }
+    }
+    *out = acc;
+}
+
+int omp_logreg_loglik(const double *theta, int64_t n, int d, const double *X, const double *y,
+                      int64_t m, double *out)
+{
+    double *Xt = (double *)malloc(sizeof(double) * (size_t)m * (size_t)d);
+    if (!Xt) return 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < m; ++r)
+        for (int k = 0; k < d; ++k) Xt[(int64_t)k * m + r] = X[r * d + k];
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) logreg_one(theta + i * d, d, Xt, y, m, out + i);
+    free(Xt);
+    return 0;
+}

@@ -96,10 +96,25 @@ def cpu_openmp(budget_s: float = 4.0, max_calls: int = 30):
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
+    # the logistic-regression likelihood (the cost of one iteration of that
+    # sampler) on a subset of the particles, extrapolated to N = 2^16
+    import numpy as np
+    c = I.LOGREG
+    X, y, _ = I.logreg_data(c["m_rows"], c["d"], 200)
+    sub = 1024
+    th = np.random.default_rng(1).standard_normal((sub, c["d"])) * 0.3
+    t0 = time.perf_counter()
+    B.logreg_loglik(th, X, y)
+    t_sub = time.perf_counter() - t0
+    per_iter = t_sub * c["n"] / sub
     return {"value": done / spent, "unit": "resampled particles/s", "cores": B.threads(),
             "kind": "openmp", "cpu": model, "nproc": os.cpu_count(),
             "sample": "%d full-size calls (N=2^24, d=16, s cycled over %s), %.2f s"
-                      % (calls, "/".join("%g" % s for s in I.RESAMPLE_SCALES), spent)}
+                      % (calls, "/".join("%g" % s for s in I.RESAMPLE_SCALES), spent),
+            "logreg_f64": {"s_per_iter_extrapolated": round(per_iter, 2),
+                           "iters_per_s": round(1.0 / per_iter, 4),
+                           "sample": "FP64 likelihood of %d of the N=2^16 particles (M=65536, "
+                                     "D=32) in %.2f s, scaled by %d" % (sub, t_sub, c["n"] // sub)}}
 
 
 def sampler_metrics(dev):

@@ -45,3 +45,16 @@ def test_minus_infinity_weights_and_errors():
         B.resample_redistribute(bad, 1, x)
     with pytest.raises(ValueError, match="status 3"):
         B.resample_redistribute(np.full(n, -np.inf), 1, x)
+
+
+def test_logreg_likelihood_against_the_oracle():
+    """The OpenMP log-likelihood equals the oracle's log-target less its prior
+    terms (a Gaussian prior with variance 10)."""
+    m, d, n = 700, 8, 64
+    X, y, _ = I.logreg_data(m, d, 31)
+    X = X.astype(np.float64)
+    th = np.random.default_rng(2).standard_normal((n, d))
+    o = O.Sampler(n, d, O.T_LOGREG, X=X, y=y, prior_var=10.0)
+    ref = o.log_target(th) - o.cfg.log_norm + 0.5 * (th * th).sum(1) / 10.0
+    got = B.logreg_loglik(th, X, y)
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 1e-11
