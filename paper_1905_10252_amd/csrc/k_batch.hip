@@ -127,6 +127,10 @@ __device__ inline double dpp_f64(double v)
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Offset of row r in a packed upper triangle of a DB x DB matrix.
+template <int DB>
+__device__ constexpr int tri_off(int r) { return r * DB - r * (r - 1) / 2; }
+
 __device__ inline double row16_sum(double v)
 {
     v += dpp_f64<0x111>(v);  // row_shr:1
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
 // key, non-finite flag and estimate sums against the chunk's own max m_b:
 // [m_b, sum e, sum e x_k, sum e x_k^2], e = exp(l - m_b).
 template <int DB, bool kInit>
-__global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_act,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DB > 32 ? 2 : 3))) void k_bquad(const BSlot *slots, const int *n_act,
                                                const int *bact, const int *bchunk_pref,
                                                int bucket, int cap, int single)
 {
@@ -383,8 +387,7 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
     const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
     const i64 n = S.n;
     const int d = S.d;
-    const CST(double) *sU = (const CST(double) *)S.upad;
-    const CST(double) *sM = sU + DB * DB;
+    const CST(double) *sM = (const CST(double) *)S.upad + DB * DB;
     const i64 i = (i64)chunk * kBChunk + tid;
     const bool act = i < n;
     const bool alt = !kInit && S.ctrl->cur;
@@ -400,6 +403,26 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
     const GLB(double) *xb = glb(alt ? S.x_scr : S.x) + base * d;
     constexpr int NQ = (DB + PW - 1) / PW;
     double tv[DB];
+    // U's upper triangle, packed by rows (row r holds k = r .. DB - 1 from
+    // offset tri_off(r)), in LDS: every lane reads the same element, so the
+    // reads are broadcasts, and many can be in flight (unlike scalar loads).
+    __shared__ double sT[DB * (DB + 1) / 2];
+    {
+        constexpr int kPer = (DB * DB + 255) / 256;
+        const GLB(double) *ug = glb(S.upad);
+        double uv[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int e = tid + 256 * j;
+            uv[j] = e < DB * DB ? ug[e] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int e = tid + 256 * j;
+            const int r = e / DB, k = e - r * DB;
+            if (e < DB * DB && k >= r) sT[tri_off<DB>(r) + k - r] = uv[j];
+        }
+    }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         if (q * PW < d) {
@@ -423,11 +446,12 @@ __global__ __launch_bounds__(256) void k_bquad(const BSlot *slots, const int *n_
         double acc = 0.0;
 #pragma unroll
         for (int r = 0; r < DB; r += 2) {
-            double s0 = fma(sU[r * DB + r], tv[r], 0.0), s1 = 0.0;
+            const double *u0 = sT + tri_off<DB>(r) - r, *u1 = sT + tri_off<DB>(r + 1) - (r + 1);
+            double s0 = fma(u0[r], tv[r], 0.0), s1 = 0.0;
 #pragma unroll
             for (int k = r + 1; k < DB; ++k) {
-                s0 = fma(sU[r * DB + k], tv[k], s0);
-                s1 = fma(sU[(r + 1) * DB + k], tv[k], s1);
+                s0 = fma(u0[k], tv[k], s0);
+                s1 = fma(u1[k], tv[k], s1);
             }
             acc = fma(s0, s0, acc);
             acc = fma(s1, s1, acc);
