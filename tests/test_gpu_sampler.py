@@ -133,21 +133,28 @@ def logreg_pair(smc, dev, m_rows, d, n, precision, mode=O.MODE_NEVER, seed=3):
     return g, o
 
 
-@pytest.mark.parametrize("m_rows,d", [(1000, 8), (333, 3), (2048, 32), (100, 64)])
-def test_logreg_f64_log_target(smc, dev, m_rows, d):
+# (M, d, scale of theta): every operand width of both kernels (FP64: 1, 2, 4, 8
+# and 16 MFMA k-steps; BF16: 1 to 4), M below one tile, a single row, and
+# |z| in the hundreds (e^-|z| underflows; the product of factors stays 1).
+LR_CASES = [(1000, 8, 0.3), (333, 3, 0.3), (2048, 32, 0.3), (100, 64, 0.3), (500, 13, 0.3),
+            (777, 40, 0.3), (17, 13, 0.3), (1, 4, 0.3), (1000, 8, 30.0)]
+
+
+@pytest.mark.parametrize("m_rows,d,scale", LR_CASES)
+def test_logreg_f64_log_target(smc, dev, m_rows, d, scale):
     import torch
     g, o = logreg_pair(smc, dev, m_rows, d, 600, "f64")
-    th = np.random.default_rng(9).standard_normal((600, d)) * 0.3
+    th = np.random.default_rng(9).standard_normal((600, d)) * scale
     lp = g.log_target(torch.from_numpy(th).to(dev)).cpu().numpy()
     ref = o.log_target(th)
     assert_close(lp, ref, 1e-11, "logreg f64 lp")
 
 
-@pytest.mark.parametrize("m_rows,d", [(1000, 8), (333, 3), (2048, 32), (100, 64)])
-def test_logreg_bf16_log_target(smc, dev, m_rows, d):
+@pytest.mark.parametrize("m_rows,d,scale", LR_CASES)
+def test_logreg_bf16_log_target(smc, dev, m_rows, d, scale):
     import torch
     g, o = logreg_pair(smc, dev, m_rows, d, 600, "bf16")
-    th = np.random.default_rng(9).standard_normal((600, d)) * 0.3
+    th = np.random.default_rng(9).standard_normal((600, d)) * scale
     lp = g.log_target(torch.from_numpy(th).to(dev)).cpu().numpy()
     ref = o.log_target(th)
     rel = np.abs(lp - ref) / np.abs(ref)
