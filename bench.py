@@ -200,7 +200,9 @@ def sampler_metrics(dev):
         timed_steps(S, 1)
         ms, per = timed_steps(S, k)
         out["logreg_%s" % prec] = {"iters_per_s": round(k / (ms / 1e3), 2),
-                                   "ms_per_iter": round(ms / k, 3)}
+                                   "ms_per_iter": round(ms / k, 3),
+                                   "p50_ms": round(pctl(per, 50), 4),
+                                   "p99_ms": round(pctl(per, 99), 4)}
         del S
     out["batch256"] = batch_metrics(dev, timed_steps)
     out["serving"] = serve_metrics(dev)
