@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
 // key, non-finite flag and estimate sums against the chunk's own max m_b:
 // [m_b, sum e, sum e x_k, sum e x_k^2], e = exp(l - m_b).
 template <int DB, bool kInit>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DB > 48 ? 2 : (DB > 24 ? 3 : 4)))) void k_bquad(const BSlot *slots, const int *n_act,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DB > 40 ? 2 : (DB > 16 ? 3 : 4)))) void k_bquad(const BSlot *slots, const int *n_act,
                                                const int *bact, const int *bchunk_pref,
                                                int bucket, int cap, int single)
 {

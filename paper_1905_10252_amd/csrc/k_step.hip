@@ -586,17 +586,21 @@ __device__ inline double srow16(double v)
     return v;
 }
 
+// nsteps consecutive iterations t0, t0 + 1, ... in one launch, each exactly
+// the iteration a launch of its own would run (info and est, when given, hold
+// one record per iteration).  slots: both parities are cleared, as the
+// sequence of single iterations leaves them.
 template <int kKind>
-__global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t, u64 r, int K,
-                                                     int mode, int ess_num, int ess_den,
+__global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t0, int nsteps,
+                                                     int K, int mode, int ess_num, int ess_den,
                                                      double *__restrict__ x,
                                                      double *__restrict__ logw,
                                                      double *__restrict__ lp,
                                                      double *__restrict__ x_scr,
                                                      double *__restrict__ lp_scr, Ctrl *ctrl,
-                                                     u64 *slots_other, double *rec_num,
-                                                     smc_resample_info *info, double *est,
-                                                     double reset)
+                                                     u64 *slots, double *rec_num,
+                                                     smc_resample_info *info_all,
+                                                     double *est_all, double reset)
 {
     constexpr int NW = kSmallT / 64;  // waves of the block
     __shared__ double s_e[kSmallN];
@@ -611,7 +615,13 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t,
     __shared__ u64 s_bu[3];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int d = a.d;
-    for (int k = tid; k < kSlots * kSlotStride; k += kSmallT) slots_other[k] = 0;
+    for (int k = tid; k < 2 * kSlots * kSlotStride; k += kSmallT) slots[k] = 0;
+
+    for (int it = 0; it < nsteps; ++it) {
+    const uint32_t t = t0 + (uint32_t)it;
+    const u64 r = resample_word(a.seed, a.sampler, t);
+    smc_resample_info *info = info_all ? info_all + it : nullptr;
+    double *est = est_all ? est_all + (i64)it * 4 * d : nullptr;
 
     // proposal and weights (items tid + 1024 j)
     u64 key = 0;
@@ -847,7 +857,10 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t,
             est[2 * d + tid] = num / s_bc[2];
         }
     }
-    if (!s_bu[2]) return;
+    if (!s_bu[2]) {
+        __syncthreads();
+        continue;
+    }
 
     // redistribution: output p takes row anc(p), the first j with
     // N S_j + U >= (p + 1) S; staged in the scratch rows, then back in place
@@ -873,6 +886,8 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t,
         lp[p] = lp_scr[p];
         logw[p] = reset;
     }
+    __syncthreads();
+    }  // iterations
 }
 
 // ------------------------------------------------------ cheap log-targets
@@ -1347,27 +1362,50 @@ smc_status step_init(const smc_config &c, const Work &w, int par, double *x, dou
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
 
+bool small_path(const smc_config &c)
+{
+    return c.n <= kSmallN && c.d <= kSmallD &&
+           (c.target == SMC_TARGET_GAUSS || c.target == SMC_TARGET_STUDENT);
+}
+
+// Small population: nsteps whole iterations in one workgroup and one launch.
+smc_status small_steps(const smc_config &c, const Work &w, int K, uint32_t t0, int nsteps,
+                       double *x, double *logw, smc_resample_info *info, double *est,
+                       hipStream_t s)
+{
+    const int64_t n = c.n;
+    const TArgs a = targs(c, w, false);
+    const double reset = -std::log((double)n);
+    if (c.target == SMC_TARGET_GAUSS)
+        hipLaunchKernelGGL(k_small_step<SMC_TARGET_GAUSS>, dim3(1), dim3(kSmallT), 0, s, a,
+                           (i64)n, t0, nsteps, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp,
+                           w.x_scr, w.lp_scr, w.ctrl, w.slots, w.rec_num, info, est, reset);
+    else
+        hipLaunchKernelGGL(k_small_step<SMC_TARGET_STUDENT>, dim3(1), dim3(kSmallT), 0, s, a,
+                           (i64)n, t0, nsteps, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp,
+                           w.x_scr, w.lp_scr, w.ctrl, w.slots, w.rec_num, info, est, reset);
+    return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+}
+
+smc_status step_run_n(const smc_config &c, const Work &w, int K, int par0, uint32_t t0,
+                      int nsteps, double *x, double *logw, smc_resample_info *info, double *est,
+                      hipStream_t s)
+{
+    if (small_path(c)) return small_steps(c, w, K, t0, nsteps, x, logw, info, est, s);
+    for (int i = 0; i < nsteps; ++i) {
+        const smc_status st = step_run(c, w, K, par0 ^ (i & 1), t0 + (uint32_t)i, x, logw,
+                                       info ? info + i : nullptr,
+                                       est ? est + (int64_t)i * 4 * c.d : nullptr, s);
+        if (st != SMC_OK) return st;
+    }
+    return SMC_OK;
+}
+
 smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t t, double *x,
                     double *logw, smc_resample_info *info, double *est, hipStream_t s)
 {
+    if (small_path(c)) return small_steps(c, w, K, t, 1, x, logw, info, est, s);
     const int64_t n = c.n;
-    if (n <= kSmallN && c.d <= kSmallD &&
-        (c.target == SMC_TARGET_GAUSS || c.target == SMC_TARGET_STUDENT)) {
-        // small population: the whole iteration in one workgroup
-        const TArgs a = targs(c, w, false);
-        const uint64_t r = resample_word(c.seed, c.sampler_id, t);
-        u64 *other = w.slots + ((par & 1) ^ 1) * kSlots * kSlotStride;
-        const double reset = -std::log((double)n);
-        if (c.target == SMC_TARGET_GAUSS)
-            hipLaunchKernelGGL(k_small_step<SMC_TARGET_GAUSS>, dim3(1), dim3(kSmallT), 0, s, a,
-                               (i64)n, t, (u64)r, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp,
-                               w.x_scr, w.lp_scr, w.ctrl, other, w.rec_num, info, est, reset);
-        else
-            hipLaunchKernelGGL(k_small_step<SMC_TARGET_STUDENT>, dim3(1), dim3(kSmallT), 0, s, a,
-                               (i64)n, t, (u64)r, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp,
-                               w.x_scr, w.lp_scr, w.ctrl, other, w.rec_num, info, est, reset);
-        return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
-    }
     const bool pf = c.target == SMC_TARGET_BEARING;
     // With resampling forced every iteration the proposal goes to the
     // workspace copy and the redistribution writes straight into x (an

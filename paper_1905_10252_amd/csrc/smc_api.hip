@@ -274,6 +274,27 @@ smc_status smc_step(smc_ctx *ctx, void *x, double *logw, smc_resample_info *info
     return st;
 }
 
+smc_status smc_steps(smc_ctx *ctx, void *x, double *logw, int32_t nsteps,
+                     smc_resample_info *info, double *est, void *stream)
+{
+    if (!ctx || !x || !logw || nsteps < 1 || ctx->cfg.target == SMC_TARGET_NONE) return SMC_E_ARG;
+    if (((uintptr_t)x & 7) || ((uintptr_t)logw & 7) || ((uintptr_t)info & 7) ||
+        ((uintptr_t)est & 7))
+        return SMC_E_ARG;
+    if ((uint64_t)ctx->t + (uint64_t)nsteps > 0xFFFFFFFFull) return SMC_E_ARG;
+    if (ctx->cfg.target == SMC_TARGET_BEARING &&
+        (int64_t)ctx->t + nsteps > (int64_t)ctx->cfg.n_obs)
+        return SMC_E_ARG;  // not enough measurements left
+    const uint32_t t0 = ctx->t + 1;
+    const int par0 = ctx->par;
+    ctx->t += (uint32_t)nsteps;
+    ctx->par ^= nsteps & 1;
+    const smc_status st = step_run_n(ctx->cfg, ctx->w, ctx->K, par0, t0, nsteps,
+                                     reinterpret_cast<double *>(x), logw, info, est, S(stream));
+    ctx->pending = false;
+    return st;
+}
+
 smc_status smc_log_target(smc_ctx *ctx, const double *x, int64_t n, double *lp, void *stream)
 {
     if (!ctx || !x || !lp || n < 1 || ctx->cfg.target == SMC_TARGET_NONE ||

@@ -252,6 +252,29 @@ class Sampler:
                                    _ptr(self.est) if est else None, _stream()), "smc_step")
         self.t += 1
 
+    def steps(self, k: int, info: bool = False, est: bool = False) -> dict:
+        """k iterations at once (smc_steps: one launch for a small population).
+        With info / est, returns the per-iteration records (decoded info
+        dicts; a [k, 4d] estimate tensor); the last also lands where info()
+        and estimates() read."""
+        k = int(k)
+        dev = self.x.device
+        ib = torch.zeros(k * L.INFO_BYTES, dtype=torch.uint8, device=dev) if info else None
+        eb = torch.zeros(k * 4 * self.d, dtype=torch.float64, device=dev) if est else None
+        L.check(self._lib.smc_steps(self.ctx, _ptr(self.x), _ptr(self.logw), k,
+                                    _ptr(ib) if info else None, _ptr(eb) if est else None,
+                                    _stream()), "smc_steps")
+        self.t += k
+        out = {}
+        if info:
+            self.info_buf.copy_(ib[(k - 1) * L.INFO_BYTES:])
+            out["info"] = [decode_info(ib[i * L.INFO_BYTES:(i + 1) * L.INFO_BYTES])
+                           for i in range(k)]
+        if est:
+            self.est.copy_(eb[(k - 1) * 4 * self.d:])
+            out["est"] = eb.view(k, 4 * self.d)
+        return out
+
     def info(self) -> dict:
         return decode_info(self.info_buf)
 

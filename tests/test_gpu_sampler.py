@@ -315,3 +315,73 @@ def test_runs_repeat_bit_for_bit(smc, dev):
     for (sa, ea), (sb, eb) in zip(a[2], b[2]):
         assert sa == sb and np.array_equal(bits(ea), bits(eb))
     assert not np.array_equal(a[0], c[0])
+
+
+def _steps_pair(smc, dev, kind, n, d, mode, seed):
+    if kind == "student":
+        nu, mu = 5.0, 1.0
+        ln, iln = I.student_log_norm(nu), I.iso_gauss_log_norm(1, 3.0)
+        mk = lambda: smc.Sampler(n, 1, "student", seed=seed, rw_sd=0.5, nu=nu, mu=mu, mode=mode,
+                                 log_norm=ln, init_log_norm=iln, device=dev)
+        o = O.Sampler(n, 1, O.T_STUDENT, seed=seed, rw_sd=0.5, nu=nu, mu=mu, mode=mode,
+                      log_norm=ln, init_log_norm=iln)
+    else:
+        mean = np.linspace(-1.0, 1.5, d)
+        var = np.linspace(0.5, 2.0, d)
+        ln, iln = I.gauss_log_norm(var), I.iso_gauss_log_norm(d, 3.0)
+        mk = lambda: smc.Sampler(n, d, "gauss", seed=seed, rw_sd=0.4, init_mean=0.0, init_sd=3.0,
+                                 mean=mean, var=var, mode=mode, log_norm=ln, init_log_norm=iln,
+                                 device=dev)
+        o = O.Sampler(n, d, O.T_GAUSS, seed=seed, rw_sd=0.4, init_mean=0.0, init_sd=3.0,
+                      mean=mean, var=var, mode=mode, log_norm=ln, init_log_norm=iln)
+    o.init()
+    return mk(), mk(), o
+
+
+@pytest.mark.parametrize("kind,n,d,mode,k", [
+    ("gauss", 1024, 1, O.MODE_AUTO, 20),     # the 1-D workload: one launch for 20 iterations
+    ("gauss", 2048, 16, O.MODE_FORCE, 7),    # the largest one-workgroup population
+    ("student", 1500, 1, O.MODE_AUTO, 9),
+    ("gauss", 1, 2, O.MODE_AUTO, 3),
+    ("gauss", 2049, 3, O.MODE_AUTO, 4),      # multi-kernel path: one iteration after another
+])
+def test_steps_equal_single_steps_and_the_oracle(smc, dev, kind, n, d, mode, k):
+    """smc_steps(k) leaves the bits k calls of smc_step leave, records every
+    iteration's info and estimates, and matches the oracle."""
+    _say("steps %s n=%d d=%d k=%d" % (kind, n, d, k))
+    A, B, o = _steps_pair(smc, dev, kind, n, d, mode, 41)
+    infos, ests = [], []
+    for _ in range(k):
+        A.step(info=True, est=True)
+        infos.append(A.info())
+        ests.append(A.est.cpu().numpy().copy())
+    out = B.steps(k, info=True, est=True)
+    assert np.array_equal(bits(A.x.cpu().numpy()), bits(B.x.cpu().numpy()))
+    assert np.array_equal(bits(A.logw.cpu().numpy()), bits(B.logw.cpu().numpy()))
+    be = out["est"].cpu().numpy()
+    for t in range(k):
+        assert out["info"][t] == infos[t], t
+        assert np.array_equal(bits(be[t]), bits(ests[t])), t
+    for _ in range(k):
+        o.step()
+    assert np.array_equal(bits(B.x.cpu().numpy()), bits(o.x))
+    assert np.array_equal(bits(B.logw.cpu().numpy()), bits(o.logw))
+    # the contexts continue alike: one more single step each
+    A.step(info=True, est=False)
+    B.step(info=True, est=False)
+    assert A.info() == B.info()
+    assert np.array_equal(bits(A.x.cpu().numpy()), bits(B.x.cpu().numpy()))
+    assert B.sync_error() == 0
+
+
+def test_steps_argument_errors(smc, dev):
+    g = I.GAUSS1D
+    S = smc.Sampler(64, 1, "gauss", seed=1, mean=g["mean"], var=g["var"], device=dev)
+    lib = smc.L.load()
+    import ctypes as C
+    rc = lib.smc_steps(S.ctx, C.c_void_p(S.x.data_ptr()), C.c_void_p(S.logw.data_ptr()), 0,
+                       None, None, smc._stream())
+    assert rc == smc.L.SMC_E_ARG
+    rc = lib.smc_steps(S.ctx, C.c_void_p(S.x.data_ptr() + 4), C.c_void_p(S.logw.data_ptr()), 2,
+                       None, None, smc._stream())
+    assert rc == smc.L.SMC_E_ARG
