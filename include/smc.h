@@ -134,13 +134,10 @@ smc_status smc_step(smc_ctx *ctx, void *x, double *logw, smc_resample_info *info
                     void *stream);
 
 /* nsteps >= 1 consecutive iterations of Alg 2 (Alg 1 for SMC_TARGET_BEARING),
- * with results identical bit for bit to nsteps calls of smc_step.  info
- * (nullable) receives nsteps records and est (nullable) nsteps blocks of 4d
- * doubles, in iteration order.  A population of at most 2048 particles with
- * d <= 16 (Gaussian or Student-t target) runs all of them in one workgroup and
- * one kernel launch; other configurations enqueue one iteration after
- * another.  SMC_E_ARG for nsteps < 1, a misaligned pointer, or (filter) fewer
- * measurements left than nsteps. */
+ * enqueued one after another: results identical bit for bit to nsteps calls
+ * of smc_step.  info (nullable) receives nsteps records and est (nullable)
+ * nsteps blocks of 4d doubles, in iteration order.  SMC_E_ARG for nsteps < 1,
+ * a misaligned pointer, or (filter) fewer measurements left than nsteps. */
 smc_status smc_steps(smc_ctx *ctx, void *x, double *logw, int32_t nsteps,
                      smc_resample_info *info, double *est, void *stream);
 

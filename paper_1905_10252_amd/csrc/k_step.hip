@@ -586,21 +586,18 @@ __device__ inline double srow16(double v)
     return v;
 }
 
-// nsteps consecutive iterations t0, t0 + 1, ... in one launch, each exactly
-// the iteration a launch of its own would run (info and est, when given, hold
-// one record per iteration).  slots: both parities are cleared, as the
-// sequence of single iterations leaves them.
+// One whole iteration t of a population of at most kSmallN particles by one
+// workgroup of kSmallT threads.
 template <int kKind>
-__global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t0, int nsteps,
-                                                     int K, int mode, int ess_num, int ess_den,
-                                                     double *__restrict__ x,
-                                                     double *__restrict__ logw,
-                                                     double *__restrict__ lp,
-                                                     double *__restrict__ x_scr,
-                                                     double *__restrict__ lp_scr, Ctrl *ctrl,
-                                                     u64 *slots, double *rec_num,
-                                                     smc_resample_info *info_all,
-                                                     double *est_all, double reset)
+__device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t t, int K,
+                                                int mode, int ess_num, int ess_den,
+                                                double *__restrict__ x,
+                                                double *__restrict__ logw,
+                                                double *__restrict__ lp,
+                                                double *__restrict__ x_scr,
+                                                double *__restrict__ lp_scr, Ctrl *ctrl,
+                                                double *rec_num, smc_resample_info *info,
+                                                double *est, double reset)
 {
     constexpr int NW = kSmallT / 64;  // waves of the block
     __shared__ double s_e[kSmallN];
@@ -615,13 +612,7 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t0
     __shared__ u64 s_bu[3];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int d = a.d;
-    for (int k = tid; k < 2 * kSlots * kSlotStride; k += kSmallT) slots[k] = 0;
-
-    for (int it = 0; it < nsteps; ++it) {
-    const uint32_t t = t0 + (uint32_t)it;
     const u64 r = resample_word(a.seed, a.sampler, t);
-    smc_resample_info *info = info_all ? info_all + it : nullptr;
-    double *est = est_all ? est_all + (i64)it * 4 * d : nullptr;
 
     // proposal and weights (items tid + 1024 j)
     u64 key = 0;
@@ -857,10 +848,7 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t0
             est[2 * d + tid] = num / s_bc[2];
         }
     }
-    if (!s_bu[2]) {
-        __syncthreads();
-        continue;
-    }
+    if (!s_bu[2]) return;
 
     // redistribution: output p takes row anc(p), the first j with
     // N S_j + U >= (p + 1) S; staged in the scratch rows, then back in place
@@ -886,8 +874,25 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t0
         lp[p] = lp_scr[p];
         logw[p] = reset;
     }
-    __syncthreads();
-    }  // iterations
+}
+
+// One iteration in one launch.  slots: the other parity's max slots are
+// cleared for the call that follows.
+template <int kKind>
+__global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t, int K, int mode,
+                                                     int ess_num, int ess_den,
+                                                     double *__restrict__ x,
+                                                     double *__restrict__ logw,
+                                                     double *__restrict__ lp,
+                                                     double *__restrict__ x_scr,
+                                                     double *__restrict__ lp_scr, Ctrl *ctrl,
+                                                     u64 *slots_other, double *rec_num,
+                                                     smc_resample_info *info, double *est,
+                                                     double reset)
+{
+    for (int k = threadIdx.x; k < kSlots * kSlotStride; k += kSmallT) slots_other[k] = 0;
+    small_iteration<kKind>(a, n, t, K, mode, ess_num, ess_den, x, logw, lp, x_scr, lp_scr, ctrl,
+                           rec_num, info, est, reset);
 }
 
 // ------------------------------------------------------ cheap log-targets
@@ -1368,22 +1373,22 @@ bool small_path(const smc_config &c)
            (c.target == SMC_TARGET_GAUSS || c.target == SMC_TARGET_STUDENT);
 }
 
-// Small population: nsteps whole iterations in one workgroup and one launch.
-smc_status small_steps(const smc_config &c, const Work &w, int K, uint32_t t0, int nsteps,
-                       double *x, double *logw, smc_resample_info *info, double *est,
-                       hipStream_t s)
+// Small population: the whole iteration in one workgroup and one launch.
+smc_status small_step(const smc_config &c, const Work &w, int K, int par, uint32_t t, double *x,
+                      double *logw, smc_resample_info *info, double *est, hipStream_t s)
 {
     const int64_t n = c.n;
     const TArgs a = targs(c, w, false);
     const double reset = -std::log((double)n);
+    u64 *other = w.slots + ((par & 1) ^ 1) * kSlots * kSlotStride;
     if (c.target == SMC_TARGET_GAUSS)
         hipLaunchKernelGGL(k_small_step<SMC_TARGET_GAUSS>, dim3(1), dim3(kSmallT), 0, s, a,
-                           (i64)n, t0, nsteps, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp,
-                           w.x_scr, w.lp_scr, w.ctrl, w.slots, w.rec_num, info, est, reset);
+                           (i64)n, t, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp, w.x_scr,
+                           w.lp_scr, w.ctrl, other, w.rec_num, info, est, reset);
     else
         hipLaunchKernelGGL(k_small_step<SMC_TARGET_STUDENT>, dim3(1), dim3(kSmallT), 0, s, a,
-                           (i64)n, t0, nsteps, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp,
-                           w.x_scr, w.lp_scr, w.ctrl, w.slots, w.rec_num, info, est, reset);
+                           (i64)n, t, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp, w.x_scr,
+                           w.lp_scr, w.ctrl, other, w.rec_num, info, est, reset);
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
 
@@ -1391,7 +1396,6 @@ smc_status step_run_n(const smc_config &c, const Work &w, int K, int par0, uint3
                       int nsteps, double *x, double *logw, smc_resample_info *info, double *est,
                       hipStream_t s)
 {
-    if (small_path(c)) return small_steps(c, w, K, t0, nsteps, x, logw, info, est, s);
     for (int i = 0; i < nsteps; ++i) {
         const smc_status st = step_run(c, w, K, par0 ^ (i & 1), t0 + (uint32_t)i, x, logw,
                                        info ? info + i : nullptr,
@@ -1404,7 +1408,7 @@ smc_status step_run_n(const smc_config &c, const Work &w, int K, int par0, uint3
 smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t t, double *x,
                     double *logw, smc_resample_info *info, double *est, hipStream_t s)
 {
-    if (small_path(c)) return small_steps(c, w, K, t, 1, x, logw, info, est, s);
+    if (small_path(c)) return small_step(c, w, K, par, t, x, logw, info, est, s);
     const int64_t n = c.n;
     const bool pf = c.target == SMC_TARGET_BEARING;
     // With resampling forced every iteration the proposal goes to the

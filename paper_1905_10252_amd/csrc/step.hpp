@@ -20,9 +20,8 @@ smc_status step_init(const smc_config &cfg, const Work &w, int par, double *x, d
                      hipStream_t s);
 smc_status step_run(const smc_config &cfg, const Work &w, int K, int par, uint32_t t, double *x,
                     double *logw, smc_resample_info *info, double *est, hipStream_t s);
-// nsteps iterations t0, t0 + 1, ... with parities par0, par0 ^ 1, ...; info
-// and est (nullable) receive one record per iteration.  A small population runs
-// them in one launch; otherwise one step_run per iteration.
+// nsteps iterations t0, t0 + 1, ... with parities par0, par0 ^ 1, ... (one
+// step_run each); info and est (nullable) receive one record per iteration.
 smc_status step_run_n(const smc_config &cfg, const Work &w, int K, int par0, uint32_t t0,
                       int nsteps, double *x, double *logw, smc_resample_info *info, double *est,
                       hipStream_t s);

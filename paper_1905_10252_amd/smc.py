@@ -253,10 +253,9 @@ class Sampler:
         self.t += 1
 
     def steps(self, k: int, info: bool = False, est: bool = False) -> dict:
-        """k iterations at once (smc_steps: one launch for a small population).
-        With info / est, returns the per-iteration records (decoded info
-        dicts; a [k, 4d] estimate tensor); the last also lands where info()
-        and estimates() read."""
+        """k iterations in one call (smc_steps).  With info / est, returns the
+        per-iteration records (decoded info dicts; a [k, 4d] estimate tensor);
+        the last also lands where info() and estimates() read."""
         k = int(k)
         dev = self.x.device
         ib = torch.zeros(k * L.INFO_BYTES, dtype=torch.uint8, device=dev) if info else None

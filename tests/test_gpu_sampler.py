@@ -339,11 +339,11 @@ def _steps_pair(smc, dev, kind, n, d, mode, seed):
 
 
 @pytest.mark.parametrize("kind,n,d,mode,k", [
-    ("gauss", 1024, 1, O.MODE_AUTO, 20),     # the 1-D workload: one launch for 20 iterations
+    ("gauss", 1024, 1, O.MODE_AUTO, 20),     # the 1-D workload
     ("gauss", 2048, 16, O.MODE_FORCE, 7),    # the largest one-workgroup population
     ("student", 1500, 1, O.MODE_AUTO, 9),
     ("gauss", 1, 2, O.MODE_AUTO, 3),
-    ("gauss", 2049, 3, O.MODE_AUTO, 4),      # multi-kernel path: one iteration after another
+    ("gauss", 2049, 3, O.MODE_AUTO, 4),      # the multi-kernel path
 ])
 def test_steps_equal_single_steps_and_the_oracle(smc, dev, kind, n, d, mode, k):
     """smc_steps(k) leaves the bits k calls of smc_step leave, records every
