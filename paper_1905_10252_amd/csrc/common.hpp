@@ -102,53 +102,97 @@ __host__ __device__ inline double okey_inv(u64 k)
 }
 
 // -------------------------------------------------- wave-level primitives
-__device__ inline u64 wave_max_u64(u64 v)
+// Built on DPP lane moves (a VALU operand modifier, no LDS round trip).  GFX9
+// controls: row_shr:n = 0x110 + n moves lane l - n of the same 16-lane row to
+// lane l; row_bcast:15 = 0x142 moves lane 15 of each row to the next row (row
+// mask 0xA: rows 1 and 3); row_bcast:31 = 0x143 moves lane 31 to rows 2 and 3
+// (row mask 0xC).  A lane with no source (or outside the row mask) receives
+// `fill`, the identity of the operation.  A scan is Hillis-Steele within each
+// row (shifts 1, 2, 4, 8), then the row totals carried forward by the two
+// broadcasts; lane 63 then holds the total, which a reduction broadcasts to
+// every lane.  All 64 lanes must take part.
+template <int CTRL, int ROW_MASK>
+__device__ inline u64 dpp_u64(u64 v, u64 fill)
 {
-    for (int o = 32; o > 0; o >>= 1) {
-        u64 w = __shfl_xor(v, o, kWave);
-        v = w > v ? w : v;
-    }
+    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)fill, (int)(unsigned)v, CTRL,
+                                               ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(fill >> 32),
+                                               (int)(unsigned)(v >> 32), CTRL, ROW_MASK, 0xF,
+                                               false);
+    return ((u64)(unsigned)hi << 32) | (u64)(unsigned)lo;
+}
+
+__device__ inline u64 lane63_u64(u64 v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+    return ((u64)hi << 32) | lo;
+}
+
+// Inclusive scan over the wave of v under op (associative, identity `fill`).
+template <class Op>
+__device__ inline u64 wave_scan_u64(u64 v, u64 fill, Op op)
+{
+    v = op(v, dpp_u64<0x111, 0xF>(v, fill));
+    v = op(v, dpp_u64<0x112, 0xF>(v, fill));
+    v = op(v, dpp_u64<0x114, 0xF>(v, fill));
+    v = op(v, dpp_u64<0x118, 0xF>(v, fill));
+    v = op(v, dpp_u64<0x142, 0xA>(v, fill));
+    v = op(v, dpp_u64<0x143, 0xC>(v, fill));
     return v;
 }
 
+__device__ inline u64 wave_max_u64(u64 v)
+{
+    return lane63_u64(wave_scan_u64(v, 0ull, [](u64 a, u64 b) { return b > a ? b : a; }));
+}
+
+// FP64 sum in a fixed order (the scan's): reproducible run to run.
 __device__ inline double wave_sum_f64(double v)
 {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    const u64 r = wave_scan_u64((u64)__double_as_longlong(v), 0ull, [](u64 a, u64 b) {
+        return (u64)__double_as_longlong(__longlong_as_double((long long)a) +
+                                         __longlong_as_double((long long)b));
+    });
+    return __longlong_as_double((long long)lane63_u64(r));
 }
 
 __device__ inline double wave_max_f64(double v)
 {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-    return v;
+    const u64 ninf = (u64)__double_as_longlong(-__builtin_huge_val());
+    const u64 r = wave_scan_u64((u64)__double_as_longlong(v), ninf, [](u64 a, u64 b) {
+        return (u64)__double_as_longlong(fmax(__longlong_as_double((long long)a),
+                                              __longlong_as_double((long long)b)));
+    });
+    return __longlong_as_double((long long)lane63_u64(r));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ inline U128 dpp_u128(U128 v)
+{
+    return U128{dpp_u64<CTRL, ROW_MASK>(v.lo, 0ull), dpp_u64<CTRL, ROW_MASK>(v.hi, 0ull)};
 }
 
 __device__ inline U128 wave_sum_u128(U128 v)
 {
-    for (int o = 32; o > 0; o >>= 1) {
-        U128 w;
-        w.lo = __shfl_xor(v.lo, o, kWave);
-        w.hi = __shfl_xor(v.hi, o, kWave);
-        v = add128(v, w);
-    }
-    return v;
+    v = add128(v, dpp_u128<0x111, 0xF>(v));
+    v = add128(v, dpp_u128<0x112, 0xF>(v));
+    v = add128(v, dpp_u128<0x114, 0xF>(v));
+    v = add128(v, dpp_u128<0x118, 0xF>(v));
+    v = add128(v, dpp_u128<0x142, 0xA>(v));
+    v = add128(v, dpp_u128<0x143, 0xC>(v));
+    return U128{lane63_u64(v.lo), lane63_u64(v.hi)};
 }
 
 __device__ inline unsigned wave_or(unsigned v)
 {
-    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
-    return v;
+    return (unsigned)lane63_u64(wave_scan_u64(v, 0ull, [](u64 a, u64 b) { return a | b; }));
 }
 
 // Inclusive scan of u64 across the 64 lanes of a wavefront.
 __device__ inline u64 wave_incl_scan_u64(u64 v)
 {
-    const int lane = threadIdx.x & (kWave - 1);
-    for (int o = 1; o < kWave; o <<= 1) {
-        u64 w = __shfl_up(v, o, kWave);
-        if (lane >= o) v += w;
-    }
-    return v;
+    return wave_scan_u64(v, 0ull, [](u64 a, u64 b) { return a + b; });
 }
 
 // Device-scope relaxed atomics on 64-bit words (coherent across XCDs).
