@@ -167,6 +167,14 @@ __device__ inline double wave_max_f64(double v)
     return __longlong_as_double((long long)lane63_u64(r));
 }
 
+__device__ inline double lane_f64(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((u64)hi << 32) | lo));
+}
+
 template <int CTRL, int ROW_MASK>
 __device__ inline U128 dpp_u128(U128 v)
 {

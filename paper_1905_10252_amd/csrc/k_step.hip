@@ -587,8 +587,10 @@ __device__ inline double srow16(double v)
 }
 
 // One whole iteration t of a population of at most kSmallN particles by one
-// workgroup of kSmallT threads.
-template <int kKind>
+// workgroup of kSmallT threads.  kD1 (d = 1): each thread keeps its items'
+// new coordinate and log-target in registers, and the redistribution gathers
+// them from LDS (no scratch rows in global memory).
+template <int kKind, bool kD1>
 __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t t, int K,
                                                 int mode, int ess_num, int ess_den,
                                                 double *__restrict__ x,
@@ -610,9 +612,12 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
     __shared__ unsigned s_bad[16];
     __shared__ double s_bc[4];
     __shared__ u64 s_bu[3];
+    __shared__ double s_lpv[kD1 ? kSmallN : 1];
+    constexpr int DM = kD1 ? 1 : kSmallD;  // coordinates a thread handles
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int d = a.d;
+    const int d = kD1 ? 1 : a.d;
     const u64 r = resample_word(a.seed, a.sampler, t);
+    double xr[kSmallI], lpr[kSmallI];  // kD1: the items' new x and log-target
 
     // proposal and weights (items tid + 1024 j)
     u64 key = 0;
@@ -632,6 +637,7 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
                 if (kk >= d) break;
                 const double xk = xi[kk] + a.rw_sd * z[h];
                 xi[kk] = xk;
+                if (kD1) xr[j] = xk;
                 if (kKind == SMC_TARGET_GAUSS) {
                     const double tt = xk - a.mean[kk];
                     acc = acc + (tt * tt) * a.prec[kk];
@@ -648,6 +654,7 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
         }
         const double lw = logw[i] + (lpn - lp[i]);
         lp[i] = lpn;
+        if (kD1) lpr[j] = lpn;
         logw[i] = lw;
         s_e[i] = lw;
         bad |= (lw != lw) | (lw == __builtin_huge_val());
@@ -718,16 +725,16 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
 
     // estimate sums: a DPP sum per 16-lane row, rows in order
     {
-        double s1[kSmallD], s2[kSmallD];
-        for (int k = 0; k < kSmallD; ++k) s1[k] = s2[k] = 0.0;
+        double s1[DM], s2[DM];
+        for (int k = 0; k < DM; ++k) s1[k] = s2[k] = 0.0;
         for (int j = 0; j < kSmallI; ++j) {
             const i64 i = tid + (i64)kSmallT * j;
             if (i >= n) continue;
             const double e = s_e[i];
 #pragma unroll
-            for (int k = 0; k < kSmallD; ++k) {
+            for (int k = 0; k < DM; ++k) {
                 if (k < d) {
-                    const double xv = x[i * d + k];
+                    const double xv = kD1 ? xr[j] : x[i * d + k];
                     const double ex = e * xv;
                     s1[k] += ex;
                     s2[k] += ex * xv;
@@ -736,13 +743,13 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
         }
         // a DPP sum per 16-lane row, then the wave's four rows in order
 #pragma unroll
-        for (int k = 0; k < kSmallD; ++k) {
+        for (int k = 0; k < DM; ++k) {
             if (k < d) {
                 const double a1 = srow16(s1[k]), a2 = srow16(s2[k]);
-                const double w1 = ((__shfl(a1, 15) + __shfl(a1, 31)) + __shfl(a1, 47)) +
-                                  __shfl(a1, 63);
-                const double w2 = ((__shfl(a2, 15) + __shfl(a2, 31)) + __shfl(a2, 47)) +
-                                  __shfl(a2, 63);
+                const double w1 = ((lane_f64(a1, 15) + lane_f64(a1, 31)) + lane_f64(a1, 47)) +
+                                  lane_f64(a1, 63);
+                const double w2 = ((lane_f64(a2, 15) + lane_f64(a2, 31)) + lane_f64(a2, 47)) +
+                                  lane_f64(a2, 63);
                 if (lane == 0) {
                     s_col[wid][k] = w1;
                     s_col[wid][kSmallD + k] = w2;
@@ -751,6 +758,16 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
         }
     }
     __syncthreads();
+    if (kD1) {
+        // s_e is free now (the decision below does not read it)
+        for (int j = 0; j < kSmallI; ++j) {
+            const i64 i = tid + (i64)kSmallT * j;
+            if (i < n) {
+                s_e[i] = xr[j];
+                s_lpv[i] = lpr[j];
+            }
+        }
+    }
     if (tid < 2 * d) {
         const int c = tid < d ? tid : kSmallD + (tid - d);
         double acc = 0.0;
@@ -852,6 +869,7 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
 
     // redistribution: output p takes row anc(p), the first j with
     // N S_j + U >= (p + 1) S; staged in the scratch rows, then back in place
+    // (kD1: gathered from LDS straight into place)
     const u64 S = s_bu[0], U = s_bu[1];
     for (int j = 0; j < kSmallI; ++j) {
         const i64 p = tid + (i64)kSmallT * j;
@@ -863,9 +881,16 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
             if (lt128(add128(mul64((u64)n, s_S[mid]), U), rhs)) lo = mid + 1;
             else hi = mid;
         }
-        for (int k = 0; k < d; ++k) x_scr[p * d + k] = x[lo * d + k];
-        lp_scr[p] = lp[lo];
+        if (kD1) {
+            x[p] = s_e[lo];
+            lp[p] = s_lpv[lo];
+            logw[p] = reset;
+        } else {
+            for (int k = 0; k < d; ++k) x_scr[p * d + k] = x[lo * d + k];
+            lp_scr[p] = lp[lo];
+        }
     }
+    if (kD1) return;
     __syncthreads();
     for (int j = 0; j < kSmallI; ++j) {
         const i64 p = tid + (i64)kSmallT * j;
@@ -878,7 +903,7 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
 
 // One iteration in one launch.  slots: the other parity's max slots are
 // cleared for the call that follows.
-template <int kKind>
+template <int kKind, bool kD1>
 __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t, int K, int mode,
                                                      int ess_num, int ess_den,
                                                      double *__restrict__ x,
@@ -891,8 +916,8 @@ __global__ __launch_bounds__(1024) void k_small_step(TArgs a, i64 n, uint32_t t,
                                                      double reset)
 {
     for (int k = threadIdx.x; k < kSlots * kSlotStride; k += kSmallT) slots_other[k] = 0;
-    small_iteration<kKind>(a, n, t, K, mode, ess_num, ess_den, x, logw, lp, x_scr, lp_scr, ctrl,
-                           rec_num, info, est, reset);
+    small_iteration<kKind, kD1>(a, n, t, K, mode, ess_num, ess_den, x, logw, lp, x_scr, lp_scr,
+                                ctrl, rec_num, info, est, reset);
 }
 
 // ------------------------------------------------------ cheap log-targets
@@ -1381,14 +1406,14 @@ smc_status small_step(const smc_config &c, const Work &w, int K, int par, uint32
     const TArgs a = targs(c, w, false);
     const double reset = -std::log((double)n);
     u64 *other = w.slots + ((par & 1) ^ 1) * kSlots * kSlotStride;
-    if (c.target == SMC_TARGET_GAUSS)
-        hipLaunchKernelGGL(k_small_step<SMC_TARGET_GAUSS>, dim3(1), dim3(kSmallT), 0, s, a,
-                           (i64)n, t, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp, w.x_scr,
-                           w.lp_scr, w.ctrl, other, w.rec_num, info, est, reset);
-    else
-        hipLaunchKernelGGL(k_small_step<SMC_TARGET_STUDENT>, dim3(1), dim3(kSmallT), 0, s, a,
-                           (i64)n, t, K, c.mode, c.ess_num, c.ess_den, x, logw, w.lp, w.x_scr,
-                           w.lp_scr, w.ctrl, other, w.rec_num, info, est, reset);
+    auto kern = c.target == SMC_TARGET_GAUSS
+                    ? (c.d == 1 ? k_small_step<SMC_TARGET_GAUSS, true>
+                                : k_small_step<SMC_TARGET_GAUSS, false>)
+                    : (c.d == 1 ? k_small_step<SMC_TARGET_STUDENT, true>
+                                : k_small_step<SMC_TARGET_STUDENT, false>);
+    hipLaunchKernelGGL(kern, dim3(1), dim3(kSmallT), 0, s, a, (i64)n, t, K, c.mode, c.ess_num,
+                       c.ess_den, x, logw, w.lp, w.x_scr, w.lp_scr, w.ctrl, other, w.rec_num, info,
+                       est, reset);
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
 
