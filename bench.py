@@ -177,6 +177,14 @@ def sampler_metrics(dev):
                                     "p50_ms": round(pctl(per, 50), 4),
                                     "p99_ms": round(pctl(per, 99), 4)}
     del S
+    # the same with the lazy reset (weights marked uniform instead of written)
+    S = smc.Sampler(n, 1, "student", seed=1, rw_sd=0.5, nu=5.0, mu=1.0, mode=smc.L.MODE_FORCE,
+                    lazy_reset=True, device=dev)
+    timed_steps(S, 3)
+    ms, per = timed_steps(S, 100)
+    out["student_t_N2e24_force"]["lazy_reset"] = {"ms_per_iter": round(ms / 100, 4),
+                                                  "particles_per_s": round(100 * n / (ms / 1e3), 1)}
+    del S
     # SIR particle filter (Alg 1), bearing-only tracking, N = 2^24, 50 updates
     B = I.BEARING
     _, ys = I.bearing_track(60, 7)
@@ -189,6 +197,13 @@ def sampler_metrics(dev):
                                "particles_per_s": round(50 * n / (ms / 1e3), 1),
                                "p50_ms": round(pctl(per, 50), 4),
                                "p99_ms": round(pctl(per, 99), 4)}
+    del S
+    S = smc.Sampler(n, 4, "bearing", seed=2, mean=B["x0"], init_sd=B["init_sd"], obs=ys,
+                    delta=B["delta"], obs_var=B["obs_var"], lazy_reset=True, device=dev)
+    timed_steps(S, 3)
+    ms, per = timed_steps(S, 50)
+    out["bearing_pf_N2e24"]["lazy_reset"] = {"ms_per_iter": round(ms / 50, 4),
+                                             "particles_per_s": round(50 * n / (ms / 1e3), 1)}
     del S
     # Bayesian logistic regression: M = 65536, D = 32, N = 2^16
     c = I.LOGREG

@@ -87,7 +87,7 @@ typedef struct smc_config {
     double prior_prec;       /* LOGREG: prior N(0, I / prior_prec)                     */
     const double *obs;       /* BEARING: [n_obs] bearings, y_t used at iteration t     */
     int32_t n_obs;           /* BEARING: number of measurements (iterations allowed)   */
-    int32_t pad0;
+    int32_t lazy_reset;      /* 1: a resampling smc_step leaves logw unwritten (below)  */
     double delta;            /* BEARING: sampling period                               */
     double obs_var;          /* BEARING: bearing noise variance                        */
     double obs_log_norm;     /* BEARING: -0.5 log(2 pi obs_var)                        */
@@ -132,6 +132,14 @@ smc_status smc_init(smc_ctx **h_out, const smc_config *h_cfg, void *workspace,
  * evidence increment.  Returns SMC_E_ARG past the last measurement. */
 smc_status smc_step(smc_ctx *ctx, void *x, double *logw, smc_resample_info *info, double *est,
                     void *stream);
+
+/* With lazy_reset = 1 a resampling iteration does not write logw = -ln N
+ * (Alg 4 reset, 8 bytes a particle); it marks the weights uniform in the
+ * workspace, and the next iteration reads -ln N in place of logw.  Everything
+ * else is unchanged.  smc_sync_weights writes the pending -ln N into logw (a
+ * no-op otherwise); call it before reading logw between iterations.
+ * Populations of at most 2048 particles always write logw. */
+smc_status smc_sync_weights(smc_ctx *ctx, double *logw, void *stream);
 
 /* nsteps >= 1 consecutive iterations of Alg 2 (Alg 1 for SMC_TARGET_BEARING),
  * enqueued one after another: results identical bit for bit to nsteps calls

@@ -22,8 +22,8 @@ TARGET_NONE, TARGET_GAUSS, TARGET_STUDENT, TARGET_LOGREG, TARGET_BEARING = 0, 1,
 MODE_AUTO, MODE_FORCE, MODE_NEVER = 0, 1, 2
 PREC_F64, PREC_BF16 = 0, 1
 
-EXPORTS = ("smc_workspace_bytes", "smc_init", "smc_step", "smc_steps", "smc_resample",
-           "smc_redistribute",
+EXPORTS = ("smc_workspace_bytes", "smc_init", "smc_step", "smc_steps", "smc_sync_weights",
+           "smc_resample", "smc_redistribute",
            "smc_log_target", "smc_sync_error", "smc_destroy", "smc_status_string",
            "smc_batch_sampler_bytes", "smc_batch_workspace_bytes", "smc_batch_create",
            "smc_batch_attach", "smc_batch_detach", "smc_batch_step", "smc_batch_set_graph",
@@ -41,7 +41,7 @@ class SmcConfig(C.Structure):
         ("init_log_norm", C.c_double), ("log_norm", C.c_double),
         ("mean", C.c_void_p), ("prec", C.c_void_p), ("nu", C.c_double), ("mu", C.c_double),
         ("m_rows", C.c_int64), ("X", C.c_void_p), ("y", C.c_void_p), ("prior_prec", C.c_double),
-        ("obs", C.c_void_p), ("n_obs", C.c_int32), ("pad0", C.c_int32), ("delta", C.c_double),
+        ("obs", C.c_void_p), ("n_obs", C.c_int32), ("lazy_reset", C.c_int32), ("delta", C.c_double),
         ("obs_var", C.c_double), ("obs_log_norm", C.c_double),
     ]
 
@@ -92,6 +92,7 @@ def load():
     L.smc_init.argtypes = [P(vp), P(SmcConfig), vp, C.c_size_t, vp, vp, vp]
     L.smc_step.argtypes = [vp, vp, vp, vp, vp, vp]
     L.smc_steps.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp]
+    L.smc_sync_weights.argtypes = [vp, vp, vp]
     L.smc_resample.argtypes = [vp, vp, C.c_int64, C.c_uint64, C.c_int32, vp, vp, vp]
     L.smc_redistribute.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, vp, vp, vp]
     L.smc_log_target.argtypes = [vp, vp, C.c_int64, vp, vp]
@@ -99,7 +100,8 @@ def load():
     L.smc_destroy.argtypes = [vp]
     L.smc_status_string.argtypes = [C.c_int]
     L.smc_status_string.restype = C.c_char_p
-    for f in ("smc_init", "smc_step", "smc_steps", "smc_resample", "smc_redistribute",
+    for f in ("smc_init", "smc_step", "smc_steps", "smc_sync_weights", "smc_resample",
+              "smc_redistribute",
               "smc_log_target", "smc_sync_error", "smc_destroy"):
         getattr(L, f).restype = C.c_int
     L.smc_batch_sampler_bytes.argtypes = [P(SmcBatchSampler)]

@@ -40,7 +40,7 @@ struct Ctrl {
     double rec_den;      // sum_t c_t exp(-lc_max)
     double log_c;
     int rec_steps;
-    unsigned unused1;
+    unsigned uniform;    // lazy reset: the weights are -ln N, logw in memory is stale
     double pad1[4];
 };
 

@@ -162,6 +162,7 @@ struct ScanArgs {
     u64 *out;           // [n] tile-local inclusive prefix
     u64 *out64;         // [n / 64] every 64th tile-local prefix value
     const u64 *slots_p; // max slots of this call's parity (quantise mode)
+    unsigned *uniform;  // lazy-reset flag to clear (nullable)
     int n_tiles;
 };
 
@@ -281,6 +282,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a)
         if (gi < n) a.out64[gi >> 6] = pre + loc[kScanItems - 1];
     }
     if (tid == 0) {
+        if (a.uniform && tile == 0) *a.uniform = 0u;
         a.tsum[tile] = agg;
         if (kQuant) {
             TilePart p;
@@ -485,9 +487,10 @@ hipError_t launch_decide(const Work &w, int par, int64_t n, int K, uint64_t r, i
 }
 
 hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, int par,
-                             hipStream_t s)
+                             hipStream_t s, bool clear_uniform)
 {
     ScanArgs a;
+    a.uniform = clear_uniform ? &w.ctrl->uniform : nullptr;
     a.lw = lw;
     a.nc = nullptr;
     a.n = n;
@@ -521,6 +524,7 @@ hipError_t launch_clear_scan(const Work &w, hipStream_t s)
 hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, hipStream_t s)
 {
     ScanArgs a;
+    a.uniform = nullptr;
     a.lw = nullptr;
     a.nc = reinterpret_cast<const i64 *>(ncopies);
     a.n = n;

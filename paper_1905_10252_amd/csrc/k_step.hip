@@ -48,6 +48,7 @@ struct TArgs {
     uint32_t sampler;
     unsigned short *thb;  // bf16 copy of the particles times log2 e [npad][dp] (nullable)
     // bearing-only particle filter
+    const unsigned *uniform;  // lazy reset flag (NULL: weights always in logw)
     const double *obs;    // measurements, y_t = obs[t - 1]
     double delta, l11, l21, l22, obs_prec, obs_log_norm, reset;
 };
@@ -200,6 +201,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const int tid = threadIdx.x;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
     const int d = a.d;
+    const bool uni = !kInit && a.uniform && *a.uniform;  // lazy reset: weights are -ln N
     const uint32_t tag = kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose;
     const uint32_t tt_ = kInit ? 0u : t;
     u64 key = 0;
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 xw[2] = n2;
                 xw[3] = n3;
                 const double e = a.obs[t - 1] - det_atan(n2 / n0);
-                lw = logw[i] + (a.obs_log_norm - 0.5 * ((e * e) * a.obs_prec));
+                lw = (uni ? a.reset : logw[i]) + (a.obs_log_norm - 0.5 * ((e * e) * a.obs_prec));
             }
             logw[i] = lw;
             bad |= (lw != lw) | (lw == __builtin_huge_val());
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             const double w = 1.0 + (tt * tt) * a.inv_nu;
             lpn = a.log_norm - a.hnu1 * det_log(w);
         }
-        const double lw = kInit ? lpn - lq0 : logw[i] + (lpn - lp[i]);
+        const double lw = kInit ? lpn - lq0 : (uni ? a.reset : logw[i]) + (lpn - lp[i]);
         (kOut ? lpo : lp)[i] = lpn;
         logw[i] = lw;
         bad |= (lw != lw) | (lw == __builtin_huge_val());
@@ -307,15 +309,17 @@ __global__ __launch_bounds__(256) void k_reweight(i64 n, int d, const double *__
                                                   const double *__restrict__ lp_new,
                                                   double *__restrict__ logw,
                                                   double *__restrict__ lp, u64 *slots_p,
-                                                  double *is_part)
+                                                  double *is_part, const unsigned *uniform,
+                                                  double reset)
 {
     const int tid = threadIdx.x;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
+    const bool uni = !kInit && uniform && *uniform;
     u64 key = 0;
     unsigned bad = 0;
     for (i64 i = gtid; i < n; i += gsz) {
         const double lpn = lp_new[i];
-        const double lw = kInit ? lpn - logw[i] : logw[i] + (lpn - lp[i]);
+        const double lw = kInit ? lpn - logw[i] : (uni ? reset : logw[i]) + (lpn - lp[i]);
         lp[i] = lpn;
         logw[i] = lw;
         bad |= (lw != lw) | (lw == __builtin_huge_val());
@@ -413,18 +417,20 @@ __global__ __launch_bounds__(256) void k_step_stats(Ctrl *ctrl, const double *is
     }
 }
 
-__global__ __launch_bounds__(256) void k_copyback(const Ctrl *ctrl, i64 n, int d, double *x,
+// uniform (lazy reset): instead of writing logw, mark the weights uniform.
+__global__ __launch_bounds__(256) void k_copyback(Ctrl *ctrl, i64 n, int d, double *x,
                                                   const double *x_scr, double *lp,
                                                   const double *lp_scr, double *logw,
-                                                  double reset)
+                                                  double reset, unsigned *uniform)
 {
     if (!ctrl->resample || ctrl->err_call) return;
     const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
     for (i64 i = gtid; i < n * d; i += gsz) x[i] = x_scr[i];
     for (i64 i = gtid; i < n; i += gsz) {
         lp[i] = lp_scr[i];
-        logw[i] = reset;
+        if (!uniform) logw[i] = reset;
     }
+    if (uniform && gtid == 0) *uniform = 1u;
 }
 
 // After a redistribution straight into x: weights reset to 1/N when it
@@ -444,7 +450,7 @@ __global__ __launch_bounds__(256) void k_reset_est(const Ctrl *ctrl, i64 n, int 
                                                    const double *__restrict__ lp_scr,
                                                    double *__restrict__ logw, double reset,
                                                    double *is_part, const double *epart,
-                                                   i64 nseg)
+                                                   i64 nseg, unsigned *uniform)
 {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
@@ -460,15 +466,19 @@ __global__ __launch_bounds__(256) void k_reset_est(const Ctrl *ctrl, i64 n, int 
         return;
     }
     const bool rs = ctrl->resample;
+    // lazy reset: the weights are marked uniform instead of written
+    const bool wr = rs && !uniform;
+    if (rs && uniform && gtid == 0) *uniform = 1u;
     if (DT == 0) {
-        if (rs)
+        if (wr)
             for (i64 i = gtid; i < n; i += gsz) logw[i] = reset;
         return;
     }
     constexpr int DA = DT > 0 ? DT : 1;
     if (rs && epart) {
         static_assert(DT == 0 || 2 + 2 * DA == kEstCols, "filter row layout");
-        for (i64 i = gtid; i < n; i += gsz) logw[i] = reset;
+        if (wr)
+            for (i64 i = gtid; i < n; i += gsz) logw[i] = reset;
         if (tid < kEstCols) {
             double v = 0.0;
             for (i64 g = blockIdx.x; g < nseg; g += gridDim.x) v += epart[g * kEstCols + tid];
@@ -482,8 +492,11 @@ __global__ __launch_bounds__(256) void k_reset_est(const Ctrl *ctrl, i64 n, int 
     for (int k = 0; k < DA; ++k) e1[k] = e2[k] = 0.0;
     for (i64 i = gtid; i < n; i += gsz) {
         double e = 1.0;
-        if (rs) logw[i] = reset;
-        else e = det_exp(logw[i] - m);
+        if (rs) {
+            if (wr) logw[i] = reset;
+        } else {
+            e = det_exp(logw[i] - m);
+        }
         e0 += e;
         for (int k = 0; k < DA; ++k) {
             const double xk = x[i * DA + k];
@@ -1222,6 +1235,7 @@ TArgs targs(const smc_config &c, const Work &w, bool with_bf16)
     a.obs_prec = c.target == SMC_TARGET_BEARING ? 1.0 / c.obs_var : 0.0;
     a.obs_log_norm = c.obs_log_norm;
     a.reset = -std::log((double)c.n);
+    a.uniform = c.lazy_reset ? &w.ctrl->uniform : nullptr;
     return a;
 }
 
@@ -1315,7 +1329,7 @@ hipError_t launch_is(const smc_config &c, const Work &w, int par, uint32_t t, do
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
         if (logreg_lp(c, w, x, n, w.lp_new, true, s) != hipSuccess) return hipErrorLaunchFailure;
         hipLaunchKernelGGL(k_reweight<kInit>, g, dim3(256), 0, s, n, c.d, x, w.lp_new, logw,
-                           w.lp, sp, w.is_part);
+                           w.lp, sp, w.is_part, a.uniform, a.reset);
         break;
     default:
         return hipErrorInvalidValue;
@@ -1445,7 +1459,8 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
     // and only resampling steps move rows.
     const bool fwd = (c.mode == SMC_MODE_FORCE && c.target != SMC_TARGET_LOGREG) || pf;
     if (launch_is<false>(c, w, par, t, x, logw, s, fwd) != hipSuccess) return SMC_E_DEVICE;
-    if (launch_quant_scan(w, logw, n, K, par, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_quant_scan(w, logw, n, K, par, s, c.lazy_reset != 0) != hipSuccess)
+        return SMC_E_DEVICE;
     const uint64_t r = resample_word(c.seed, c.sampler_id, t);
     if (launch_decide(w, par, n, K, r, c.mode, c.ess_num, c.ess_den, info, s) != hipSuccess)
         return SMC_E_DEVICE;
@@ -1455,6 +1470,7 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
         if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
     }
     const double reset = -std::log((double)n);
+    unsigned *uni = c.lazy_reset ? &w.ctrl->uniform : nullptr;
     if (fwd) {
         // the particle filter carries no cached log-target
         // the filter's row sums ride on 16-byte chunks of its 32-byte rows
@@ -1466,13 +1482,13 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
             hipLaunchKernelGGL(k_reset_est<4>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)n,
                                c.d, x, w.x_scr, (double *)nullptr, (const double *)nullptr,
                                logw, reset, w.is_part, (const double *)ep,
-                               (i64)expand_segments(n));
+                               (i64)expand_segments(n), uni);
             hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
                                w.is_grid, c.d, w.rec_num, est, info, 0);
         } else {
             hipLaunchKernelGGL(k_reset_est<0>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)n,
                                c.d, x, w.x_scr, w.lp, w.lp_scr, logw, reset, w.is_part,
-                               (const double *)nullptr, (i64)0);
+                               (const double *)nullptr, (i64)0, uni);
         }
         return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
     }
@@ -1480,7 +1496,23 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
                       true) != hipSuccess)
         return SMC_E_DEVICE;
     hipLaunchKernelGGL(k_copyback, dim3(grid_for(n * c.d)), dim3(256), 0, s, w.ctrl, (i64)n, c.d,
-                       x, w.x_scr, w.lp, w.lp_scr, logw, reset);
+                       x, w.x_scr, w.lp, w.lp_scr, logw, reset, uni);
+    return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+}
+
+__global__ __launch_bounds__(256) void k_sync_weights(const Ctrl *ctrl, i64 n, double *logw,
+                                                      double reset)
+{
+    if (!ctrl->uniform) return;
+    const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
+    for (i64 i = gtid; i < n; i += gsz) logw[i] = reset;
+}
+
+smc_status step_sync_weights(const smc_config &c, const Work &w, double *logw, hipStream_t s)
+{
+    if (!c.lazy_reset) return SMC_OK;
+    hipLaunchKernelGGL(k_sync_weights, dim3(grid_for(c.n)), dim3(256), 0, s, w.ctrl, (i64)c.n,
+                       logw, -std::log((double)c.n));
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
 

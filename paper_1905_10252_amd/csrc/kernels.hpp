@@ -71,8 +71,10 @@ hipError_t launch_init_ctrl(const Work &w, hipStream_t s);
 hipError_t launch_max(const Work &w, const double *lw, int64_t n, int par, hipStream_t s);
 hipError_t launch_fold(const Work &w, int par, hipStream_t s);
 // Quantise + scan; reads the max slots of parity par.
+// clear_uniform: also clears the lazy-reset flag (an iteration's scan runs
+// after the kernels that read it).
 hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, int par,
-                             hipStream_t s);
+                             hipStream_t s, bool clear_uniform = false);
 // Error and decision of the call from the max slots of parity par and the
 // scan; info is a device smc_resample_info (nullable).
 hipError_t launch_decide(const Work &w, int par, int64_t n, int K, uint64_t r, int mode,

@@ -48,6 +48,7 @@ bool config_ok(const smc_config *c)
     if (c->ess_num < 0 || c->ess_num > 16 || c->ess_den < 1 || c->ess_den > 16) return false;
     if (c->mode < SMC_MODE_AUTO || c->mode > SMC_MODE_NEVER) return false;
     if (c->target < SMC_TARGET_NONE || c->target > SMC_TARGET_BEARING) return false;
+    if (c->lazy_reset != 0 && c->lazy_reset != 1) return false;
     if (c->target != SMC_TARGET_NONE) {
         if (c->d > kMaxDim || c->x_dtype != SMC_DTYPE_F64) return false;
         if (!(c->rw_sd >= 0.0) || !(c->init_sd > 0.0)) return false;
@@ -293,6 +294,13 @@ smc_status smc_steps(smc_ctx *ctx, void *x, double *logw, int32_t nsteps,
                                      reinterpret_cast<double *>(x), logw, info, est, S(stream));
     ctx->pending = false;
     return st;
+}
+
+smc_status smc_sync_weights(smc_ctx *ctx, double *logw, void *stream)
+{
+    if (!ctx || !logw || ctx->cfg.target == SMC_TARGET_NONE || ((uintptr_t)logw & 7))
+        return SMC_E_ARG;
+    return step_sync_weights(ctx->cfg, ctx->w, logw, S(stream));
 }
 
 smc_status smc_log_target(smc_ctx *ctx, const double *x, int64_t n, double *lp, void *stream)

@@ -25,6 +25,9 @@ smc_status step_run(const smc_config &cfg, const Work &w, int K, int par, uint32
 smc_status step_run_n(const smc_config &cfg, const Work &w, int K, int par0, uint32_t t0,
                       int nsteps, double *x, double *logw, smc_resample_info *info, double *est,
                       hipStream_t s);
+// Lazy reset: writes -ln N into logw when the last iteration left the weights
+// marked uniform.
+smc_status step_sync_weights(const smc_config &cfg, const Work &w, double *logw, hipStream_t s);
 smc_status step_log_target(const smc_config &cfg, const Work &w, const double *x, int64_t n,
                            double *lp, hipStream_t s);
 

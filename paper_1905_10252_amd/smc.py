@@ -171,13 +171,15 @@ class Sampler:
                  mode: int = L.MODE_AUTO, ess_num: int = 1, ess_den: int = 2, mean=None,
                  var=None, nu=None, mu=None, X=None, y=None, prior_var=None,
                  precision: str = "f64", log_norm=None, init_log_norm=None, obs=None,
-                 delta: float = 1.0, obs_var: float = 1e-4, device=None):
+                 delta: float = 1.0, obs_var: float = 1e-4, lazy_reset: bool = False,
+                 device=None):
         lib = L.load()
         self._lib = lib
         self.n, self.d = int(n), int(d)
         self.device = torch.device(device or "cuda")
         dev = self.device
         cfg = L.SmcConfig()
+        cfg.lazy_reset = 1 if lazy_reset else 0
         cfg.n, cfg.d, cfg.x_dtype = self.n, self.d, L.DTYPE_F64
         cfg.mode, cfg.ess_num, cfg.ess_den = mode, ess_num, ess_den
         cfg.sampler_id, cfg.seed = sampler_id, int(seed) & (2**64 - 1)
@@ -273,6 +275,12 @@ class Sampler:
             self.est.copy_(eb[(k - 1) * 4 * self.d:])
             out["est"] = eb.view(k, 4 * self.d)
         return out
+
+    def sync_weights(self) -> None:
+        """With lazy_reset: writes the pending -ln N of a resampling iteration
+        into logw (smc_sync_weights; nothing to do otherwise)."""
+        L.check(self._lib.smc_sync_weights(self.ctx, _ptr(self.logw), _stream()),
+                "smc_sync_weights")
 
     def info(self) -> dict:
         return decode_info(self.info_buf)

@@ -63,6 +63,10 @@ def test_workspace_bytes(lib):
     assert lib.smc_workspace_bytes(C.byref(cfg)) > 0
     cfg.x_dtype = 0  # samplers need FP64 particles
     assert lib.smc_workspace_bytes(C.byref(cfg)) == 0
+    cfg.x_dtype, cfg.lazy_reset = 1, 1
+    assert lib.smc_workspace_bytes(C.byref(cfg)) > 0
+    cfg.lazy_reset = 2  # a flag: 0 or 1
+    assert lib.smc_workspace_bytes(C.byref(cfg)) == 0
 
 
 def test_status_strings(lib):

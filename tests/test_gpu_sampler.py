@@ -385,3 +385,51 @@ def test_steps_argument_errors(smc, dev):
     rc = lib.smc_steps(S.ctx, C.c_void_p(S.x.data_ptr() + 4), C.c_void_p(S.logw.data_ptr()), 2,
                        None, None, smc._stream())
     assert rc == smc.L.SMC_E_ARG
+
+
+def _lazy_pair(smc, dev, kind, n, mode):
+    def mk(lazy):
+        if kind == "student":
+            return smc.Sampler(n, 1, "student", seed=5, rw_sd=0.5, nu=5.0, mu=1.0, mode=mode,
+                               lazy_reset=lazy, device=dev)
+        if kind == "gauss":
+            return smc.Sampler(n, 3, "gauss", seed=17, rw_sd=0.3, mean=[1.0, -2.0, 0.5],
+                               var=[0.5, 2.0, 1.5], mode=mode, lazy_reset=lazy, device=dev)
+        if kind == "bearing":
+            B = I.BEARING
+            _, ys = I.bearing_track(12, 7)
+            return smc.Sampler(n, 4, "bearing", seed=3, mean=B["x0"], init_sd=B["init_sd"],
+                               obs=ys, delta=B["delta"], obs_var=B["obs_var"], mode=mode,
+                               lazy_reset=lazy, device=dev)
+        X, y, _ = I.logreg_data(500, 8, 300)
+        return smc.Sampler(n, 8, "logreg", seed=3, X=X.astype(np.float64), y=y, prior_var=10.0,
+                           rw_sd=0.01, init_sd=math.sqrt(10.0), mode=mode, lazy_reset=lazy,
+                           device=dev)
+    return mk(False), mk(True)
+
+
+@pytest.mark.parametrize("kind,n,mode", [("student", 70001, O.MODE_FORCE),
+                                         ("gauss", 3001, O.MODE_AUTO),
+                                         ("bearing", 20000, O.MODE_AUTO),
+                                         ("logreg", 3000, O.MODE_FORCE),
+                                         ("gauss", 1500, O.MODE_FORCE)])
+def test_lazy_reset_matches_eager(smc, dev, kind, n, mode):
+    """A lazy-reset sampler follows the eager one bit for bit; its logw catches
+    up on smc_sync_weights (synced on every other iteration here, so that
+    iterations also start from stale memory marked uniform)."""
+    _say("lazy %s n=%d" % (kind, n))
+    E, Lz = _lazy_pair(smc, dev, kind, n, mode)
+    resampled = 0
+    for t in range(1, 9):
+        E.step(info=True, est=True)
+        Lz.step(info=True, est=True)
+        ie, il = E.info(), Lz.info()
+        assert ie == il, t
+        resampled += ie["resampled"]
+        assert np.array_equal(bits(E.x.cpu().numpy()), bits(Lz.x.cpu().numpy())), t
+        assert np.array_equal(bits(E.est.cpu().numpy()), bits(Lz.est.cpu().numpy())), t
+        if t % 2 == 0:
+            Lz.sync_weights()
+            assert np.array_equal(bits(E.logw.cpu().numpy()), bits(Lz.logw.cpu().numpy())), t
+    assert resampled > 0
+    assert Lz.sync_error() == 0
