@@ -433,3 +433,15 @@ def test_lazy_reset_matches_eager(smc, dev, kind, n, mode):
             assert np.array_equal(bits(E.logw.cpu().numpy()), bits(Lz.logw.cpu().numpy())), t
     assert resampled > 0
     assert Lz.sync_error() == 0
+
+
+def test_lazy_reset_with_steps(smc, dev):
+    """smc_steps on a lazy-reset sampler: the same bits as eager single steps."""
+    E, Lz = _lazy_pair(smc, dev, "student", 9000, O.MODE_FORCE)
+    for _ in range(5):
+        E.step(info=False, est=False)
+    out = Lz.steps(5, info=True)
+    assert out["info"][-1]["resampled"] == 1
+    assert np.array_equal(bits(E.x.cpu().numpy()), bits(Lz.x.cpu().numpy()))
+    Lz.sync_weights()
+    assert np.array_equal(bits(E.logw.cpu().numpy()), bits(Lz.logw.cpu().numpy()))
