@@ -8,8 +8,9 @@ every admitted request by one iteration, and retires the finished ones:
   - Gaussian requests (any N and d <= 64, full-precision target) share one
     batched step of ``smc.Batch``: all of them advance in the same launches;
   - logistic-regression requests each advance by one ``smc_step`` of their
-    own context (BF16 MFMA likelihood), on a second stream, so their kernels
-    overlap the batched step on the device.
+    own context (BF16 MFMA likelihood), on further streams (contexts dealt
+    round robin over them), so their kernels overlap the batched step and
+    each other on the device.
 
 Particle state stays on the device from admission to retirement.  A request's
 result depends only on the request: the batch gives every sampler the same
@@ -65,16 +66,20 @@ def request_bytes(r: Request) -> int:
 class DeviceBackend:
     """The device side of a server: one ``smc.Batch`` of ``capacity`` slots
     for the Gaussian requests, one ``smc.Sampler`` context per
-    logistic-regression request on a second stream, and retirement of
-    results through pinned host memory behind events."""
+    logistic-regression request on one of ``side_streams`` further streams
+    (contexts dealt round robin, so that the small likelihood launches of
+    different requests overlap), and retirement of results through pinned
+    host memory behind events."""
 
     def __init__(self, capacity: int, *, graph: bool = True, keep_particles: bool = False,
-                 device=None):
+                 device=None, side_streams: int = 3):
         self.device = torch.device(device or "cuda")
         self.batch = smc.Batch(capacity, graph=graph, device=self.device)
         self.keep = keep_particles
         self.main = torch.cuda.current_stream(self.device)
-        self.side = torch.cuda.Stream(device=self.device)  # default priority
+        # default priority; with the main stream, one per hardware queue
+        self.sides = [torch.cuda.Stream(device=self.device) for _ in range(max(1, side_streams))]
+        self.opened = 0
         self.t0 = None
 
     def attach(self, slot: int, r: Request) -> None:
@@ -86,20 +91,23 @@ class DeviceBackend:
 
     def open(self, r: Request):
         p = r.params
-        with torch.cuda.stream(self.side):
-            return smc.Sampler(r.n, r.d, "logreg", seed=r.seed, sampler_id=r.sampler_id,
-                               X=p["X"], y=p["y"], prior_var=p["prior_var"],
-                               precision=p.get("precision", "bf16"), rw_sd=p["rw_sd"],
-                               init_sd=math.sqrt(p["prior_var"]),
-                               mode=p.get("mode", L.MODE_AUTO), device=self.device)
+        stream = self.sides[self.opened % len(self.sides)]
+        self.opened += 1
+        with torch.cuda.stream(stream):
+            s = smc.Sampler(r.n, r.d, "logreg", seed=r.seed, sampler_id=r.sampler_id,
+                            X=p["X"], y=p["y"], prior_var=p["prior_var"],
+                            precision=p.get("precision", "bf16"), rw_sd=p["rw_sd"],
+                            init_sd=math.sqrt(p["prior_var"]),
+                            mode=p.get("mode", L.MODE_AUTO), device=self.device)
+        s.serve_stream = stream
+        return s
 
     def step(self, batch: bool, contexts) -> None:
         if batch:
             self.batch.step(info=False, est=True)
-        if contexts:
-            with torch.cuda.stream(self.side):
-                for s in contexts:
-                    s.step(info=False, est=True)
+        for s in contexts:
+            with torch.cuda.stream(s.serve_stream):
+                s.step(info=False, est=True)
 
     def _token(self, est_dev, x_dev, stream):
         with torch.cuda.stream(stream):
@@ -118,9 +126,9 @@ class DeviceBackend:
         return tok
 
     def retire_context(self, s, r: Request):
-        # the context's buffers were allocated on the side stream: freeing
-        # them with the sampler is ordered after its last use there
-        return self._token(s.est[:4 * r.d], s.x if self.keep else None, self.side)
+        # the context's buffers were allocated on its stream: freeing them
+        # with the sampler is ordered after its last use there
+        return self._token(s.est[:4 * r.d], s.x if self.keep else None, s.serve_stream)
 
     def ready(self, tok) -> bool:
         return tok[0].query()
