@@ -116,6 +116,8 @@ def lib():
         L.orc_resample.restype = C.c_int
         L.orc_redistribute.argtypes = [C.c_int64, P(C.c_int64), C.c_void_p, C.c_int64, C.c_void_p,
                                        P(C.c_int64)]
+        L.orc_normalised_weights.argtypes = [P(C.c_double), C.c_int64, P(C.c_double)]
+        L.orc_normalised_weights.restype = C.c_int
         L.orc_redistribute.restype = C.c_int
         L.orc_log_target_batch.argtypes = [P(SmcCfg), P(C.c_double), C.c_int64, P(C.c_double)]
         L.orc_smc_init.argtypes = [P(SmcCfg), P(C.c_double), P(C.c_double), P(C.c_double),
@@ -191,6 +193,17 @@ def resample(logw, r, mode=MODE_AUTO, ess_num=1, ess_den=2):
     lib().orc_resample(_p(lw, C.c_double), lw.size, int(r) & (2**64 - 1), mode, ess_num,
                        ess_den, _p(nc, C.c_int64), C.byref(info))
     return nc[:lw.size], info.as_dict()
+
+
+def normalised_weights(logw):
+    """eq. normalise: exp(l_i - m) / sum_j exp(l_j - m); raises on the
+    resample errors (status in the message)."""
+    lw = np.ascontiguousarray(logw, dtype=np.float64)
+    w = np.zeros(lw.shape[0], dtype=np.float64)
+    rc = lib().orc_normalised_weights(_p(lw, C.c_double), lw.shape[0], _p(w, C.c_double))
+    if rc != E_OK:
+        raise ValueError("normalised_weights failed: status %d" % rc)
+    return w
 
 
 def redistribute(ncopies, x):

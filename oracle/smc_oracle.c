@@ -335,6 +335,26 @@ int orc_resample(const double *logw, int64_t n, uint64_t r, int32_t mode, int32_
     return ORC_OK;
 }
 
+/* eq. normalise: w~_i = w_i / sum_j w_j with w_i = exp(l_i), taken as
+ * exp(l_i - m) / Z, m = max l, Z = sum exp(l_j - m) (libm exp, Neumaier sum).
+ * Errors as orc_resample: NaN or +inf, or every weight zero. */
+int orc_normalised_weights(const double *logw, int64_t n, double *w)
+{
+    if (n < 1) return ORC_E_ARG;
+    double m = -INFINITY;
+    for (int64_t i = 0; i < n; ++i) {
+        double v = logw[i];
+        if (v != v || v == INFINITY) return ORC_E_NONFINITE;
+        if (v > m) m = v;
+    }
+    if (m == -INFINITY) return ORC_E_DEGENERATE;
+    double Z = 0.0, cz = 0.0;
+    for (int64_t i = 0; i < n; ++i) neu_add(&Z, &cz, exp(logw[i] - m));
+    Z += cz;
+    for (int64_t i = 0; i < n; ++i) w[i] = exp(logw[i] - m) / Z;
+    return ORC_OK;
+}
+
 /* Alg 5, sequential redistribute: copy row j ncopies_j times, in source
  * order.  anc (nullable) receives the source index of every output row. */
 int orc_redistribute(int64_t n, const int64_t *ncopies, const void *x, int64_t row_bytes,

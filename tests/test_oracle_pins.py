@@ -553,3 +553,33 @@ def test_gauss_chol_importance_sampling_moments():
     k = math.sqrt(ms.shape[0])
     assert np.all(np.abs(ms.mean(0) - mean) < 5 * ms.std(0) / k + 1e-3)
     assert np.all(np.abs(m2s.mean(0) - (np.diag(cov) + mean ** 2)) < 5 * m2s.std(0) / k + 2e-3)
+
+
+def test_normalised_weights_pins():
+    """eq. normalise: w~_i = w_i / sum_j w_j.  Equal weights give exactly 1/N;
+    weights in ratio 1:3 give 1/4 and 3/4; zero weights stay zero; ratios
+    follow exp(l_i - l_j); the sum is 1; a common shift changes nothing."""
+    for n in (1, 3, 1000):
+        assert np.all(O.normalised_weights(np.full(n, -2.5)) == 1.0 / n)
+    w = O.normalised_weights(np.array([0.0, math.log(3.0)]))
+    assert abs(w[0] - 0.25) <= 2.0 ** -54 * 4 and abs(w[1] - 0.75) <= 2.0 ** -53 * 2
+    rng = np.random.default_rng(12)
+    lw = rng.normal(0.0, 3.0, 5000)
+    lw[::7] = -np.inf
+    w = O.normalised_weights(lw)
+    assert np.all(w[::7] == 0.0) and np.all(w[1::7] > 0.0)
+    assert abs(w.sum() - 1.0) < 5000 * 2.0 ** -52
+    i, j = rng.integers(1, 5000, 200), rng.integers(1, 5000, 200)
+    ok = (i % 7 != 0) & (j % 7 != 0)
+    ratio = w[i[ok]] / w[j[ok]]
+    ref = np.exp(lw[i[ok]] - lw[j[ok]])
+    assert np.max(np.abs(ratio / ref - 1.0)) < 1e-12
+    # shift by 1000: l + 1000 is rounded to a grid of 2^-43, which bounds the change
+    w2 = O.normalised_weights(lw + 1000.0)
+    pos = w > 0.0
+    assert np.all(w2[~pos] == 0.0)
+    assert np.max(np.abs(w2[pos] / w[pos] - 1.0)) < 4 * 2.0 ** -43
+    with pytest.raises(ValueError):
+        O.normalised_weights(np.array([0.0, np.nan]))
+    with pytest.raises(ValueError):
+        O.normalised_weights(np.full(4, -np.inf))
