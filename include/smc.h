@@ -160,6 +160,14 @@ smc_status smc_steps(smc_ctx *ctx, void *x, double *logw, int32_t nsteps,
 smc_status smc_resample(smc_ctx *ctx, const double *logw, int64_t n, uint64_t r, int32_t mode,
                         int64_t *ncopies, smc_resample_info *info, void *stream);
 
+/* eq. normalise: w[i] = exp(logw[i] - m) / Z, with m and the FP64 sum Z of
+ * the last smc_resample on this context (call it with the same logw[n]);
+ * exp is the deterministic one of the fixed-point weights.  Nothing is
+ * written when that call found an error (info->err).  w must not overlap
+ * logw. */
+smc_status smc_normalised_weights(smc_ctx *ctx, const double *logw, int64_t n, double *w,
+                                  void *stream);
+
 /* Alg 5 semantics, load-balanced: x_out row p = x row anc(p) where the
  * ancestors are non-decreasing and source j appears ncopies_j times.
  * ncopies == NULL uses the pending result of the last smc_resample on this

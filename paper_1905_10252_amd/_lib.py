@@ -23,7 +23,7 @@ MODE_AUTO, MODE_FORCE, MODE_NEVER = 0, 1, 2
 PREC_F64, PREC_BF16 = 0, 1
 
 EXPORTS = ("smc_workspace_bytes", "smc_init", "smc_step", "smc_steps", "smc_sync_weights",
-           "smc_resample", "smc_redistribute",
+           "smc_resample", "smc_normalised_weights", "smc_redistribute",
            "smc_log_target", "smc_sync_error", "smc_destroy", "smc_status_string",
            "smc_batch_sampler_bytes", "smc_batch_workspace_bytes", "smc_batch_create",
            "smc_batch_attach", "smc_batch_detach", "smc_batch_step", "smc_batch_set_graph",
@@ -93,6 +93,7 @@ def load():
     L.smc_step.argtypes = [vp, vp, vp, vp, vp, vp]
     L.smc_steps.argtypes = [vp, vp, vp, C.c_int32, vp, vp, vp]
     L.smc_sync_weights.argtypes = [vp, vp, vp]
+    L.smc_normalised_weights.argtypes = [vp, vp, C.c_int64, vp, vp]
     L.smc_resample.argtypes = [vp, vp, C.c_int64, C.c_uint64, C.c_int32, vp, vp, vp]
     L.smc_redistribute.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, vp, vp, vp]
     L.smc_log_target.argtypes = [vp, vp, C.c_int64, vp, vp]
@@ -101,7 +102,7 @@ def load():
     L.smc_status_string.argtypes = [C.c_int]
     L.smc_status_string.restype = C.c_char_p
     for f in ("smc_init", "smc_step", "smc_steps", "smc_sync_weights", "smc_resample",
-              "smc_redistribute",
+              "smc_normalised_weights", "smc_redistribute",
               "smc_log_target", "smc_sync_error", "smc_destroy"):
         getattr(L, f).restype = C.c_int
     L.smc_batch_sampler_bytes.argtypes = [P(SmcBatchSampler)]

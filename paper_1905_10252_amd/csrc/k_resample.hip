@@ -507,6 +507,25 @@ hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, 
     return hipGetLastError();
 }
 
+// eq. normalise: w_i = exp(l_i - m) / Z with the max and the FP64 sum of
+// the last decision (nothing is written when that call found an error).
+__global__ __launch_bounds__(256) void k_weights(const Ctrl *ctrl, const double *lw, i64 n,
+                                                 double *w)
+{
+    if (ctrl->err_call) return;
+    const double m = ctrl->m, Z = ctrl->Z;
+    const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
+    for (i64 i = gtid; i < n; i += gsz) w[i] = det_exp(lw[i] - m) / Z;
+}
+
+hipError_t launch_weights(const Work &w, const double *lw, int64_t n, double *out, hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    blocks = blocks > 8192 ? 8192 : blocks;
+    hipLaunchKernelGGL(k_weights, dim3((unsigned)blocks), dim3(256), 0, s, w.ctrl, lw, (i64)n, out);
+    return hipGetLastError();
+}
+
 // Resets the per-call flags before a scan of caller-supplied counts.
 __global__ void k_clear_scan(Ctrl *ctrl)
 {

@@ -80,6 +80,8 @@ hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, 
 hipError_t launch_decide(const Work &w, int par, int64_t n, int K, uint64_t r, int mode,
                          int ess_num, int ess_den, void *info, hipStream_t s);
 hipError_t launch_clear_scan(const Work &w, hipStream_t s);
+// Normalised weights exp(l_i - m) / Z from the last decision.
+hipError_t launch_weights(const Work &w, const double *lw, int64_t n, double *out, hipStream_t s);
 hipError_t launch_count_scan(const Work &w, const int64_t *ncopies, int64_t n, hipStream_t s);
 hipError_t launch_ncopies(const Work &w, int64_t n, int count_mode, int64_t *ncopies,
                           hipStream_t s);

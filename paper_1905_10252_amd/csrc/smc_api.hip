@@ -230,6 +230,15 @@ smc_status smc_resample(smc_ctx *ctx, const double *logw, int64_t n, uint64_t r,
     return SMC_OK;
 }
 
+smc_status smc_normalised_weights(smc_ctx *ctx, const double *logw, int64_t n, double *w,
+                                  void *stream)
+{
+    if (!ctx || !logw || !w || n != ctx->cfg.n) return SMC_E_ARG;
+    if (((uintptr_t)logw & 7) || ((uintptr_t)w & 7)) return SMC_E_ARG;
+    if (overlap(logw, w, (size_t)n * 8)) return SMC_E_ARG;
+    return launch_weights(ctx->w, logw, n, w, S(stream)) == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+}
+
 smc_status smc_redistribute(smc_ctx *ctx, const int64_t *ncopies, const void *x, void *x_out,
                             int64_t n, int32_t row_bytes, int64_t *ncopies_out, int64_t *anc,
                             void *stream)

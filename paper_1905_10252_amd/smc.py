@@ -86,6 +86,18 @@ class Resampler:
                                        _stream()), "smc_resample")
         return ncopies
 
+    def normalised_weights(self, logw: torch.Tensor,
+                           out: torch.Tensor | None = None) -> torch.Tensor:
+        """eq. normalise, exp(l_i - m) / Z with m and Z of the last resample()
+        (call it with the same logw)."""
+        _need(logw, torch.float64, self.n, "logw")
+        if out is None:
+            out = torch.empty_like(logw)
+        _need(out, torch.float64, self.n, "out")
+        L.check(self._lib.smc_normalised_weights(self.ctx, _ptr(logw), self.n, _ptr(out),
+                                                 _stream()), "smc_normalised_weights")
+        return out
+
     def redistribute(self, x: torch.Tensor, x_out: torch.Tensor | None = None,
                      ncopies: torch.Tensor | None = None,
                      ncopies_out: torch.Tensor | None = None,

@@ -301,3 +301,22 @@ def test_maximum_size(smc, dev):
     assert R.sync_error() == 0
     del R, lw, x, nc1, nc2, xo, idx
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,s", [(1, 1.0), (1000, 0.5), (70001, 8.0), (1 << 20, 2.0)])
+def test_normalised_weights(smc, dev, n, s):
+    """eq. normalise against the oracle: exp(l - m) / Z, zero weights zero,
+    unit sum."""
+    import torch
+    lw = I.logw_normal(n, s, 31 + n)
+    if n > 7:
+        lw[::7] = -np.inf
+    R = smc.Resampler(n, device=dev)
+    t = torch.from_numpy(lw).to(dev)
+    R.resample(t, 5, O.MODE_FORCE)
+    w = R.normalised_weights(t).cpu().numpy()
+    ref = O.normalised_weights(lw)
+    pos = ref > 0
+    assert np.array_equal(w[~pos], ref[~pos])
+    assert np.max(np.abs(w[pos] / ref[pos] - 1.0)) < 1e-12
+    assert abs(w.sum() - 1.0) < 1e-12
