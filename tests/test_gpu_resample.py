@@ -303,7 +303,8 @@ def test_maximum_size(smc, dev):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("n,s", [(1, 1.0), (1000, 0.5), (70001, 8.0), (1 << 20, 2.0)])
+@pytest.mark.parametrize("n,s", [(1, 1.0), (1000, 0.5), (70001, 8.0), (1 << 20, 2.0),
+                                 (1 << 24, 8.0)])
 def test_normalised_weights(smc, dev, n, s):
     """eq. normalise against the oracle: exp(l - m) / Z, zero weights zero,
     unit sum."""

@@ -408,7 +408,8 @@ def _lazy_pair(smc, dev, kind, n, mode):
     return mk(False), mk(True)
 
 
-@pytest.mark.parametrize("kind,n,mode", [("student", 70001, O.MODE_FORCE),
+@pytest.mark.parametrize("kind,n,mode", [("student", 1 << 24, O.MODE_FORCE),
+                                         ("student", 70001, O.MODE_FORCE),
                                          ("gauss", 3001, O.MODE_AUTO),
                                          ("bearing", 20000, O.MODE_AUTO),
                                          ("logreg", 3000, O.MODE_FORCE),
