@@ -28,6 +28,7 @@
 #include "common.hpp"
 #include "det.hpp"
 #include "kernels.hpp"
+#include "stats.hpp"
 #include "reduce.hpp"
 
 namespace smc {
@@ -369,7 +370,7 @@ __global__ __launch_bounds__(1024) void k_decide(Ctrl *ctrl, u64 *slots, int par
                                                  const TilePart *tpart, u64 *tsum,
                                                  int n_tiles, i64 n, int K, u64 r, int mode,
                                                  int ess_num, int ess_den,
-                                                 smc_resample_info *info)
+                                                 smc_resample_info *info, StatsArgs st)
 {
     __shared__ double s_z[16], s_z2[16];
     __shared__ u64 s_lo[16], s_hi[16];
@@ -416,73 +417,81 @@ __global__ __launch_bounds__(1024) void k_decide(Ctrl *ctrl, u64 *slots, int par
         s_hi[wid] = q2.hi;
     }
     __syncthreads();
-    if (tid != 0) return;
-    double Z = s_z[0], Z2 = s_z2[0];
-    U128 Q2{s_lo[0], s_hi[0]};
-    for (int i = 1; i < 16; ++i) {
-        Z += s_z[i];
-        Z2 += s_z2[i];
-        Q2 = add128(Q2, U128{s_lo[i], s_hi[i]});
+    if (tid == 0) {
+        double Z = s_z[0], Z2 = s_z2[0];
+        U128 Q2{s_lo[0], s_hi[0]};
+        for (int i = 1; i < 16; ++i) {
+            Z += s_z[i];
+            Z2 += s_z2[i];
+            Q2 = add128(Q2, U128{s_lo[i], s_hi[i]});
+        }
+        const u64 key = s_key;
+        const double m = okey_inv(key);
+        unsigned err = 0;
+        if (s_badf) err = kErrNonfinite;
+        else if (key <= okey(-__builtin_huge_val())) err = kErrDegenerate;
+        ctrl->mkey = key;
+        ctrl->m = m;
+        ctrl->err_call = err;
+        if (err && !ctrl->err_latch) ctrl->err_latch = err;
+        int resample;
+        if (mode == SMC_MODE_FORCE) {
+            resample = 1;
+        } else if (mode == SMC_MODE_NEVER) {
+            resample = 0;
+        } else {
+            // ess_den * S^2 < ess_num * N * Q2; both sides stay below 2^127
+            const U128 lhs = mul128_small(mul64(S, S), (u64)ess_den);
+            const U128 rhs = mul128_small(mul128_small(Q2, (u64)n), (u64)ess_num);
+            resample = lt128(lhs, rhs) ? 1 : 0;
+        }
+        if (err) resample = 0;
+        const u64 U = mul64(r, S).hi;
+        const double logZ = m + log(Z);
+        const double ess = (Z * Z) / Z2;
+        ctrl->S = S;
+        ctrl->U = U;
+        ctrl->Q2lo = Q2.lo;
+        ctrl->Q2hi = Q2.hi;
+        ctrl->Z = Z;
+        ctrl->Z2 = Z2;
+        ctrl->logZ = logZ;
+        ctrl->ess = ess;
+        ctrl->K = K;
+        ctrl->resample = (unsigned)resample;
+        ctrl->pending = err ? 0 : 1;
+        if (info) {
+            info->m = m;
+            info->logZ = logZ;
+            info->ess = ess;
+            info->Z = Z;
+            info->Z2 = Z2;
+            info->S = S;
+            info->U = U;
+            info->Q2_hi = Q2.hi;
+            info->Q2_lo = Q2.lo;
+            info->K = K;
+            info->resampled = resample;
+            info->err = (int)err;
+            info->pad = 0;
+            info->log_c = 0.0;
+        }
     }
-    const u64 key = s_key;
-    const double m = okey_inv(key);
-    unsigned err = 0;
-    if (s_badf) err = kErrNonfinite;
-    else if (key <= okey(-__builtin_huge_val())) err = kErrDegenerate;
-    ctrl->mkey = key;
-    ctrl->m = m;
-    ctrl->err_call = err;
-    if (err && !ctrl->err_latch) ctrl->err_latch = err;
-    int resample;
-    if (mode == SMC_MODE_FORCE) {
-        resample = 1;
-    } else if (mode == SMC_MODE_NEVER) {
-        resample = 0;
-    } else {
-        // ess_den * S^2 < ess_num * N * Q2; both sides stay below 2^127
-        const U128 lhs = mul128_small(mul64(S, S), (u64)ess_den);
-        const U128 rhs = mul128_small(mul128_small(Q2, (u64)n), (u64)ess_num);
-        resample = lt128(lhs, rhs) ? 1 : 0;
-    }
-    if (err) resample = 0;
-    const u64 U = mul64(r, S).hi;
-    const double logZ = m + log(Z);
-    const double ess = (Z * Z) / Z2;
-    ctrl->S = S;
-    ctrl->U = U;
-    ctrl->Q2lo = Q2.lo;
-    ctrl->Q2hi = Q2.hi;
-    ctrl->Z = Z;
-    ctrl->Z2 = Z2;
-    ctrl->logZ = logZ;
-    ctrl->ess = ess;
-    ctrl->K = K;
-    ctrl->resample = (unsigned)resample;
-    ctrl->pending = err ? 0 : 1;
-    if (info) {
-        info->m = m;
-        info->logZ = logZ;
-        info->ess = ess;
-        info->Z = Z;
-        info->Z2 = Z2;
-        info->S = S;
-        info->U = U;
-        info->Q2_hi = Q2.hi;
-        info->Q2_lo = Q2.lo;
-        info->K = K;
-        info->resampled = resample;
-        info->err = (int)err;
-        info->pad = 0;
-        info->log_c = 0.0;
+    // a sampler iteration's statistics follow the decision in the same
+    // workgroup (they read the log Z and the decision written above)
+    if (st.is_part) {
+        __syncthreads();
+        step_stats_block<1024>(ctrl, st.is_part, st.nblk, st.d, st.rec_num, st.est, info, 0);
     }
 }
 
 hipError_t launch_decide(const Work &w, int par, int64_t n, int K, uint64_t r, int mode,
-                         int ess_num, int ess_den, void *info, hipStream_t s)
+                         int ess_num, int ess_den, void *info, hipStream_t s,
+                         const StatsArgs &st)
 {
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(1024), 0, s, w.ctrl, w.slots, par, w.tpart,
                        w.tsum, w.n_tiles, (i64)n, K, (u64)r, mode, ess_num, ess_den,
-                       reinterpret_cast<smc_resample_info *>(info));
+                       reinterpret_cast<smc_resample_info *>(info), st);
     return hipGetLastError();
 }
 

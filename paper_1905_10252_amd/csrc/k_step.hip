@@ -32,7 +32,10 @@
 #include "kernels.hpp"
 #include "reduce.hpp"
 #include "rng_wave.hpp"
+#include "stats.hpp"
 #include "step.hpp"
+
+static_assert(smc::kStatsMaxDim == smc::kMaxDim, "statistics width");
 
 namespace smc {
 
@@ -334,87 +337,7 @@ __global__ __launch_bounds__(256) void k_step_stats(Ctrl *ctrl, const double *is
                                                     int d, double *rec_num, double *est,
                                                     smc_resample_info *info, int init)
 {
-    __shared__ double s_col[2 + 2 * kMaxDim];
-    __shared__ double s_red[4][2 + 2 * kMaxDim];
-    __shared__ double s_sc, s_wgt, s_den;
-    __shared__ u64 s_mk[4];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int ncol = 2 + 2 * d;
-    // reference: the largest block reference (blocks with no weight carry -inf)
-    u64 mk = 0;
-    for (int b = tid; b < nblk; b += 256) {
-        const u64 k = okey(is_part[(i64)b * ncol]);
-        mk = k > mk ? k : mk;
-    }
-    mk = wave_max_u64(mk);
-    if ((tid & 63) == 0) s_mk[tid >> 6] = mk;
-    __syncthreads();
-    for (int i = 1; i < 4; ++i) mk = s_mk[i] > mk ? s_mk[i] : mk;
-    mk = s_mk[0] > mk ? s_mk[0] : mk;
-    const double m = okey_inv(mk);
-    // thread tid folds blocks tid, tid + 256, ... (nblk <= kIsBlocks), then a
-    // fixed-order wave and block sum per column
-    constexpr int kPer = kIsBlocks / 256;
-    double sc[kPer];
-    for (int j = 0; j < kPer; ++j) {
-        const int b = tid + 256 * j;
-        const double mb = b < nblk ? is_part[(i64)b * ncol] : -__builtin_huge_val();
-        sc[j] = mb > -__builtin_huge_val() ? det_exp(mb - m) : 0.0;
-    }
-    for (int c = 1; c < ncol; ++c) {
-        double acc = 0.0;
-        for (int j = 0; j < kPer; ++j) {
-            const int b = tid + 256 * j;
-            if (b < nblk && sc[j] != 0.0) acc += sc[j] * is_part[(i64)b * ncol + c];
-        }
-        acc = wave_sum_f64(acc);
-        if (lane == 0) s_red[wid][c] = acc;
-    }
-    __syncthreads();
-    for (int c = 1 + tid; c < ncol; c += 256)
-        s_col[c] = ((s_red[0][c] + s_red[1][c]) + s_red[2][c]) + s_red[3][c];
-    __syncthreads();
-    const double E0 = s_col[1];
-    if (init) {
-        if (tid == 0) {
-            ctrl->logZ_prev = m + log(E0);
-            ctrl->lc_max = -__builtin_huge_val();
-            ctrl->rec_den = 0.0;
-            ctrl->rec_steps = 0;
-        }
-        for (int c = tid; c < 2 * d; c += 256) rec_num[c] = 0.0;
-        return;
-    }
-    if (tid == 0) {
-        const double logc = ctrl->logZ - ctrl->logZ_prev;
-        double sc = 1.0;
-        double den = ctrl->rec_den;
-        if (logc > ctrl->lc_max) {
-            sc = ctrl->rec_steps ? exp(ctrl->lc_max - logc) : 0.0;
-            den *= sc;
-            ctrl->lc_max = logc;
-        }
-        const double wgt = exp(logc - ctrl->lc_max);
-        den += wgt;
-        ctrl->rec_den = den;
-        ctrl->rec_steps += 1;
-        ctrl->log_c = logc;
-        ctrl->logZ_prev = (ctrl->resample && !ctrl->err_call) ? 0.0 : ctrl->logZ;
-        s_sc = sc;
-        s_wgt = wgt;
-        s_den = den;
-        if (info) info->log_c = logc;
-    }
-    __syncthreads();
-    for (int k = tid; k < 2 * d; k += 256) {
-        const double f = s_col[2 + k] / E0;
-        const double num = rec_num[k] * s_sc + s_wgt * f;
-        rec_num[k] = num;
-        if (est) {
-            est[k] = f;
-            est[2 * d + k] = num / s_den;
-        }
-    }
+    step_stats_block<256>(ctrl, is_part, nblk, d, rec_num, est, info, init);
 }
 
 // uniform (lazy reset): instead of writing logw, mark the weights uniform.
@@ -1462,13 +1385,18 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
     if (launch_quant_scan(w, logw, n, K, par, s, c.lazy_reset != 0) != hipSuccess)
         return SMC_E_DEVICE;
     const uint64_t r = resample_word(c.seed, c.sampler_id, t);
-    if (launch_decide(w, par, n, K, r, c.mode, c.ess_num, c.ess_den, info, s) != hipSuccess)
-        return SMC_E_DEVICE;
-    if (!pf) {  // Alg 2 estimates come before resampling
-        hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
-                           w.is_grid, c.d, w.rec_num, est, info, 0);
-        if (hipGetLastError() != hipSuccess) return SMC_E_DEVICE;
+    // Alg 2 estimates come before resampling: the decision's workgroup forms
+    // them (the filter takes its mean after resampling, below)
+    StatsArgs st;
+    if (!pf) {
+        st.is_part = w.is_part;
+        st.nblk = w.is_grid;
+        st.d = c.d;
+        st.rec_num = w.rec_num;
+        st.est = est;
     }
+    if (launch_decide(w, par, n, K, r, c.mode, c.ess_num, c.ess_den, info, s, st) != hipSuccess)
+        return SMC_E_DEVICE;
     const double reset = -std::log((double)n);
     unsigned *uni = c.lazy_reset ? &w.ctrl->uniform : nullptr;
     if (fwd) {

@@ -75,10 +75,19 @@ hipError_t launch_fold(const Work &w, int par, hipStream_t s);
 // after the kernels that read it).
 hipError_t launch_quant_scan(const Work &w, const double *lw, int64_t n, int K, int par,
                              hipStream_t s, bool clear_uniform = false);
+// A sampler iteration's statistics, computed by the decision's workgroup
+// right after the decision (is_part NULL: none).
+struct StatsArgs {
+    const double *is_part = nullptr;
+    int nblk = 0, d = 0;
+    double *rec_num = nullptr, *est = nullptr;
+};
+
 // Error and decision of the call from the max slots of parity par and the
 // scan; info is a device smc_resample_info (nullable).
 hipError_t launch_decide(const Work &w, int par, int64_t n, int K, uint64_t r, int mode,
-                         int ess_num, int ess_den, void *info, hipStream_t s);
+                         int ess_num, int ess_den, void *info, hipStream_t s,
+                         const StatsArgs &st = StatsArgs());
 hipError_t launch_clear_scan(const Work &w, hipStream_t s);
 // Normalised weights exp(l_i - m) / Z from the last decision.
 hipError_t launch_weights(const Work &w, const double *lw, int64_t n, double *out, hipStream_t s);
