@@ -47,14 +47,31 @@ __device__ inline void step_stats_block(Ctrl *ctrl, const double *is_part, int n
         const double mb = b < nblk ? is_part[(i64)b * ncol] : -__builtin_huge_val();
         sc[j] = mb > -__builtin_huge_val() ? det_exp(mb - m) : 0.0;
     }
-    for (int c = 1; c < ncol; ++c) {
-        double acc = 0.0;
-        for (int j = 0; j < kPer; ++j) {
-            const int b = tid + NT * j;
-            if (b < nblk && sc[j] != 0.0) acc += sc[j] * is_part[(i64)b * ncol + c];
+    // four columns at a time: their loads are all issued before the first
+    // sum waits on them (the per-column sums and their order are unchanged)
+    constexpr int CU = 4;
+    for (int c0 = 1; c0 < ncol; c0 += CU) {
+        double v[CU][kPer];
+#pragma unroll
+        for (int q = 0; q < CU; ++q)
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) {
+                const int b = tid + NT * j;
+                v[q][j] = (c0 + q < ncol && b < nblk && sc[j] != 0.0)
+                              ? is_part[(i64)b * ncol + c0 + q]
+                              : 0.0;
+            }
+#pragma unroll
+        for (int q = 0; q < CU; ++q) {
+            if (c0 + q >= ncol) break;
+            double acc = 0.0;
+            for (int j = 0; j < kPer; ++j) {
+                const int b = tid + NT * j;
+                if (b < nblk && sc[j] != 0.0) acc += sc[j] * v[q][j];
+            }
+            acc = wave_sum_f64(acc);
+            if (lane == 0) s_red[wid][c0 + q] = acc;
         }
-        acc = wave_sum_f64(acc);
-        if (lane == 0) s_red[wid][c] = acc;
     }
     __syncthreads();
     for (int c = 1 + tid; c < ncol; c += NT) {
