@@ -333,11 +333,12 @@ __global__ __launch_bounds__(256) void k_reweight(i64 n, int d, const double *__
 }
 
 // -------------------------------------------- estimates, c_t and recycling
-__global__ __launch_bounds__(256) void k_step_stats(Ctrl *ctrl, const double *is_part, int nblk,
-                                                    int d, double *rec_num, double *est,
-                                                    smc_resample_info *info, int init)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_step_stats(Ctrl *ctrl, const double *is_part, int nblk,
+                                                   int d, double *rec_num, double *est,
+                                                   smc_resample_info *info, int init)
 {
-    step_stats_block<256>(ctrl, is_part, nblk, d, rec_num, est, info, init);
+    step_stats_block<NT>(ctrl, is_part, nblk, d, rec_num, est, info, init);
 }
 
 // uniform (lazy reset): instead of writing logw, mark the weights uniform.
@@ -1324,7 +1325,7 @@ smc_status step_init(const smc_config &c, const Work &w, int par, double *x, dou
     if (c.target == SMC_TARGET_BEARING)  // equal initial weights: sums from the common reference
         hipLaunchKernelGGL(k_post_est<4>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)c.n,
                            c.d, x, logw, -std::log((double)c.n), w.is_part);
-    hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part, w.is_grid,
+    hipLaunchKernelGGL(k_step_stats<1024>, dim3(1), dim3(1024), 0, s, w.ctrl, w.is_part, w.is_grid,
                        c.d, w.rec_num, (double *)nullptr, (smc_resample_info *)nullptr, 1);
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
@@ -1411,7 +1412,7 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
                                c.d, x, w.x_scr, (double *)nullptr, (const double *)nullptr,
                                logw, reset, w.is_part, (const double *)ep,
                                (i64)expand_segments(n), uni);
-            hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(256), 0, s, w.ctrl, w.is_part,
+            hipLaunchKernelGGL(k_step_stats<1024>, dim3(1), dim3(1024), 0, s, w.ctrl, w.is_part,
                                w.is_grid, c.d, w.rec_num, est, info, 0);
         } else {
             hipLaunchKernelGGL(k_reset_est<0>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)n,
