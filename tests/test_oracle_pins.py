@@ -420,6 +420,50 @@ def test_log_c_is_ratio_of_weight_sums():
     assert abs(out["log_c"] - (after - before)) < 1e-12
 
 
+def test_log_c_after_a_resampling_step():
+    """eq. normconst across the reset of Alg 4: after a resampling step the
+    weights are 1/N each (sum 1), so the next log c_t is the log-sum-exp of
+    the new log-weights alone, and those are -ln N + log pi(x_t) - log pi(x_{t-1})
+    (scipy's normal log-density; the proposal is the step's random walk).  A
+    reset to 1 instead of 1/N, or a log Z_{t-1} left at the pre-reset value,
+    moves log c_t by ln N or more."""
+    g = I.GAUSS1D
+    s = gauss_sampler(11, mode=O.MODE_FORCE)
+    s.init()
+    s.step()
+    assert np.all(s.logw == -math.log(s.cfg.n))
+    x_prev = s.x[:, 0].copy()
+    s.cfg.mode = O.MODE_NEVER  # keep the weights of the next step in place
+    out = s.step()
+    tgt = stats.norm(loc=g["mean"][0], scale=math.sqrt(g["var"][0]))
+    z = np.array([O.normals(s.cfg.seed, O.TAG_PROPOSE, 0, 2, i, 1)[0] for i in range(s.cfg.n)])
+    x_new = x_prev + g["rw_sd"] * z
+    assert np.allclose(s.x[:, 0], x_new, rtol=0, atol=1e-15)
+    lw = -math.log(s.cfg.n) + tgt.logpdf(x_new) - tgt.logpdf(x_prev)
+    assert np.allclose(s.logw, lw, rtol=0, atol=1e-12)
+    assert abs(out["log_c"] - special.logsumexp(lw)) < 1e-12
+    assert abs(out["info"]["logZ"] - special.logsumexp(lw)) < 1e-12
+
+
+def test_evidence_estimate_is_unbiased():
+    """The running product of the c_t with the initial sum w0 / N estimates
+    integral(pi) = 1 without bias at any N, with resampling in between
+    (systematic resampling is unbiased); N(2, 1) is normalised, so the mean
+    over 1000 seeds of exp(log(sum w0 / N) + sum_t log c_t) after three forced
+    resampling steps is 1 within 5 standard errors (about 0.005).  A wrong
+    reset convention scales the product by a power of N."""
+    vals = []
+    for seed in range(1, 1001):
+        s = gauss_sampler(seed, mode=O.MODE_FORCE)
+        s.init()
+        lz = s.rec.logZ_prev - math.log(s.cfg.n)
+        for _ in range(3):
+            lz += s.step()["log_c"]
+        vals.append(math.exp(lz))
+    v = np.array(vals)
+    assert abs(v.mean() - 1.0) < 5 * v.std() / math.sqrt(v.size)
+
+
 def test_logreg_log_target_bruteforce():
     rng = np.random.default_rng(14)
     X = rng.standard_normal((7, 3))
@@ -465,7 +509,7 @@ def test_pf_transition_moments_closed_form():
     """With a flat likelihood and no resampling, one step moves the cloud to
     A mu0 with covariance A A^T + Q (the paper's process noise)."""
     f, _, _ = pf(1 << 16, obs_var=1e12, mode=O.MODE_NEVER)
-    f.step()
+    out = f.step()
     A = np.array([[1, 1, 0, 0], [0, 1, 0, 0], [0, 0, 1, 1], [0, 0, 0, 1]], float)
     Q = np.zeros((4, 4))
     Q[:2, :2] = Q[2:, 2:] = [[5 / 3, 5 / 2], [5 / 2, 5]]
@@ -476,6 +520,33 @@ def test_pf_transition_moments_closed_form():
     se = np.sqrt(np.diag(cov) / f.x.shape[0])
     assert np.all(np.abs(emp_mu - mu) < 5 * se)
     assert np.all(np.abs(emp_cov - cov) < 0.05 * np.sqrt(np.outer(np.diag(cov), np.diag(cov))))
+    # the filter's reported estimate (Alg 1 "Mean"): the weighted mean and
+    # second moment, here under an almost flat likelihood
+    assert np.all(np.abs(out["mean"] - mu) < 5 * se)
+    m2 = np.diag(cov) + mu ** 2
+    assert np.all(np.abs(out["m2"] - m2) < 0.05 * m2 + 5 * se * np.abs(mu))
+
+
+def test_pf_mean_after_resampling_is_plain_mean():
+    """Alg 1 forms its estimate after resampling: with resampling forced the
+    weights are equal, so the reported mean and second moment are the plain
+    averages of the resampled rows (numpy, in long double)."""
+    f, _, _ = pf(5000, T=4, mode=O.MODE_FORCE)
+    for _ in range(4):
+        out = f.step()
+        assert out["info"]["resampled"] == 1
+        xl = f.x.astype(np.longdouble)
+        mean = np.asarray(xl.mean(0), dtype=np.float64)
+        m2 = np.asarray((xl * xl).mean(0), dtype=np.float64)
+        assert np.allclose(out["mean"], mean, rtol=1e-12, atol=1e-13)
+        assert np.allclose(out["m2"], m2, rtol=1e-12, atol=1e-13)
+    # and with the ESS rule keeping the weights: the weighted averages
+    g, _, _ = pf(5000, T=2, mode=O.MODE_NEVER)
+    out = g.step()
+    w = np.exp(g.logw - g.logw.max())
+    w /= w.sum()
+    assert np.allclose(out["mean"], w @ g.x, rtol=1e-10, atol=1e-12)
+    assert np.allclose(out["m2"], w @ (g.x * g.x), rtol=1e-10, atol=1e-12)
 
 
 def test_pf_likelihood_is_bearing_gaussian():
