@@ -720,6 +720,7 @@ __global__ __launch_bounds__(256) void k_bdecide(const BSlot *slots, const int *
     __shared__ u64 s_lo[4], s_hi[4];
     __shared__ double s_col[2 * SMC_BATCH_DMAX];
     __shared__ double s_sc, s_wgt, s_den, s_Z;
+    __shared__ unsigned s_err;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if ((int)blockIdx.x >= n_act[0]) return;
     const int slot = act[blockIdx.x];
@@ -780,20 +781,23 @@ __global__ __launch_bounds__(256) void k_bdecide(const BSlot *slots, const int *
         const u64 U = mul64(r, Ssum).hi;
         const double logZ = m + log(Z);
         const double ess = (Z * Z) / Z2;
-        // normalising constant (eq. normconst) and recycling (eq. recycling)
-        const double logc = logZ - c->logZ_prev;
-        double sc = 1.0, den = c->rec_den;
-        if (logc > c->lc_max) {
-            sc = c->rec_steps ? exp(c->lc_max - logc) : 0.0;
-            den *= sc;
-            c->lc_max = logc;
+        // normalising constant (eq. normconst) and recycling (eq. recycling);
+        // an iteration that found an error leaves them and the estimates
+        double logc = 0.0, sc = 1.0, wgt = 0.0, den = c->rec_den;
+        if (!err) {
+            logc = logZ - c->logZ_prev;
+            if (logc > c->lc_max) {
+                sc = c->rec_steps ? exp(c->lc_max - logc) : 0.0;
+                den *= sc;
+                c->lc_max = logc;
+            }
+            wgt = exp(logc - c->lc_max);
+            den += wgt;
+            c->rec_den = den;
+            c->rec_steps += 1;
+            c->log_c = logc;
+            c->logZ_prev = resample ? 0.0 : logZ;
         }
-        const double wgt = exp(logc - c->lc_max);
-        den += wgt;
-        c->rec_den = den;
-        c->rec_steps += 1;
-        c->log_c = logc;
-        c->logZ_prev = (resample && !err) ? 0.0 : logZ;
         c->S = Ssum;
         c->U = U;
         c->Q2lo = Q2.lo;
@@ -811,6 +815,7 @@ __global__ __launch_bounds__(256) void k_bdecide(const BSlot *slots, const int *
         s_wgt = wgt;
         s_den = den;
         s_Z = Z;
+        s_err = err;
         if (info) {
             smc_resample_info *o = info + slot;
             o->m = m;
@@ -830,7 +835,7 @@ __global__ __launch_bounds__(256) void k_bdecide(const BSlot *slots, const int *
         }
     }
     __syncthreads();
-    if (tid < 2 * d) {
+    if (tid < 2 * d && !s_err) {
         const double f = s_col[tid] / s_Z;
         const double num = S.rec_num[tid] * s_sc + s_wgt * f;
         S.rec_num[tid] = num;

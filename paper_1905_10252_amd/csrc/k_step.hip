@@ -548,7 +548,7 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
     __shared__ u64 s_key[16], s_wsum[16], s_lo[16], s_hi[16];
     __shared__ unsigned s_bad[16];
     __shared__ double s_bc[4];
-    __shared__ u64 s_bu[3];
+    __shared__ u64 s_bu[4];
     __shared__ double s_lpv[kD1 ? kSmallN : 1];
     constexpr int DM = kD1 ? 1 : kSmallD;  // coordinates a thread handles
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -755,19 +755,23 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
         ctrl->K = K;
         ctrl->resample = (unsigned)resample;
         ctrl->pending = 0;
-        const double logc = logZ - ctrl->logZ_prev;
-        double sc = 1.0, den = ctrl->rec_den;
-        if (logc > ctrl->lc_max) {
-            sc = ctrl->rec_steps ? exp(ctrl->lc_max - logc) : 0.0;
-            den *= sc;
-            ctrl->lc_max = logc;
+        // c_t and the recycling sums; an iteration that found an error leaves
+        // them (and the estimates) unchanged
+        double logc = 0.0, sc = 1.0, wgt = 0.0, den = ctrl->rec_den;
+        if (!err) {
+            logc = logZ - ctrl->logZ_prev;
+            if (logc > ctrl->lc_max) {
+                sc = ctrl->rec_steps ? exp(ctrl->lc_max - logc) : 0.0;
+                den *= sc;
+                ctrl->lc_max = logc;
+            }
+            wgt = exp(logc - ctrl->lc_max);
+            den += wgt;
+            ctrl->rec_den = den;
+            ctrl->rec_steps += 1;
+            ctrl->log_c = logc;
+            ctrl->logZ_prev = resample ? 0.0 : logZ;
         }
-        const double wgt = exp(logc - ctrl->lc_max);
-        den += wgt;
-        ctrl->rec_den = den;
-        ctrl->rec_steps += 1;
-        ctrl->log_c = logc;
-        ctrl->logZ_prev = (resample && !err) ? 0.0 : logZ;
         if (info) {
             info->m = m;
             info->logZ = logZ;
@@ -791,9 +795,10 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
         s_bu[0] = S;
         s_bu[1] = U;
         s_bu[2] = (u64)resample;
+        s_bu[3] = (u64)err;
     }
     __syncthreads();
-    if (tid < 2 * d) {
+    if (tid < 2 * d && !s_bu[3]) {
         const double f = s_tot[tid] / s_bc[3];
         const double num = rec_num[tid] * s_bc[0] + s_bc[1] * f;
         rec_num[tid] = num;

@@ -91,6 +91,13 @@ __device__ inline void step_stats_block(Ctrl *ctrl, const double *is_part, int n
         for (int c = tid; c < 2 * d; c += NT) rec_num[c] = 0.0;
         return;
     }
+    // an iteration whose decision found an error (NaN / +inf weight, all
+    // weights zero) leaves c_t, the recycling sums and the estimates as they
+    // were, as the iteration stops at the resampling step
+    __shared__ unsigned s_err;
+    if (tid == 0) s_err = ctrl->err_call;
+    __syncthreads();
+    if (s_err) return;
     if (tid == 0) {
         const double logc = ctrl->logZ - ctrl->logZ_prev;
         double sc = 1.0;
@@ -105,7 +112,7 @@ __device__ inline void step_stats_block(Ctrl *ctrl, const double *is_part, int n
         ctrl->rec_den = den;
         ctrl->rec_steps += 1;
         ctrl->log_c = logc;
-        ctrl->logZ_prev = (ctrl->resample && !ctrl->err_call) ? 0.0 : ctrl->logZ;
+        ctrl->logZ_prev = ctrl->resample ? 0.0 : ctrl->logZ;
         s_sc = sc;
         s_wgt = wgt;
         s_den = den;

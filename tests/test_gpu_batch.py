@@ -231,3 +231,36 @@ def test_autotuner_picks_a_candidate(dev):
     specs = I.batch_specs(count=12, seed=301)
     r = tune.tune_group(specs, device=dev, steps=1)
     assert r["best"] in tune.GROUP_CANDIDATES and set(r["ms"]) == set(tune.GROUP_CANDIDATES)
+
+
+def test_batch_failed_iteration_leaves_recycling(smc, dev):
+    """A NaN log-weight in one sampler fails that sampler's iteration at the
+    resampling step: its c_t and recycling sums stay as they were (the oracle
+    returns there), its neighbour is untouched, and after the repair both
+    continue as the oracle's samplers do."""
+    B = smc.Batch(2, graph=True, device=dev)
+    sps = [spec(0, 3000, 5, O.MODE_AUTO, seed=610), spec(1, 5000, 12, O.MODE_AUTO, seed=610)]
+    os_ = []
+    for k, sp in enumerate(sps):
+        attach(B, k, sp)
+        os_.append(oracle_of(B, k, sp))
+    for t in range(3):
+        B.step()
+        for k in range(2):
+            check_step(B, k, os_[k], os_[k].step(), "before t=%d slot %d" % (t, k))
+    B.logw(1)[7] = float("nan")
+    os_[1].logw[7] = np.nan
+    B.step()
+    check_step(B, 0, os_[0], os_[0].step(), "failed step, slot 0")
+    with pytest.raises(ValueError):
+        os_[1].step()
+    assert B.info(1)["err"] == O.E_NONFINITE
+    assert B.sync_error(1) == O.E_NONFINITE
+    check_state(B, 1, os_[1], "failed step, slot 1")
+    B.logw(1)[7] = -0.5
+    os_[1].logw[7] = -0.5
+    for t in range(3):
+        B.step()
+        for k in range(2):
+            check_step(B, k, os_[k], os_[k].step(), "after t=%d slot %d" % (t, k))
+    assert B.sync_error(0) == 0 and B.sync_error(1) == 0

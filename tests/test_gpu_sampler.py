@@ -446,3 +446,54 @@ def test_lazy_reset_with_steps(smc, dev):
     assert np.array_equal(bits(E.x.cpu().numpy()), bits(Lz.x.cpu().numpy()))
     Lz.sync_weights()
     assert np.array_equal(bits(E.logw.cpu().numpy()), bits(Lz.logw.cpu().numpy()))
+
+
+@pytest.mark.parametrize("mode", ["auto", "force"])
+def test_gauss_4d_multi_kernel_path(smc, dev, mode):
+    """d = 4 above the one-workgroup size: the update kernel's four-coordinate
+    one-pass estimate; bit-exact trajectories against the oracle."""
+    _say("gauss 4d", mode)
+    G, Or = pair_gauss(smc, dev, 5000, [0.5, -1.0, 2.0, 0.0], [1.0, 0.5, 2.0, 1.5], 29,
+                       MODES[mode], rw_sd=0.4)
+    run_and_compare(G, Or, 6)
+
+
+@pytest.mark.parametrize("kind,n,d", [("gauss", 3001, 3), ("gauss", 1024, 1),
+                                      ("student", 70001, 1)])
+def test_failed_iteration_leaves_recycling(smc, dev, kind, n, d):
+    """A NaN log-weight makes one iteration fail at the resampling step (the
+    oracle returns there): c_t, the recycling sums and log Z_{t-1} stay as they
+    were, so once the weight is repaired the run continues as the oracle's
+    does, recycled estimates included."""
+    import torch
+    _say("failed iteration %s n=%d d=%d" % (kind, n, d))
+    if kind == "student":
+        _, G, Or = _steps_pair(smc, dev, "student", n, 1, O.MODE_AUTO, 13)
+    else:
+        rng = np.random.default_rng(d)
+        G, Or = pair_gauss(smc, dev, n, rng.standard_normal(d), rng.uniform(0.5, 2.0, d), 13,
+                           O.MODE_AUTO, rw_sd=0.4)
+    for _ in range(3):
+        G.step()
+        Or.step()
+    G.logw[5] = float("nan")
+    Or.logw[5] = np.nan
+    G.step()
+    with pytest.raises(ValueError):
+        Or.step()
+    assert G.info()["err"] == O.E_NONFINITE
+    assert G.sync_error() == O.E_NONFINITE
+    assert np.array_equal(bits(G.x.cpu().numpy()), bits(Or.x))
+    G.logw[5] = 0.25
+    Or.logw[5] = 0.25
+    for t in range(3):
+        G.step()
+        out = Or.step()
+        assert np.array_equal(bits(G.x.cpu().numpy()), bits(Or.x)), t
+        assert np.array_equal(bits(G.logw.cpu().numpy()), bits(Or.logw)), t
+        assert abs(G.info()["log_c"] - out["log_c"]) <= 1e-11, t
+        e = G.estimates()
+        for k in ("mean", "m2", "rec_mean", "rec_m2"):
+            assert_close(e[k], out[k], 1e-11, "%s after the failed iteration, t=%d" % (k, t))
+    assert G.sync_error() == 0
+    del torch
