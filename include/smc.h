@@ -173,7 +173,8 @@ smc_status smc_normalised_weights(smc_ctx *ctx, const double *logw, int64_t n, d
  * ncopies == NULL uses the pending result of the last smc_resample on this
  * context; otherwise the given int64[n] counts are scanned first (each >= 0,
  * summing to n, else err = SMC_E_ARG on the device and nothing is written).
- * row_bytes is a positive multiple of 4; x_out must not overlap x.
+ * row_bytes is a positive multiple of 4 of at most 2^20 (1 MiB), and
+ * n * row_bytes at most 2^46; x_out must not overlap x.
  * ncopies_out and anc (int64[n], nullable) receive the counts and the source
  * index of every output row. */
 smc_status smc_redistribute(smc_ctx *ctx, const int64_t *ncopies, const void *x, void *x_out,

@@ -18,6 +18,10 @@ constexpr int kMaxBlocks = 1024;                  // grid of the max / reweight 
 constexpr int kIsBlocks = 2048;                   // max grid of the sampler kernels
 constexpr int kExpandThreads = 256;
 constexpr int kSegLen = 2048;                     // merge-path steps per expand workgroup
+// Largest row of smc_redistribute: a segment's 32-bit chunk count
+// (kSegLen rows of row_bytes / 4 chunks) then stays below 2^31.
+constexpr int kMaxRowBytes = 1 << 20;
+static_assert((long long)kSegLen * (kMaxRowBytes / 4) < (1ll << 31), "expand chunk count");
 constexpr int kEstCols = 10;                      // 2 + 2 d sums of a filter row (d = 4)
 static_assert(kSegLen + 1 <= kTile, "an expand segment spans at most two scan tiles");
 constexpr int kLogregSplit = 8;                   // row blocks of the likelihood contraction

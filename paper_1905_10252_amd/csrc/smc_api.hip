@@ -244,7 +244,7 @@ smc_status smc_redistribute(smc_ctx *ctx, const int64_t *ncopies, const void *x,
                             void *stream)
 {
     if (!ctx || !x || !x_out || n != ctx->cfg.n) return SMC_E_ARG;
-    if (row_bytes <= 0 || (row_bytes & 3)) return SMC_E_ARG;
+    if (row_bytes <= 0 || (row_bytes & 3) || row_bytes > kMaxRowBytes) return SMC_E_ARG;
     if (((uintptr_t)x & 3) || ((uintptr_t)x_out & 3)) return SMC_E_ARG;
     if (((uintptr_t)ncopies & 7) || ((uintptr_t)ncopies_out & 7) || ((uintptr_t)anc & 7))
         return SMC_E_ARG;

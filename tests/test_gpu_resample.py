@@ -321,3 +321,29 @@ def test_normalised_weights(smc, dev, n, s):
     assert np.array_equal(w[~pos], ref[~pos])
     assert np.max(np.abs(w[pos] / ref[pos] - 1.0)) < 1e-12
     assert abs(w.sum() - 1.0) < 1e-12
+
+
+def test_redistribute_row_size_bound(smc, dev):
+    """Rows up to 1 MiB are copied (the expand's 32-bit chunk count per
+    segment stays in range); a larger row is an argument error, returned
+    before anything is enqueued."""
+    import ctypes as C
+    import torch
+    n = 5
+    lw = np.array([0.0, -1.0, 2.0, -0.5, 1.0])
+    R = smc.Resampler(n, device=dev)
+    R.resample(torch.from_numpy(lw).to(dev), 12345, O.MODE_FORCE)
+    row = 1 << 20
+    x = torch.arange(n * row // 4, dtype=torch.int32, device=dev).view(n, row // 4)
+    xo = R.redistribute(x)
+    torch.cuda.synchronize()
+    onc, _ = O.resample(lw, 12345, O.MODE_FORCE)
+    ox, _ = O.redistribute(onc, x.cpu().numpy())
+    assert np.array_equal(xo.cpu().numpy(), ox)
+    big = torch.zeros(n * (row + 4), dtype=torch.uint8, device=dev)
+    out = torch.zeros_like(big)
+    lib = smc.L.load()
+    rc = lib.smc_redistribute(R.ctx, None, C.c_void_p(big.data_ptr()), C.c_void_p(out.data_ptr()),
+                              n, row + 4, None, None, smc._stream())
+    assert rc == smc.L.SMC_E_ARG
+    del x
