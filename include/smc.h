@@ -160,6 +160,24 @@ smc_status smc_steps(smc_ctx *ctx, void *x, double *logw, int32_t nsteps,
 smc_status smc_resample(smc_ctx *ctx, const double *logw, int64_t n, uint64_t r, int32_t mode,
                         int64_t *ncopies, smc_resample_info *info, void *stream);
 
+/* For callers that cannot allocate device memory or create a context
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * allocation): smc_resample on n <= SMC_NOALLOC_MAX_N log-weights with the
+ * same results, bit for bit, as smc_resample with ncopies on a context of
+ * that N (ess_num / ess_den as in smc_config).  Its workspace is a fixed
+ * array in device memory, one per GPU (about 8.6 MB, held until the process
+ * ends); calls allocate nothing.  ncopies (int64[n]) is required; info is
+ * nullable and receives device-found errors (no context latches them).
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one
+ * GPU (different streams or host threads without ordering) race and give
+ * wrong results.  The device is the current one; the stream must belong to
+ * it.  n > SMC_NOALLOC_MAX_N returns SMC_E_NOMEM; other argument errors
+ * SMC_E_ARG. */
+#define SMC_NOALLOC_MAX_N (1 << 20)
+smc_status smc_resample_noalloc(const double *logw, int64_t n, uint64_t r, int32_t mode,
+                                int32_t ess_num, int32_t ess_den, int64_t *ncopies,
+                                smc_resample_info *info, void *stream);
+
 /* eq. normalise: w[i] = exp(logw[i] - m) / Z, with m and the FP64 sum Z of
  * the last smc_resample on this context (call it with the same logw[n]);
  * exp is the deterministic one of the fixed-point weights.  Nothing is

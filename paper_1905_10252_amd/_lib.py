@@ -28,8 +28,9 @@ EXPORTS = ("smc_workspace_bytes", "smc_init", "smc_step", "smc_steps", "smc_sync
            "smc_batch_sampler_bytes", "smc_batch_workspace_bytes", "smc_batch_create",
            "smc_batch_attach", "smc_batch_detach", "smc_batch_step", "smc_batch_set_graph",
            "smc_batch_counts", "smc_batch_sync_error", "smc_batch_destroy",
-           "smc_batch_particles", "smc_batch_set_group")
+           "smc_batch_particles", "smc_batch_set_group", "smc_resample_noalloc")
 BATCH_DMAX, BATCH_EST_STRIDE = 64, 256
+NOALLOC_MAX_N = 1 << 20
 
 
 class SmcConfig(C.Structure):
@@ -95,6 +96,8 @@ def load():
     L.smc_sync_weights.argtypes = [vp, vp, vp]
     L.smc_normalised_weights.argtypes = [vp, vp, C.c_int64, vp, vp]
     L.smc_resample.argtypes = [vp, vp, C.c_int64, C.c_uint64, C.c_int32, vp, vp, vp]
+    L.smc_resample_noalloc.argtypes = [vp, C.c_int64, C.c_uint64, C.c_int32, C.c_int32,
+                                       C.c_int32, vp, vp, vp]
     L.smc_redistribute.argtypes = [vp, vp, vp, vp, C.c_int64, C.c_int32, vp, vp, vp]
     L.smc_log_target.argtypes = [vp, vp, C.c_int64, vp, vp]
     L.smc_sync_error.argtypes = [vp, vp]
@@ -102,6 +105,7 @@ def load():
     L.smc_status_string.argtypes = [C.c_int]
     L.smc_status_string.restype = C.c_char_p
     for f in ("smc_init", "smc_step", "smc_steps", "smc_sync_weights", "smc_resample",
+              "smc_resample_noalloc",
               "smc_normalised_weights", "smc_redistribute",
               "smc_log_target", "smc_sync_error", "smc_destroy"):
         getattr(L, f).restype = C.c_int

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/smc.h"
@@ -16,6 +17,21 @@
 #include "step.hpp"
 
 using namespace smc;
+
+// Workspace of smc_resample_noalloc: a resample-only context's sections for
+// up to SMC_NOALLOC_MAX_N weights (as layout_of() places them in a caller's
+// workspace), in a fixed device array, one copy per GPU, held until the
+// process ends (about 8.6 MB).
+static constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+static constexpr size_t kNaTiles = ((size_t)SMC_NOALLOC_MAX_N + kTile - 1) / kTile;
+static constexpr size_t kNaCtrl = 0;
+static constexpr size_t kNaSlots = kNaCtrl + al256(sizeof(Ctrl));
+static constexpr size_t kNaTsum = kNaSlots + al256(8 * (size_t)kSlotWords);
+static constexpr size_t kNaTpart = kNaTsum + al256(8 * kNaTiles);
+static constexpr size_t kNaPref = kNaTpart + al256(sizeof(TilePart) * kNaTiles);
+static constexpr size_t kNaPref64 = kNaPref + al256(8 * (size_t)SMC_NOALLOC_MAX_N);
+static constexpr size_t kNaBytes = kNaPref64 + al256(8 * ((size_t)SMC_NOALLOC_MAX_N / 64 + 1));
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
 
 struct smc_ctx {
     smc_config cfg;
@@ -113,6 +129,26 @@ Layout layout_of(const smc_config *c)
 }
 
 inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ------------------------------------------------ smc_resample_noalloc
+// Per-device address of `scratch`, looked up once per device (the array's
+// name is not a device address in host code).
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mutex;
+unsigned char *g_na_ptr[kNaMaxDevices];
+
+unsigned char *noalloc_scratch()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNaMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    if (!g_na_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_na_ptr[dev] = reinterpret_cast<unsigned char *>(p);
+    }
+    return g_na_ptr[dev];
+}
 
 bool overlap(const void *a, const void *b, size_t bytes)
 {
@@ -227,6 +263,41 @@ smc_status smc_resample(smc_ctx *ctx, const double *logw, int64_t n, uint64_t r,
         return SMC_E_DEVICE;
     ctx->pending = true;
     if (ncopies && launch_ncopies(w, n, 0, ncopies, s) != hipSuccess) return SMC_E_DEVICE;
+    return SMC_OK;
+}
+
+smc_status smc_resample_noalloc(const double *logw, int64_t n, uint64_t r, int32_t mode,
+                                int32_t ess_num, int32_t ess_den, int64_t *ncopies,
+                                smc_resample_info *info, void *stream)
+{
+    if (!logw || !ncopies || n < 1) return SMC_E_ARG;
+    if (n > SMC_NOALLOC_MAX_N) return SMC_E_NOMEM;
+    if (mode < SMC_MODE_AUTO || mode > SMC_MODE_NEVER) return SMC_E_ARG;
+    if (ess_num < 0 || ess_num > 16 || ess_den < 1 || ess_den > 16) return SMC_E_ARG;
+    if (((uintptr_t)logw & 7) || ((uintptr_t)ncopies & 7) || ((uintptr_t)info & 7))
+        return SMC_E_ARG;
+    unsigned char *b = noalloc_scratch();
+    if (!b) return SMC_E_DEVICE;
+    Work w{};
+    w.ctrl = reinterpret_cast<Ctrl *>(b + kNaCtrl);
+    w.slots = reinterpret_cast<u64 *>(b + kNaSlots);
+    w.tsum = reinterpret_cast<u64 *>(b + kNaTsum);
+    w.tpart = reinterpret_cast<TilePart *>(b + kNaTpart);
+    w.pref = reinterpret_cast<u64 *>(b + kNaPref);
+    w.pref64 = reinterpret_cast<u64 *>(b + kNaPref64);
+    w.n_tiles = n_tiles_of(n);
+    int c = 0;
+    while ((1LL << c) < n) ++c;
+    const int K = 61 - c < 52 ? 61 - c : 52;
+    hipStream_t s = S(stream);
+    // the last call's control block and max slots are cleared by a kernel
+    // (no memset node if the caller captures the stream); parity 0 always
+    if (launch_init_ctrl(w, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_max(w, logw, n, 0, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_quant_scan(w, logw, n, K, 0, s) != hipSuccess) return SMC_E_DEVICE;
+    if (launch_decide(w, 0, n, K, r, mode, ess_num, ess_den, info, s) != hipSuccess)
+        return SMC_E_DEVICE;
+    if (launch_ncopies(w, n, 0, ncopies, s) != hipSuccess) return SMC_E_DEVICE;
     return SMC_OK;
 }
 

@@ -157,6 +157,23 @@ def resample(logw: torch.Tensor, r: int, mode: int = L.MODE_AUTO,
     return rs.resample(logw, r, mode, ncopies=ncopies, info=False)
 
 
+def resample_noalloc(logw: torch.Tensor, r: int, ncopies: torch.Tensor,
+                     mode: int = L.MODE_AUTO, info: torch.Tensor | None = None,
+                     ess_num: int = 1, ess_den: int = 2) -> torch.Tensor:
+    """``resample`` through smc_resample_noalloc: no context, no workspace and
+    no allocation in the library (N <= 2^20; the caller passes ``ncopies``
+    and, optionally, a uint8 device buffer ``info`` of INFO_BYTES)."""
+    n = logw.shape[0]
+    _need(logw, torch.float64, n, "logw")
+    _need(ncopies, torch.int64, n, "ncopies")
+    if info is not None:
+        _need(info, torch.uint8, L.INFO_BYTES, "info")
+    L.check(L.load().smc_resample_noalloc(_ptr(logw), n, int(r) & (2**64 - 1), mode, ess_num,
+                                          ess_den, _ptr(ncopies), _ptr(info), _stream()),
+            "smc_resample_noalloc")
+    return ncopies
+
+
 def redistribute(x: torch.Tensor, ncopies: torch.Tensor | None = None,
                  x_out: torch.Tensor | None = None) -> torch.Tensor:
     """Alg 5 semantics on the rows of ``x`` ([N][...], contiguous, device):
