@@ -183,6 +183,12 @@ struct VecT<4> {
 // stores is non-temporal: the new population is not read again by this call,
 // and keeping it out of the caches spares the next resample the write-back
 // of a cache full of dirty rows (about 5 us per call at N = 2^24 on MI355X).
+// kNtLoad: the source rows are read non-temporally too.  A segment whose
+// outputs are mostly distinct sources reads each line about once; streaming
+// those lines past the caches measured 48 us faster per call at N = 2^24,
+// s = 0.5 (HBM read requests are whole 128-byte lines either way).  Where a
+// few sources fill many outputs (heavy degeneracy) the cached reads are
+// faster, the same lines serving the whole segment.
 // kSum (VEC = 16, rows of four FP64 values): the thread also adds up the two
 // values of every chunk it copies, and their squares, into acc; its chunks all
 // sit in the same half of a row (the lane stride is a multiple of two chunks).
@@ -196,7 +202,7 @@ __device__ inline void add_chunk(const u32x4 &v, double *acc)
     acc[3] += hi * hi;
 }
 
-template <int VEC, bool kSum = false>
+template <int VEC, bool kSum = false, bool kNtLoad = false>
 __device__ inline void copy_rows(const unsigned char *__restrict__ src,
                                  unsigned char *__restrict__ dst, int row_bytes, int cpr_shift,
                                  const unsigned *sAnc, i64 p0, int np, double *acc = nullptr)
@@ -222,7 +228,8 @@ __device__ inline void copy_rows(const unsigned char *__restrict__ src,
                 r = cc / cpr;
                 col = cc - r * cpr;
             }
-            v[u] = *reinterpret_cast<const V *>(src + (i64)sAnc[r] * row_bytes + col * VEC);
+            const V *sp = reinterpret_cast<const V *>(src + (i64)sAnc[r] * row_bytes + col * VEC);
+            v[u] = kNtLoad ? __builtin_nontemporal_load(sp) : *sp;
             doff[u] = (p0 + r) * (i64)row_bytes + col * VEC;
         }
 #pragma unroll
@@ -394,6 +401,9 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
     } else if (VEC == 8 && a.row_bytes == 8 && a.aux && a.aux_bytes == 8) {
         copy_rows_8x2(a.x, a.xo, a.aux, a.auxo, sAnc, p0, np);
         return;
+    } else if (np < 2 * ns) {
+        // fewer than two outputs per source in this segment
+        copy_rows<VEC, false, true>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np);
     } else {
         copy_rows<VEC>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np);
     }
