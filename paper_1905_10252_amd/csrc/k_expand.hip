@@ -255,7 +255,9 @@ __device__ inline void copy_rows(const unsigned char *__restrict__ src,
 }
 
 // Rows of 8 bytes with an 8-byte side row each (a 1-D sampler's particle and
-// its cached log-target): both copies in one loop, twice the loads in flight.
+// its cached log-target): both copies in one loop, twice the loads in flight;
+// kNtLoad as in copy_rows.
+template <bool kNtLoad>
 __device__ inline void copy_rows_8x2(const unsigned char *__restrict__ src,
                                      unsigned char *__restrict__ dst,
                                      const unsigned char *__restrict__ src2,
@@ -272,8 +274,8 @@ __device__ inline void copy_rows_8x2(const unsigned char *__restrict__ src,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const unsigned j = sAnc[r + u * kExpandThreads];
-            v[u] = s1[j];
-            w[u] = s2[j];
+            v[u] = kNtLoad ? __builtin_nontemporal_load(s1 + j) : s1[j];
+            w[u] = kNtLoad ? __builtin_nontemporal_load(s2 + j) : s2[j];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -396,10 +398,14 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
     __syncthreads();
     if constexpr (kSum) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        copy_rows<VEC, true>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np, acc);
+        if (np < 2 * ns)
+            copy_rows<VEC, true, true>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np, acc);
+        else
+            copy_rows<VEC, true>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np, acc);
         store_row_sums(acc, np, a.est_part + (i64)blockIdx.x * kEstCols);
     } else if (VEC == 8 && a.row_bytes == 8 && a.aux && a.aux_bytes == 8) {
-        copy_rows_8x2(a.x, a.xo, a.aux, a.auxo, sAnc, p0, np);
+        if (np < 2 * ns) copy_rows_8x2<true>(a.x, a.xo, a.aux, a.auxo, sAnc, p0, np);
+        else copy_rows_8x2<false>(a.x, a.xo, a.aux, a.auxo, sAnc, p0, np);
         return;
     } else if (np < 2 * ns) {
         // fewer than two outputs per source in this segment
@@ -407,7 +413,12 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
     } else {
         copy_rows<VEC>(a.x, a.xo, a.row_bytes, a.cpr_shift, sAnc, p0, np);
     }
-    if (a.aux) copy_rows<8>(a.aux, a.auxo, a.aux_bytes, a.aux_shift, sAnc, p0, np);
+    if (a.aux) {
+        if (np < 2 * ns)
+            copy_rows<8, false, true>(a.aux, a.auxo, a.aux_bytes, a.aux_shift, sAnc, p0, np);
+        else
+            copy_rows<8>(a.aux, a.auxo, a.aux_bytes, a.aux_shift, sAnc, p0, np);
+    }
 }
 
 static int shift_of(int v)
