@@ -28,7 +28,8 @@ EXPORTS = ("smc_workspace_bytes", "smc_init", "smc_step", "smc_steps", "smc_sync
            "smc_batch_sampler_bytes", "smc_batch_workspace_bytes", "smc_batch_create",
            "smc_batch_attach", "smc_batch_detach", "smc_batch_step", "smc_batch_set_graph",
            "smc_batch_counts", "smc_batch_sync_error", "smc_batch_destroy",
-           "smc_batch_particles", "smc_batch_set_group", "smc_resample_noalloc")
+           "smc_batch_particles", "smc_batch_set_group", "smc_resample_noalloc",
+           "smc_batch_set_bucket_waves")
 BATCH_DMAX, BATCH_EST_STRIDE = 64, 256
 NOALLOC_MAX_N = 1 << 20
 
@@ -121,11 +122,13 @@ def load():
     L.smc_batch_counts.argtypes = [vp, P(C.c_int32), P(C.c_int64)]
     L.smc_batch_particles.argtypes = [vp, C.c_int32, P(vp), P(vp), vp]
     L.smc_batch_set_group.argtypes = [vp, C.c_int32, vp]
+    L.smc_batch_set_bucket_waves.argtypes = [vp, C.c_int32, C.c_int32]
     L.smc_batch_sync_error.argtypes = [vp, C.c_int32, vp]
     L.smc_batch_destroy.argtypes = [vp]
     for f in ("smc_batch_create", "smc_batch_attach", "smc_batch_detach", "smc_batch_step",
               "smc_batch_set_graph", "smc_batch_counts", "smc_batch_sync_error",
-              "smc_batch_destroy", "smc_batch_particles", "smc_batch_set_group"):
+              "smc_batch_destroy", "smc_batch_particles", "smc_batch_set_group",
+              "smc_batch_set_bucket_waves"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L

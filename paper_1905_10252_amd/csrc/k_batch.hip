@@ -366,10 +366,13 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
 // staged in LDS and the row in registers, the weight update, the chunk's max
 // key, non-finite flag and estimate sums against the chunk's own max m_b:
 // [m_b, sum e, sum e x_k, sum e x_k^2], e = exp(l - m_b).
-template <int DB, bool kInit>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DB > 40 ? 2 : (DB > 16 ? 3 : 4)))) void k_bquad(const BSlot *slots, const int *n_act,
-                                               const int *bact, const int *bchunk_pref,
-                                               int bucket, int cap, int single)
+// W: the occupancy the register allocation aims at (waves per SIMD), a
+// per-bucket speed knob (smc_batch_set_bucket_waves); results do not depend
+// on it.
+template <int DB, bool kInit, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k_bquad(
+    const BSlot *slots, const int *n_act, const int *bact, const int *bchunk_pref, int bucket,
+    int cap, int single)
 {
     __shared__ u64 s_key[4];
     __shared__ unsigned s_bad[4];
@@ -1009,6 +1012,7 @@ struct smc_batch {
     int n_act, total_tiles, total_chunks;
     int64_t total_units;
     int G;  // coordinate pairs per proposal unit
+    int quad_waves[kBuckets];  // occupancy aim of k_bquad per dimension bucket
     int btiles[kBuckets];
     // graph of one step for the current membership and output pointers
     bool graph_on;
@@ -1050,23 +1054,49 @@ hipError_t launch_tables(smc_batch *b, hipStream_t s)
     return hipGetLastError();
 }
 
-template <bool kInit>
-void launch_quad_bucket(int q, dim3 g, hipStream_t s, const smc_batch *b, int single)
+// Highest occupancy aim the kernel of bucket width DB can meet (LDS and
+// registers of the wider rows); larger requests are clamped to it.
+constexpr int max_quad_waves(int DB) { return DB <= 16 ? 4 : (DB <= 40 ? 3 : 2); }
+
+template <int DB, bool kInit>
+void launch_quad_waves(int w, dim3 g, hipStream_t s, const smc_batch *b, int q, int single)
 {
     const BSlot *sl = b->d_slots;
     const BTabs &t = b->tabs;
-    switch (q) {
-#define SMC_BIS_CASE(Q)                                                                        \
-    case Q:                                                                                    \
-        hipLaunchKernelGGL((k_bquad<8 * (Q + 1), kInit>), g, dim3(256), 0, s, sl, t.n_act,       \
-                           t.bact, t.btile_pref, Q, b->cap, single);                           \
+    w = w < max_quad_waves(DB) ? w : max_quad_waves(DB);
+    switch (w) {
+#define SMC_BQW_CASE(W)                                                                        \
+    case W:                                                                                    \
+        if constexpr (W <= max_quad_waves(DB))                                                 \
+            hipLaunchKernelGGL((k_bquad<DB, kInit, W>), g, dim3(256), 0, s, sl, t.n_act,       \
+                               t.bact, t.btile_pref, q, b->cap, single);                       \
         break;
-        SMC_BIS_CASE(0) SMC_BIS_CASE(1) SMC_BIS_CASE(2) SMC_BIS_CASE(3)
-        SMC_BIS_CASE(4) SMC_BIS_CASE(5) SMC_BIS_CASE(6) SMC_BIS_CASE(7)
-#undef SMC_BIS_CASE
+        SMC_BQW_CASE(1) SMC_BQW_CASE(2) SMC_BQW_CASE(3) SMC_BQW_CASE(4)
+#undef SMC_BQW_CASE
     default: break;
     }
 }
+
+template <bool kInit>
+void launch_quad_bucket(int q, dim3 g, hipStream_t s, const smc_batch *b, int single)
+{
+    const int w = b->quad_waves[q];
+    switch (q) {
+    case 0: launch_quad_waves<8, kInit>(w, g, s, b, q, single); break;
+    case 1: launch_quad_waves<16, kInit>(w, g, s, b, q, single); break;
+    case 2: launch_quad_waves<24, kInit>(w, g, s, b, q, single); break;
+    case 3: launch_quad_waves<32, kInit>(w, g, s, b, q, single); break;
+    case 4: launch_quad_waves<40, kInit>(w, g, s, b, q, single); break;
+    case 5: launch_quad_waves<48, kInit>(w, g, s, b, q, single); break;
+    case 6: launch_quad_waves<56, kInit>(w, g, s, b, q, single); break;
+    case 7: launch_quad_waves<64, kInit>(w, g, s, b, q, single); break;
+    default: break;
+    }
+}
+
+// Default occupancy aim of the quadratic-form kernel per bucket: the highest
+// it reaches (the widest rows need the registers of two waves per SIMD).
+inline int default_quad_waves(int q) { return max_quad_waves(8 * (q + 1)); }
 
 hipError_t enqueue_step(smc_batch *b, smc_resample_info *info, double *est, hipStream_t s)
 {
@@ -1132,6 +1162,7 @@ smc_status smc_batch_create(smc_batch **h_out, int32_t capacity, void *ws, size_
     for (auto &v : b->h_slots) v.n = 0;
     b->graph_on = true;
     b->G = 8;
+    for (int q = 0; q < kBuckets; ++q) b->quad_waves[q] = default_quad_waves(q);
     b->graph = nullptr;
     b->exec = nullptr;
     b->version = 0;
@@ -1297,6 +1328,16 @@ smc_status smc_batch_set_group(smc_batch *b, int32_t pairs, void *stream)
     b->G = pairs;
     mirror_update(b);
     return launch_tables(b, HS(stream)) == hipSuccess ? SMC_OK : SMC_E_DEVICE;
+}
+
+smc_status smc_batch_set_bucket_waves(smc_batch *b, int32_t bucket, int32_t waves)
+{
+    if (!b || bucket < 0 || bucket >= kBuckets || waves < 1 || waves > 4) return SMC_E_ARG;
+    if (b->quad_waves[bucket] == waves) return SMC_OK;
+    b->quad_waves[bucket] = waves;
+    b->version += 1;  // a captured step holds the old kernel: capture again
+    b->eager_same = 0;
+    return SMC_OK;
 }
 
 smc_status smc_batch_set_graph(smc_batch *b, int32_t enable)

@@ -177,7 +177,16 @@ __device__ inline u64 quant_one(double v, double m, int K, u64 top, double &z, d
     const double f = floor(ldexp(e, K));
     u64 q = (u64)f;
     q = q > top ? top : q;
-    q2 = add128(q2, mul64(q, q));
+    // q < 2^53: q = h 2^32 + l, q^2 = l^2 + 2 h l 2^32 + h^2 2^64
+    const unsigned l = (unsigned)q, h = (unsigned)(q >> 32);
+    const u64 ll = (u64)l * l, hl = (u64)h * l, hh = (u64)h * h;
+    const u64 lo1 = q2.lo + ll;
+    const u64 c1 = lo1 < ll ? 1ull : 0ull;
+    const u64 s = hl << 33;
+    const u64 lo2 = lo1 + s;
+    const u64 c2 = lo2 < s ? 1ull : 0ull;
+    q2.lo = lo2;
+    q2.hi += hh + (hl >> 31) + c1 + c2;
     return q;
 }
 

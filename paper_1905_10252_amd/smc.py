@@ -421,6 +421,12 @@ class Batch:
         L.check(self._lib.smc_batch_set_group(self.h, int(pairs), _stream()),
                 "smc_batch_set_group")
 
+    def set_bucket_waves(self, bucket: int, waves: int) -> None:
+        """Occupancy aim (1-4 waves per SIMD) of the target kernel for samplers
+        with d in (8 bucket, 8 bucket + 8]; speed only."""
+        L.check(self._lib.smc_batch_set_bucket_waves(self.h, int(bucket), int(waves)),
+                "smc_batch_set_bucket_waves")
+
     def set_graph(self, enable: bool) -> None:
         L.check(self._lib.smc_batch_set_graph(self.h, 1 if enable else 0), "smc_batch_set_graph")
 

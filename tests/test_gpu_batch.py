@@ -226,11 +226,54 @@ def test_batch_unit_size_does_not_change_results(smc, dev):
         B.set_group(9)
 
 
-def test_autotuner_picks_a_candidate(dev):
+def test_batch_bucket_waves_do_not_change_results(smc, dev):
+    """The per-bucket occupancy aim of the target kernel is a speed knob:
+    every setting gives the same bits (graph replay included)."""
+    print("batch bucket waves", flush=True)
+    specs = [spec(120 + k, *m) for k, m in enumerate(MIX)]
+    outs = []
+    for waves in (None, 1, 2):
+        B = smc.Batch(len(MIX), device=dev)
+        if waves is not None:
+            for q in range(8):
+                B.set_bucket_waves(q, waves)
+        for slot, sp in enumerate(specs):
+            attach(B, slot, sp)
+        for _ in range(4):
+            B.step()
+        outs.append([(B.x(s).cpu().numpy(), B.logw(s).cpu().numpy(), B.estimates(s)["mean"])
+                     for s in range(len(MIX))])
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            for u, v in zip(a, b):
+                assert np.array_equal(bits(u), bits(v))
+    for bad in ((8, 2), (-1, 2), (3, 0), (3, 5)):
+        with pytest.raises(smc.L.SmcError):
+            B.set_bucket_waves(*bad)
+
+
+def test_autotuner_picks_candidates_and_caches(dev, tmp_path, monkeypatch):
     from paper_1905_10252_amd import tune
+    monkeypatch.setenv("SMC_TUNE_CACHE", str(tmp_path / "tune.json"))
     specs = I.batch_specs(count=12, seed=301)
     r = tune.tune_group(specs, device=dev, steps=1)
+    assert not r["cached"]
     assert r["best"] in tune.GROUP_CANDIDATES and set(r["ms"]) == set(tune.GROUP_CANDIDATES)
+    rb = tune.tune_buckets(specs, device=dev, steps=1, pairs=r["best"])
+    present = sorted({(sp["d"] - 1) // 8 for sp in specs})
+    assert sorted(rb["best"]) == present and not rb["cached"]
+    for q, w in rb["best"].items():
+        assert 1 <= w <= tune._max_waves(q)
+    # the second call reads the cache (keyed by kernel, knob, bucket, device
+    # architecture and workload shapes) instead of timing
+    r2 = tune.tune_group(specs, device=dev, steps=1)
+    rb2 = tune.tune_buckets(specs, device=dev, steps=1)
+    assert r2["cached"] and r2["best"] == r["best"]
+    assert sorted(rb2["cached"]) == present and rb2["best"] == rb["best"]
+    import json
+    keys = json.load(open(tmp_path / "tune.json"))
+    arch = tune.arch(dev)
+    assert any(k.startswith("k_bquad|waves|%d|%s|" % (present[0], arch)) for k in keys)
 
 
 def test_batch_failed_iteration_leaves_recycling(smc, dev):
