@@ -23,6 +23,28 @@
 
 namespace smc {
 
+// Horner coefficients.  kSc: on the device each coefficient reaches its fma
+// through a scalar register pair (an empty asm statement with an SGPR
+// operand).  An FP64 vector instruction cannot carry a 64-bit immediate, and
+// left alone the compiler rebuilds every coefficient in vector registers with
+// two vector moves per use; as a scalar operand it costs two scalar moves,
+// which issue beside the vector work.  The value, and so every result, is the
+// same either way.  The choice is made per call site: the scalar registers it
+// takes are scarce in kernels that already hold many uniform values.
+template <bool kSc>
+__host__ __device__ inline double coef(double c)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (kSc) {
+        double r;
+        asm volatile("" : "=s"(r) : "0"(c));
+        return r;
+    }
+#endif
+    return c;
+}
+
+template <bool kSc = false>
 __host__ __device__ inline double det_exp(double x)
 {
     if (x != x) return x;
@@ -31,23 +53,24 @@ __host__ __device__ inline double det_exp(double x)
     const double kd = rint(x * 0x1.71547652b82fep+0);
     double r = fma(-kd, 0x1.62e42fee00000p-1, x);
     r = fma(-kd, 0x1.a39ef35793c76p-33, r);
-    double p = 0x1.6124613a86d09p-33;  // 1/13!
-    p = fma(p, r, 0x1.1eed8eff8d898p-29);  // 1/12!
-    p = fma(p, r, 0x1.ae64567f544e4p-26);  // 1/11!
-    p = fma(p, r, 0x1.27e4fb7789f5cp-22);  // 1/10!
-    p = fma(p, r, 0x1.71de3a556c734p-19);  // 1/9!
-    p = fma(p, r, 0x1.a01a01a01a01ap-16);  // 1/8!
-    p = fma(p, r, 0x1.a01a01a01a01ap-13);  // 1/7!
-    p = fma(p, r, 0x1.6c16c16c16c17p-10);  // 1/6!
-    p = fma(p, r, 0x1.1111111111111p-7);   // 1/5!
-    p = fma(p, r, 0x1.5555555555555p-5);   // 1/4!
-    p = fma(p, r, 0x1.5555555555555p-3);   // 1/3!
+    double p = coef<kSc>(0x1.6124613a86d09p-33);  // 1/13!
+    p = fma(p, r, coef<kSc>(0x1.1eed8eff8d898p-29));  // 1/12!
+    p = fma(p, r, coef<kSc>(0x1.ae64567f544e4p-26));  // 1/11!
+    p = fma(p, r, coef<kSc>(0x1.27e4fb7789f5cp-22));  // 1/10!
+    p = fma(p, r, coef<kSc>(0x1.71de3a556c734p-19));  // 1/9!
+    p = fma(p, r, coef<kSc>(0x1.a01a01a01a01ap-16));  // 1/8!
+    p = fma(p, r, coef<kSc>(0x1.a01a01a01a01ap-13));  // 1/7!
+    p = fma(p, r, coef<kSc>(0x1.6c16c16c16c17p-10));  // 1/6!
+    p = fma(p, r, coef<kSc>(0x1.1111111111111p-7));   // 1/5!
+    p = fma(p, r, coef<kSc>(0x1.5555555555555p-5));   // 1/4!
+    p = fma(p, r, coef<kSc>(0x1.5555555555555p-3));   // 1/3!
     p = fma(p, r, 0x1.0000000000000p-1);   // 1/2!
     p = fma(p, r, 1.0);                    // 1/1!
     p = fma(p, r, 1.0);                    // 1/0!
     return ldexp(p, (int)kd);
 }
 
+template <bool kSc = false>
 __host__ __device__ inline double det_log(double x)
 {
     if (!(x > 0.0)) return x == 0.0 ? -__builtin_huge_val() : __builtin_nan("");
@@ -60,17 +83,17 @@ __host__ __device__ inline double det_log(double x)
     }
     const double f = (m - 1.0) / (m + 1.0);
     const double s = f * f;
-    double p = 0x1.642c8590b2164p-4;   // 2/23
-    p = fma(p, s, 0x1.8618618618618p-4);  // 2/21
-    p = fma(p, s, 0x1.af286bca1af28p-4);  // 2/19
-    p = fma(p, s, 0x1.e1e1e1e1e1e1ep-4);  // 2/17
-    p = fma(p, s, 0x1.1111111111111p-3);  // 2/15
-    p = fma(p, s, 0x1.3b13b13b13b14p-3);  // 2/13
-    p = fma(p, s, 0x1.745d1745d1746p-3);  // 2/11
-    p = fma(p, s, 0x1.c71c71c71c71cp-3);  // 2/9
-    p = fma(p, s, 0x1.2492492492492p-2);  // 2/7
-    p = fma(p, s, 0x1.999999999999ap-2);  // 2/5
-    p = fma(p, s, 0x1.5555555555555p-1);  // 2/3
+    double p = coef<kSc>(0x1.642c8590b2164p-4);   // 2/23
+    p = fma(p, s, coef<kSc>(0x1.8618618618618p-4));  // 2/21
+    p = fma(p, s, coef<kSc>(0x1.af286bca1af28p-4));  // 2/19
+    p = fma(p, s, coef<kSc>(0x1.e1e1e1e1e1e1ep-4));  // 2/17
+    p = fma(p, s, coef<kSc>(0x1.1111111111111p-3));  // 2/15
+    p = fma(p, s, coef<kSc>(0x1.3b13b13b13b14p-3));  // 2/13
+    p = fma(p, s, coef<kSc>(0x1.745d1745d1746p-3));  // 2/11
+    p = fma(p, s, coef<kSc>(0x1.c71c71c71c71cp-3));  // 2/9
+    p = fma(p, s, coef<kSc>(0x1.2492492492492p-2));  // 2/7
+    p = fma(p, s, coef<kSc>(0x1.999999999999ap-2));  // 2/5
+    p = fma(p, s, coef<kSc>(0x1.5555555555555p-1));  // 2/3
     p = fma(p, s, 2.0);                   // 2/1
     const double lm = f * p;
     const double E = (double)e;
@@ -86,6 +109,7 @@ __host__ __device__ inline double det_sqrt(double v)
 #endif
 }
 
+template <bool kSc = false>
 __host__ __device__ inline double det_atan(double z)
 {
     if (z != z) return z;
@@ -96,18 +120,18 @@ __host__ __device__ inline double det_atan(double z)
     a = a / (1.0 + det_sqrt(fma(a, a, 1.0)));
     a = a / (1.0 + det_sqrt(fma(a, a, 1.0)));
     const double s = a * a;
-    double p = 0x1.47ae147ae147bp-5;      // 1/25
-    p = fma(p, -s, 0x1.642c8590b2164p-5);  // 1/23
-    p = fma(p, -s, 0x1.8618618618618p-5);  // 1/21
-    p = fma(p, -s, 0x1.af286bca1af28p-5);  // 1/19
-    p = fma(p, -s, 0x1.e1e1e1e1e1e1ep-5);  // 1/17
-    p = fma(p, -s, 0x1.1111111111111p-4);  // 1/15
-    p = fma(p, -s, 0x1.3b13b13b13b14p-4);  // 1/13
-    p = fma(p, -s, 0x1.745d1745d1746p-4);  // 1/11
-    p = fma(p, -s, 0x1.c71c71c71c71cp-4);  // 1/9
-    p = fma(p, -s, 0x1.2492492492492p-3);  // 1/7
-    p = fma(p, -s, 0x1.999999999999ap-3);  // 1/5
-    p = fma(p, -s, 0x1.5555555555555p-2);  // 1/3
+    double p = coef<kSc>(0x1.47ae147ae147bp-5);      // 1/25
+    p = fma(p, -s, coef<kSc>(0x1.642c8590b2164p-5));  // 1/23
+    p = fma(p, -s, coef<kSc>(0x1.8618618618618p-5));  // 1/21
+    p = fma(p, -s, coef<kSc>(0x1.af286bca1af28p-5));  // 1/19
+    p = fma(p, -s, coef<kSc>(0x1.e1e1e1e1e1e1ep-5));  // 1/17
+    p = fma(p, -s, coef<kSc>(0x1.1111111111111p-4));  // 1/15
+    p = fma(p, -s, coef<kSc>(0x1.3b13b13b13b14p-4));  // 1/13
+    p = fma(p, -s, coef<kSc>(0x1.745d1745d1746p-4));  // 1/11
+    p = fma(p, -s, coef<kSc>(0x1.c71c71c71c71cp-4));  // 1/9
+    p = fma(p, -s, coef<kSc>(0x1.2492492492492p-3));  // 1/7
+    p = fma(p, -s, coef<kSc>(0x1.999999999999ap-3));  // 1/5
+    p = fma(p, -s, coef<kSc>(0x1.5555555555555p-2));  // 1/3
     p = fma(p, -s, 1.0);                   // 1/1
     double r = 4.0 * (a * p);
     if (inv) r = (0x1.921fb54442d18p+0 - r) + 0x1.1a62633145c07p-54;

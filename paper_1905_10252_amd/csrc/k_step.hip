@@ -220,10 +220,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         double *xw = (kOut ? xo : x) + i * d;
         if (kKind == SMC_TARGET_BEARING) {
             double z[4];
-            normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, 0u, act, z[0], z[1],
-                             s_xch[tid >> 6]);
-            normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)i, 1u, act, z[2], z[3],
-                             s_xch[tid >> 6]);
+            // coefficients as scalar operands (coef()): 1.5 % faster here;
+            // no gain for the other targets, whose uniform values already
+            // fill the scalar registers
+            normal_pair_wave<true>(a.seed, tag, a.sampler, tt_, (uint32_t)i, 0u, act, z[0], z[1],
+                                   s_xch[tid >> 6]);
+            normal_pair_wave<true>(a.seed, tag, a.sampler, tt_, (uint32_t)i, 1u, act, z[2], z[3],
+                                   s_xch[tid >> 6]);
             if (!act) continue;
             double lw;
             if (kInit) {
@@ -243,7 +246,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 xw[1] = n1;
                 xw[2] = n2;
                 xw[3] = n3;
-                const double e = a.obs[t - 1] - det_atan(n2 / n0);
+                const double e = a.obs[t - 1] - det_atan<true>(n2 / n0);
                 lw = (uni ? a.reset : logw[i]) + (a.obs_log_norm - 0.5 * ((e * e) * a.obs_prec));
             }
             logw[i] = lw;

@@ -34,6 +34,8 @@ __device__ inline bool polar_uniforms(uint64_t seed, uint32_t tag, uint32_t samp
 
 // xch: this wave's 64-entry exchange buffer in LDS (16 bytes a lane).  Lanes
 // of one wave read and write it in program order, so no barrier is needed.
+// kSc: the logarithm's coefficients as scalar operands (see coef()).
+template <bool kSc = false>
 __device__ inline void normal_pair_wave(uint64_t seed, uint32_t tag, uint32_t sampler, uint32_t t,
                                         uint32_t idx, uint32_t pair, bool active, double &z1,
                                         double &z2, uint4 *xch)
@@ -83,7 +85,7 @@ __device__ inline void normal_pair_wave(uint64_t seed, uint32_t tag, uint32_t sa
     }
     if (ok) {
         const double s = v1 * v1 + v2 * v2;
-        const double c = (-2.0 * det_log(s)) / s;
+        const double c = (-2.0 * det_log<kSc>(s)) / s;
         const double f = det_sqrt(c);
         z1 = v1 * f;
         z2 = v2 * f;
