@@ -10,7 +10,9 @@
 //   k_bquad<DB> per chunk of samplers whose dimension falls in the bucket
 //               (DB - 8, DB]: |U (x - mean)|^2 with U staged in LDS and the row
 //               in registers, weight update, chunk max key and estimate sums
-//               against the chunk's max.  One launch per bucket.
+//               against the chunk's max.  One launch per bucket.  From
+//               DB = 24 up, k_bquad_mx: the same results with the product
+//               U (x - mean) on the FP64 matrix cores.
 //   k_bscan     per tile of 4096 particles of every sampler: the sampler's max
 //               from its chunk keys, 64-bit fixed-point weights, FP64 sums,
 //               the exact sum of squares, and the inclusive prefix by a
@@ -507,6 +509,223 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
     for (int c = tid; c < 1 + 2 * d; c += 256) {
         double a = s_col[0][c];
         for (int r = 1; r < 16; ++r) a += s_col[r][c];
+        cp[1 + c] = a;
+    }
+    if (tid == 0) {
+        cp[0] = mb;
+        BTileIS o;
+        o.key = bk;
+        o.bad = bb;
+        o.pad = 0;
+        S.tis[chunk] = o;
+    }
+}
+
+// The same update with the quadratic form on the FP64 matrix cores.  Every
+// wavefront takes its 64 particles in tiles of 16: Y = T U^T (T: the tile's
+// x - mean, 16 x DB) by v_mfma_f64_16x16x4f64 over k in steps of four, one
+// accumulator per block of 16 rows of U (blocks of U^T wholly below the
+// diagonal are skipped).  The instruction adds its four products to the
+// accumulator one fused multiply-add at a time, in k order (checked bit for
+// bit against a sequential fma chain on MI355X, subnormal products and zero
+// operands included), so row r of Y is the chain fma(U_rk, t_k, .) from +0
+// over k: the terms k < r leave it +0, and it equals the row-by-row form above
+// bit for bit.  Y goes through LDS to one lane per particle, which adds the
+// squares of its rows in row order.  A particle with a non-finite difference
+// (possible only with non-finite parameters, where a zero of U times inf gives
+// NaN instead of the row-by-row result) takes the row-by-row loop instead.
+// U's operands and the mean wait in LDS.  The estimate sums re-read the
+// chunk's rows (from cache) once the chunk's max is known, per lane over its
+// four particles, then across the 16 lanes of each row, then over the
+// wavefronts in order: the same sums as above within rounding.
+template <int DB>
+__host__ __device__ constexpr int mx_pair(int R, int c)
+{
+    int p = 0;
+    for (int q = 0; q < R; ++q) p += DB / 4 - 4 * q;
+    return p + c - 4 * R;
+}
+
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+template <int DB, bool kInit, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k_bquad_mx(
+    const BSlot *slots, const int *n_act, const int *bact, const int *bchunk_pref, int bucket,
+    int cap, int single)
+{
+    constexpr int NC = DB / 4;           // k steps of four coordinates
+    constexpr int NRB = (DB + 15) / 16;  // blocks of 16 rows of U
+    constexpr int NP = mx_pair<DB>(NRB, 4 * NRB);
+    static_assert(DB % 8 == 0 && NP > 0, "bucket width");
+    __shared__ double sU[NP][64];         // B operands, one per lane and step
+    __shared__ double sMean[DB];
+    __shared__ double sY[4][16][DB + 1];  // per wavefront: its tile's Y
+    __shared__ double s_q[kBChunk];
+    __shared__ double s_e[kBChunk];
+    __shared__ double s_col[4][1 + 2 * DB];  // one partial per wavefront
+    __shared__ u64 s_key[4];
+    __shared__ unsigned s_bad[4];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    int slot, chunk;
+    if (single >= 0) {
+        slot = single;
+        chunk = blockIdx.x;
+    } else if (!locate(bchunk_pref + bucket * (cap + 1), bact + bucket * cap, n_act[1 + bucket],
+                       blockIdx.x, slot, chunk)) {
+        return;
+    }
+    // a local copy: stores through the sampler's arrays cannot alias it
+    const BSlot S = slots[__builtin_amdgcn_readfirstlane(slot)];
+    const i64 n = S.n;
+    const int d = S.d;
+    const CST(double) *sM = (const CST(double) *)S.upad + DB * DB;
+    const GLB(double) *ug = glb(S.upad);
+    const i64 base = (i64)chunk * kBChunk;
+    const int cnt = (int)((n - base) < kBChunk ? (n - base) : kBChunk);
+    const bool alt = !kInit && S.ctrl->cur;
+    const GLB(double) *xb = glb(alt ? S.x_scr : S.x) + base * d;
+    const int p16 = lane & 15, g = lane >> 4;
+
+    // lane (g, p16) of step (R, c) multiplies U[16 R + p16][4 c + g]
+#pragma unroll
+    for (int R = 0; R < NRB; ++R)
+#pragma unroll
+        for (int c = 4 * R; c < NC; ++c)
+            if (mx_pair<DB>(R, c) % 4 == wid) {
+                const int r = 16 * R + p16;
+                sU[mx_pair<DB>(R, c)][lane] = r < DB ? ug[r * DB + 4 * c + g] : 0.0;
+            }
+    for (int k = tid; k < DB; k += 256) sMean[k] = k < d ? sM[k] : 0.0;
+    __syncthreads();
+
+#pragma unroll 1
+    for (int tile = 0; tile < 4; ++tile) {
+        if (wid * 64 + tile * 16 >= cnt) break;  // past the chunk's last particle
+        const int pl = wid * 64 + tile * 16 + p16;
+        const bool pact = pl < cnt;
+        const int plc = pact ? pl : 0;
+        // every load of the tile is issued before the first is used (the
+        // empty asm keeps the compiler from sinking each load into its use)
+        double xv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xv[c] = xb[(i64)plc * d + (4 * c + g < d ? 4 * c + g : d - 1)];
+        asm volatile("" ::: "memory");
+        f64x4_t acc[NRB];
+#pragma unroll
+        for (int R = 0; R < NRB; ++R) acc[R] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+        bool nf = false;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int k = 4 * c + g;
+            const double t = (pact && k < d) ? xv[c] - sMean[k] : 0.0;
+            nf |= !__builtin_isfinite(t);
+#pragma unroll
+            for (int R = 0; R < NRB; ++R)
+                if (4 * R <= c)
+                    acc[R] = __builtin_amdgcn_mfma_f64_16x16x4f64(t, sU[mx_pair<DB>(R, c)][lane],
+                                                                  acc[R], 0, 0, 0);
+        }
+        const u64 nfm = __ballot(nf);
+        // element v of lane (g, p16) in block R is Y[4 v + g][16 R + p16]
+#pragma unroll
+        for (int R = 0; R < NRB; ++R)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (16 * R + p16 < DB) sY[wid][4 * v + g][16 * R + p16] = acc[R][v];
+        __builtin_amdgcn_wave_barrier();
+        if (lane < 16) {
+            const int pt = wid * 64 + tile * 16 + lane;
+            double q = 0.0;
+            if (((nfm >> lane) & 0x0001000100010001ull) && pt < cnt) {
+                const GLB(double) *xr = xb + (i64)pt * d;
+                for (int r = 0; r < d; ++r) {
+                    double sr = 0.0;
+                    for (int k = r; k < d; ++k) sr = fma(ug[r * DB + k], xr[k] - sMean[k], sr);
+                    q = fma(sr, sr, q);
+                }
+            } else {
+                for (int r = 0; r < d; ++r) {
+                    const double y = sY[wid][lane][r];
+                    q = fma(y, y, q);
+                }
+            }
+            s_q[pt] = q;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    const i64 i = base + tid;
+    const bool act = tid < cnt;
+    GLB(double) *lpg = glb(alt ? S.lp_scr : S.lp);
+    GLB(double) *lwg = glb(S.logw);
+    double lw = -__builtin_huge_val();
+    if (act) {
+        const double lpn = S.log_norm - 0.5 * s_q[tid];
+        lw = kInit ? lpn - (S.init_log_norm - 0.5 * glb(S.lp_scr)[i]) : lwg[i] + (lpn - lpg[i]);
+        lpg[i] = lpn;
+        lwg[i] = lw;
+    }
+    const unsigned bad = wave_or((lw != lw) | (lw == __builtin_huge_val()));
+    const u64 key = wave_max_u64(act ? okey(lw) : 0ull);
+    if (lane == 0) {
+        s_key[wid] = key;
+        s_bad[wid] = bad;
+    }
+    __syncthreads();
+    u64 bk = s_key[0];
+    unsigned bb = s_bad[0];
+    for (int w = 1; w < 4; ++w) {
+        bk = s_key[w] > bk ? s_key[w] : bk;
+        bb |= s_bad[w];
+    }
+    const double mb = okey_inv(bk);
+    const bool live = act && mb > -__builtin_huge_val();
+    s_e[tid] = live ? det_exp(lw - mb) : 0.0;
+    __syncthreads();
+
+    // estimate sums: lane (g, p16) takes coordinates 4 c + g of particles
+    // wid * 64 + 16 tile + p16, then the 16 lanes of each row are added up
+    double s1[NC], s2[NC], s0 = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s1[c] = s2[c] = 0.0;
+#pragma unroll 1
+    for (int tile = 0; tile < 4; ++tile) {
+        if (wid * 64 + tile * 16 >= cnt) break;
+        const int pl = wid * 64 + tile * 16 + p16;
+        const bool pact = pl < cnt;
+        const int plc = pact ? pl : 0;
+        const double e = s_e[pl];
+        s0 += e;
+        double xv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xv[c] = xb[(i64)plc * d + (4 * c + g < d ? 4 * c + g : d - 1)];
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int k = 4 * c + g;
+            const double xk = (pact && k < d) ? xv[c] : 0.0;
+            const double ex = e * xk;
+            s1[c] += ex;
+            s2[c] += ex * xk;
+        }
+    }
+    s0 = row16_sum(s0);
+    if (lane == 15) s_col[wid][0] = s0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const double v1 = row16_sum(s1[c]), v2 = row16_sum(s2[c]);
+        const int k = 4 * c + g;
+        if (p16 == 15 && k < d) {
+            s_col[wid][1 + k] = v1;
+            s_col[wid][1 + d + k] = v2;
+        }
+    }
+    __syncthreads();
+    double *cp = S.cpart + (i64)chunk * (2 + 2 * d);
+    for (int c = tid; c < 1 + 2 * d; c += 256) {
+        double a = s_col[0][c];
+        for (int w = 1; w < 4; ++w) a += s_col[w][c];
         cp[1 + c] = a;
     }
     if (tid == 0) {
@@ -1054,9 +1273,18 @@ hipError_t launch_tables(smc_batch *b, hipStream_t s)
     return hipGetLastError();
 }
 
+#ifndef SMC_QUAD_MX_MIN
+#define SMC_QUAD_MX_MIN 24
+#endif
+// Buckets from this width up take the matrix-core form of the update.
+constexpr int kQuadMxMin = SMC_QUAD_MX_MIN;
+
 // Highest occupancy aim the kernel of bucket width DB can meet (LDS and
 // registers of the wider rows); larger requests are clamped to it.
-constexpr int max_quad_waves(int DB) { return DB <= 16 ? 4 : (DB <= 40 ? 3 : 2); }
+constexpr int max_quad_waves(int DB)
+{
+    return DB >= kQuadMxMin ? (DB <= 32 ? 3 : 2) : (DB <= 16 ? 4 : (DB <= 40 ? 3 : 2));
+}
 
 template <int DB, bool kInit>
 void launch_quad_waves(int w, dim3 g, hipStream_t s, const smc_batch *b, int q, int single)
@@ -1067,9 +1295,14 @@ void launch_quad_waves(int w, dim3 g, hipStream_t s, const smc_batch *b, int q, 
     switch (w) {
 #define SMC_BQW_CASE(W)                                                                        \
     case W:                                                                                    \
-        if constexpr (W <= max_quad_waves(DB))                                                 \
-            hipLaunchKernelGGL((k_bquad<DB, kInit, W>), g, dim3(256), 0, s, sl, t.n_act,       \
-                               t.bact, t.btile_pref, q, b->cap, single);                       \
+        if constexpr (W <= max_quad_waves(DB)) {                                               \
+            if constexpr (DB >= kQuadMxMin)                                                    \
+                hipLaunchKernelGGL((k_bquad_mx<DB, kInit, W>), g, dim3(256), 0, s, sl,         \
+                                   t.n_act, t.bact, t.btile_pref, q, b->cap, single);          \
+            else                                                                               \
+                hipLaunchKernelGGL((k_bquad<DB, kInit, W>), g, dim3(256), 0, s, sl, t.n_act,   \
+                                   t.bact, t.btile_pref, q, b->cap, single);                   \
+        }                                                                                      \
         break;
         SMC_BQW_CASE(1) SMC_BQW_CASE(2) SMC_BQW_CASE(3) SMC_BQW_CASE(4)
 #undef SMC_BQW_CASE
