@@ -14,6 +14,41 @@ import torch
 from . import _lib as L
 
 
+# Normalising constants of the targets (log of the constant factor of each
+# density), the defaults of Sampler and Batch.attach; a caller may pass its own.
+def q0_log_norm(d: int, init_sd: float) -> float:
+    """log of (2 pi init_sd^2)^(-d/2): x0 ~ N(init_mean, init_sd^2 I)."""
+    return -0.5 * d * math.log(2.0 * math.pi * init_sd * init_sd)
+
+
+def gauss_log_norm(var) -> float:
+    """Diagonal Gaussian with variances `var`: -(d log 2 pi + sum log var) / 2."""
+    v = [float(a) for a in torch.as_tensor(var, dtype=torch.float64).reshape(-1)]
+    return -0.5 * (len(v) * math.log(2.0 * math.pi) + sum(math.log(a) for a in v))
+
+
+def student_log_norm(nu: float) -> float:
+    """Student-t with nu degrees of freedom, unit scale."""
+    return math.lgamma(0.5 * (nu + 1.0)) - math.lgamma(0.5 * nu) - 0.5 * math.log(nu * math.pi)
+
+
+def logreg_log_norm(d: int, prior_var: float) -> float:
+    """The logistic regression's N(0, prior_var I) prior on the d weights."""
+    return -0.5 * d * math.log(2.0 * math.pi * prior_var)
+
+
+def bearing_obs_log_norm(obs_var: float) -> float:
+    """The bearing-only model's N(0, obs_var) observation noise."""
+    return -0.5 * math.log(2.0 * math.pi * obs_var)
+
+
+def chol_log_norm(U) -> float:
+    """Gaussian with precision U^T U (U upper triangular): -(d/2) log 2 pi + sum log U_ii."""
+    Ut = torch.as_tensor(U, dtype=torch.float64)
+    d = Ut.shape[0]
+    return -0.5 * d * math.log(2.0 * math.pi) + float(torch.log(torch.diagonal(Ut)).sum())
+
+
 def _stream():
     # torch's current HIP stream; the raw getter skips building a Stream
     # object (about 0.3 instead of 4 us a call)
@@ -214,7 +249,7 @@ class Sampler:
         cfg.sampler_id, cfg.seed = sampler_id, int(seed) & (2**64 - 1)
         cfg.rw_sd, cfg.init_mean, cfg.init_sd = rw_sd, init_mean, init_sd
         cfg.init_log_norm = (init_log_norm if init_log_norm is not None
-                             else -0.5 * d * math.log(2.0 * math.pi * init_sd * init_sd))
+                             else q0_log_norm(d, init_sd))
         self._keep = []
         if target == "gauss":
             cfg.target = L.TARGET_GAUSS
@@ -223,15 +258,11 @@ class Sampler:
             pr = (1.0 / v).to(dev)
             self._keep += [m, pr]
             cfg.mean, cfg.prec = m.data_ptr(), pr.data_ptr()
-            cfg.log_norm = (log_norm if log_norm is not None else
-                            float(-0.5 * (v.numel() * math.log(2.0 * math.pi)
-                                          + sum(math.log(float(a)) for a in v))))
+            cfg.log_norm = log_norm if log_norm is not None else gauss_log_norm(v)
         elif target == "student":
             cfg.target = L.TARGET_STUDENT
             cfg.nu, cfg.mu = nu, mu
-            cfg.log_norm = (log_norm if log_norm is not None else
-                            math.lgamma(0.5 * (nu + 1.0)) - math.lgamma(0.5 * nu)
-                            - 0.5 * math.log(nu * math.pi))
+            cfg.log_norm = log_norm if log_norm is not None else student_log_norm(nu)
         elif target == "logreg":
             cfg.target = L.TARGET_LOGREG
             Xd = torch.as_tensor(X, dtype=torch.float64).contiguous().to(dev)
@@ -240,8 +271,7 @@ class Sampler:
             cfg.m_rows, cfg.X, cfg.y = Xd.shape[0], Xd.data_ptr(), yd.data_ptr()
             cfg.prior_prec = 1.0 / prior_var
             cfg.loglik_precision = L.PREC_BF16 if precision == "bf16" else L.PREC_F64
-            cfg.log_norm = (log_norm if log_norm is not None
-                            else -0.5 * d * math.log(2.0 * math.pi * prior_var))
+            cfg.log_norm = log_norm if log_norm is not None else logreg_log_norm(d, prior_var)
         elif target == "bearing":
             # SIR particle filter (Alg 1): mean = X0 mean [4], obs = bearings
             if d != 4:
@@ -253,7 +283,7 @@ class Sampler:
             cfg.mean, cfg.obs, cfg.n_obs = m.data_ptr(), ob.data_ptr(), ob.numel()
             cfg.delta, cfg.obs_var = delta, obs_var
             cfg.obs_log_norm = (log_norm if log_norm is not None
-                                else -0.5 * math.log(2.0 * math.pi * obs_var))
+                                else bearing_obs_log_norm(obs_var))
         else:
             raise ValueError("unknown target %r" % target)
         self.cfg = cfg
@@ -389,10 +419,8 @@ class Batch:
         desc.sampler_id, desc.seed = sampler_id, int(seed) & (2**64 - 1)
         desc.rw_sd, desc.init_mean, desc.init_sd = rw_sd, init_mean, init_sd
         desc.init_log_norm = (init_log_norm if init_log_norm is not None
-                              else -0.5 * d * math.log(2.0 * math.pi * init_sd * init_sd))
-        desc.log_norm = (log_norm if log_norm is not None else
-                         -0.5 * d * math.log(2.0 * math.pi)
-                         + float(torch.log(torch.diagonal(U)).sum()))
+                              else q0_log_norm(d, init_sd))
+        desc.log_norm = log_norm if log_norm is not None else chol_log_norm(U)
         md, Ud = m.to(dev), U.to(dev)
         x = torch.empty((n, d), dtype=torch.float64, device=dev)
         logw = torch.empty(n, dtype=torch.float64, device=dev)
