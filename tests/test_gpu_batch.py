@@ -307,3 +307,41 @@ def test_batch_failed_iteration_leaves_recycling(smc, dev):
         for k in range(2):
             check_step(B, k, os_[k], os_[k].step(), "after t=%d slot %d" % (t, k))
     assert B.sync_error(0) == 0 and B.sync_error(1) == 0
+
+
+def test_batch_infinite_coordinate_matches_row_by_row(smc, dev):
+    """A particle with one infinite coordinate: the oracle's row-by-row
+    quadratic form makes every row through that coordinate infinite, so
+    log pi = -inf and the particle's weight is zero.  The matrix-core form
+    (d = 40 here) multiplies the zeros of U below the diagonal by that
+    coordinate too, which would give NaN; such a particle must take the
+    row-by-row path and match the oracle bit for bit (d = 12: the vector
+    kernel).  Resampling is forced, so the particle is dropped after the
+    step and the next step runs on finite rows again."""
+    import torch
+    print("batch infinite coordinate", flush=True)
+    B = smc.Batch(2, graph=False, device=dev)
+    specs = [spec(0, 3000, 40, O.MODE_FORCE), spec(1, 3000, 12, O.MODE_FORCE)]
+    for slot, sp in enumerate(specs):
+        attach(B, slot, sp)
+    orcs = [oracle_of(B, slot, sp) for slot, sp in enumerate(specs)]
+    rows = [5, 700, 1601, 2999]
+    for slot, sp in enumerate(specs):
+        xg = B.x(slot)
+        for j, r in enumerate(rows):
+            k = (7 * j + 3) % sp["d"]
+            v = math.inf if j % 2 == 0 else -math.inf
+            xg[r, k] = v
+            orcs[slot].x[r, k] = v
+    torch.cuda.synchronize()
+    B.step()
+    for slot in range(2):
+        orcs[slot].step()
+        x = B.x(slot).cpu().numpy()  # the rows with an infinite coordinate were dropped
+        assert np.all(np.isfinite(x)), slot
+        check_state(B, slot, orcs[slot], ("inf coordinate", slot))
+        assert B.info(slot)["err"] == 0
+    B.step()
+    for slot in range(2):
+        orcs[slot].step()
+        check_state(B, slot, orcs[slot], ("after", slot))
