@@ -56,6 +56,7 @@ constexpr int kMaxGroup = 8;           // coordinate pairs of a proposal unit (1
 constexpr int kBSpin = 1 << 22;        // lookback poll bound
 constexpr int kBuckets = 8;            // dimension buckets (8b, 8b + 8]
 constexpr int kBMaxCap = 4096;
+constexpr int kBStage = 2048;          // prefix values of one expand chunk staged in LDS
 constexpr int64_t kBMaxN = 1ll << 28;
 
 // The per-sampler arrays are reached through pointers read from the slot
@@ -1087,14 +1088,50 @@ __global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *
     const double *xs = alt ? S.x_scr : S.x, *lps = alt ? S.lp_scr : S.lp;
     double *xd = alt ? S.x : S.x_scr, *lpd = alt ? S.lp : S.lp_scr;
     const i64 p = (i64)ch * kBChunk + tid;
-    // anc(p) = first j with N S_j + U >= (p + 1) S (it exists: j = n - 1)
-    i64 lo = 0, hi = n - 1;
+    // anc(p) = first j with N S_j + U >= (p + 1) S (it exists: j = n - 1).
+    // The chunk's outputs have non-decreasing ancestors in [a0, a1]: two
+    // wavefronts find those ends by rounds of 64 probes, the prefix values in
+    // between are staged into LDS when they fit, and every output searches
+    // its ancestor there (in global memory, within [a0, a1], when they do not)
+    __shared__ u64 s_pref[kBStage];
+    __shared__ i64 s_a[2];
+    const GLB(u64) *pg = glb(S.pref);
+    if (wid < 2) {
+        const i64 pe = wid == 0 ? (i64)ch * kBChunk
+                                : ((i64)ch * kBChunk + kBChunk < n ? (i64)ch * kBChunk + kBChunk : n) - 1;
+        const U128 rhs = mul64((u64)(pe + 1), Ssum);
+        i64 lo = 0, hi = n;  // first index in [lo, hi) where the test fails
+        while (hi > lo) {
+            const i64 len = hi - lo;
+            const i64 stride = (len + 63) / 64;
+            const i64 pos = lo + (i64)lane * stride;
+            const bool t = pos < hi ? lt128(add128(mul64((u64)n, pg[pos]), U), rhs) : false;
+            const int cnt = __popcll(__ballot(t));
+            if (cnt == 0) {
+                hi = lo;
+                break;
+            }
+            const i64 nlo = lo + (i64)(cnt - 1) * stride + 1;
+            i64 nhi = lo + (i64)cnt * stride;
+            if (nhi > hi) nhi = hi;
+            lo = nlo;
+            hi = nhi;
+        }
+        if (lane == 0) s_a[wid] = lo < n ? lo : n - 1;
+    }
+    __syncthreads();
+    const i64 a0 = s_a[0], a1 = s_a[1];
+    const bool staged = a1 - a0 + 1 <= kBStage;
+    if (staged)
+        for (i64 k = tid; k <= a1 - a0; k += 256) s_pref[k] = pg[a0 + k];
+    __syncthreads();
+    i64 lo = a0, hi = a1;
     if (p < n) {
         const U128 rhs = mul64((u64)(p + 1), Ssum);
-        const GLB(u64) *pg = glb(S.pref);
         while (lo < hi) {
             const i64 mid = (lo + hi) >> 1;
-            if (lt128(add128(mul64((u64)n, pg[mid]), U), rhs)) lo = mid + 1;
+            const u64 pm = staged ? s_pref[mid - a0] : pg[mid];
+            if (lt128(add128(mul64((u64)n, pm), U), rhs)) lo = mid + 1;
             else hi = mid;
         }
         glb(lpd)[p] = glb(lps)[lo];
