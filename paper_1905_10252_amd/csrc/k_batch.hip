@@ -1137,35 +1137,41 @@ __global__ __launch_bounds__(256) void k_bexpand(const BSlot *slots, const int *
         glb(lpd)[p] = glb(lps)[lo];
         glb(S.logw)[p] = S.reset;
     }
-    const i64 anc = lo;
-    int dp2 = 1;
-    while (dp2 < d) dp2 <<= 1;
-    const int R = 64 / dp2;
-    const int col = lane & (dp2 - 1), rsub = lane / dp2;
-    const i64 pw = (i64)ch * kBChunk + wid * 64;
-    // a wave copies its 64 rows R at a time; UB such steps' loads are issued
-    // before the first wait (addresses clamped into the array, so no branch)
+    // the chunk's new rows are contiguous: they are copied as one flat array
+    // of cnt * d values, 256 consecutive values per step of the workgroup,
+    // value e being column e mod d of output row e / d (quotient from an
+    // FP32 reciprocal, corrected by one: e < 2^14); UB steps' loads are
+    // issued before the first wait (indices clamped, so no branch)
+    __shared__ i64 s_anc[kBChunk];
+    s_anc[tid] = lo;
+    __syncthreads();
+    const int cnt = (int)(n - (i64)ch * kBChunk < kBChunk ? n - (i64)ch * kBChunk : kBChunk);
+    const int nel = cnt * d;
+    const i64 dst0 = (i64)ch * kBChunk * d;
+    const float inv_d = 1.0f / (float)d;
     constexpr int UB = 8;
-    const int cc = col < d ? col : d - 1;
-    for (int o0 = 0; o0 < 64; o0 += R * UB) {
+    for (int e0 = 0; e0 < nel; e0 += 256 * UB) {
         double v[UB];
-        i64 dst[UB];
-        bool ok[UB];
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
-            const int o = o0 + u * R + rsub;
-            const int oc = o < 64 ? o : 63;
-            const int lo32 = __shfl((int)(anc & 0xffffffff), oc, kWave);
-            const int hi32 = __shfl((int)(anc >> 32), oc, kWave);
-            const i64 src = ((i64)hi32 << 32) | (i64)(unsigned)lo32;
-            const i64 pp = pw + o;
-            ok[u] = o < 64 && col < d && pp < n;
-            dst[u] = pp * d + col;
-            v[u] = glb(xs)[src * d + cc];
+            const int e = e0 + u * 256 + tid;
+            const int ec = e < nel ? e : nel - 1;
+            int o = (int)((float)ec * inv_d);
+            int col = ec - o * d;
+            if (col < 0) {
+                --o;
+                col += d;
+            } else if (col >= d) {
+                ++o;
+                col -= d;
+            }
+            v[u] = glb(xs)[s_anc[o] * d + col];
         }
 #pragma unroll
-        for (int u = 0; u < UB; ++u)
-            if (ok[u]) glb(xd)[dst[u]] = v[u];
+        for (int u = 0; u < UB; ++u) {
+            const int e = e0 + u * 256 + tid;
+            if (e < nel) glb(xd)[dst0 + e] = v[u];
+        }
     }
 }
 
