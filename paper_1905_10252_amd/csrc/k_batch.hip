@@ -1316,11 +1316,9 @@ hipError_t launch_tables(smc_batch *b, hipStream_t s)
     return hipGetLastError();
 }
 
-#ifndef SMC_QUAD_MX_MIN
-#define SMC_QUAD_MX_MIN 24
-#endif
-// Buckets from this width up take the matrix-core form of the update.
-constexpr int kQuadMxMin = SMC_QUAD_MX_MIN;
+// Buckets from this width up take the matrix-core form of the update (below
+// it the vector form measured as fast: a 16-row block is mostly padding).
+constexpr int kQuadMxMin = 24;
 
 // Highest occupancy aim the kernel of bucket width DB can meet (LDS and
 // registers of the wider rows); larger requests are clamped to it.
