@@ -111,9 +111,14 @@ __device__ inline void is_block_finish(i64 n, int d, const double *x, const doub
 }
 
 // One-pass variant for small d (the row stays in registers): each thread keeps
-// a running reference max and rescales its sums when the max grows, so the
-// rows are read once; blocks combine the thread references with exact
-// power-free rescaling by det_exp.
+// a reference and sums e = exp(l - ref), so the rows are read once; blocks
+// combine the thread references by det_exp rescaling.  The reference is the
+// first finite weight and moves (rescaling the sums) only when a weight exceeds
+// it by more than kOnlineSlack nats: terms stay below e^64, far from FP64
+// overflow, and a lane no longer pays a second exponential at every new
+// maximum, which in a wave of 64 lanes happened on most iterations.
+constexpr double kOnlineSlack = 64.0;
+
 template <int DT>
 struct Online {
     double m, e0, e1[DT], e2[DT];
@@ -126,7 +131,7 @@ struct Online {
     __device__ void add(double lw, const double *xv)
     {
         if (!(lw > -__builtin_huge_val())) return;  // zero weight, or NaN (flagged elsewhere)
-        if (lw > m) {
+        if (lw > m + kOnlineSlack) {
             if (m > -__builtin_huge_val()) {
                 const double sc = det_exp(m - lw);
                 e0 *= sc;
