@@ -460,6 +460,25 @@ def test_gauss_4d_multi_kernel_path(smc, dev, mode):
     run_and_compare(G, Or, 6)
 
 
+@pytest.mark.parametrize("d,mode", [(1, "never"), (4, "never"), (1, "auto")])
+def test_estimate_reference_over_wide_weight_spread(smc, dev, d, mode):
+    """Log-weights spread over 400 nats at N = 2^20 + 3: the update kernel runs
+    one full residency, so each thread folds several particles into its one-pass
+    estimate sums and meets weights far above (the reference moves, the sums
+    are rescaled) and far below its reference (terms underflow harmlessly).
+    Trajectories bit for bit, estimates within the FP64-sum tolerance."""
+    import torch
+    _say("estimate reference d=%d %s" % (d, mode))
+    n = (1 << 20) + 3
+    rng = np.random.default_rng(5 + d)
+    G, Or = pair_gauss(smc, dev, n, rng.standard_normal(d), rng.uniform(0.5, 2.0, d), 31,
+                       MODES[mode], rw_sd=0.3)
+    lw = rng.uniform(-400.0, 0.0, n)
+    G.logw.copy_(torch.from_numpy(lw).to(dev))
+    Or.logw[:] = lw
+    run_and_compare(G, Or, 2)
+
+
 @pytest.mark.parametrize("kind,n,d", [("gauss", 3001, 3), ("gauss", 1024, 1),
                                       ("student", 70001, 1)])
 def test_failed_iteration_leaves_recycling(smc, dev, kind, n, d):
