@@ -114,8 +114,8 @@ smc_status smc_batch_set_group(smc_batch *b, int32_t pairs, void *stream);
  * weight update of eq. smcs_drawing_weights for samplers whose dimension
  * falls in bucket `bucket`, i.e. d in (8 bucket, 8 bucket + 8]) is compiled to
  * aim at: `waves` wavefronts per SIMD, 1 <= waves <= 4, bucket 0..7, clamped
- * to what the bucket's kernel can reach (4 for d <= 16, 3 for d <= 32, 2
- * above), which is also the default.  Fewer waves leave more registers per
+ * to what the bucket's kernel can reach (4 for d <= 40, 3 above), which is
+ * also the default.  Fewer waves leave more registers per
  * thread for the longer rows.  A tuning knob: results do not depend on it. */
 smc_status smc_batch_set_bucket_waves(smc_batch *b, int32_t bucket, int32_t waves);
 

@@ -523,18 +523,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
 }
 
 // The same update with the quadratic form on the FP64 matrix cores.  Every
-// wavefront takes its 64 particles in tiles of 16: Y = T U^T (T: the tile's
+// wavefront takes its 64 particles in tiles of 16: Y^T = U T^T (T: the tile's
 // x - mean, 16 x DB) by v_mfma_f64_16x16x4f64 over k in steps of four, one
-// accumulator per block of 16 rows of U (blocks of U^T wholly below the
+// accumulator per block of 16 rows of U (blocks of U wholly below the
 // diagonal are skipped).  The instruction adds its four products to the
 // accumulator one fused multiply-add at a time, in k order (checked bit for
 // bit against a sequential fma chain on MI355X, subnormal products and zero
 // operands included), so row r of Y is the chain fma(U_rk, t_k, .) from +0
 // over k: the terms k < r leave it +0, and it equals the row-by-row form above
-// bit for bit.  Y goes through LDS to one lane per particle, which adds the
-// squares of its rows in row order.  A particle with a non-finite difference
-// (possible only with non-finite parameters, where a zero of U times inf gives
-// NaN instead of the row-by-row result) takes the row-by-row loop instead.
+// bit for bit.  The accumulators then hold Y in exactly the operand layout of
+// the same instruction (lane (g, p16), element v of block R: Y of particle
+// p16, row 16 R + 4 v + g), so Y Y^T over the row blocks and elements in
+// order is, on its diagonal, the chain fma(y_r, y_r, .) from +0 over r in row
+// order: the sum of squares of the row-by-row form, bit for bit (rows past d
+// are +0 and add nothing).  No LDS holds Y, which leaves the LDS footprint
+// small enough that registers alone set the occupancy.  A particle with a
+// non-finite difference (possible only with non-finite parameters, where a
+// zero of U times inf gives NaN instead of the row-by-row result) takes the
+// row-by-row loop instead.
 // U's operands and the mean wait in LDS.  The estimate sums re-read the
 // chunk's rows (from cache) once the chunk's max is known, per lane over its
 // four particles, then across the 16 lanes of each row, then over the
@@ -560,7 +566,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
     static_assert(DB % 8 == 0 && NP > 0, "bucket width");
     __shared__ double sU[NP][64];         // B operands, one per lane and step
     __shared__ double sMean[DB];
-    __shared__ double sY[4][16][DB + 1];  // per wavefront: its tile's Y
     __shared__ double s_q[kBChunk];
     __shared__ double s_e[kBChunk];
     __shared__ double s_col[4][1 + 2 * DB];  // one partial per wavefront
@@ -623,36 +628,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
 #pragma unroll
             for (int R = 0; R < NRB; ++R)
                 if (4 * R <= c)
-                    acc[R] = __builtin_amdgcn_mfma_f64_16x16x4f64(t, sU[mx_pair<DB>(R, c)][lane],
+                    acc[R] = __builtin_amdgcn_mfma_f64_16x16x4f64(sU[mx_pair<DB>(R, c)][lane], t,
                                                                   acc[R], 0, 0, 0);
         }
         const u64 nfm = __ballot(nf);
-        // element v of lane (g, p16) in block R is Y[4 v + g][16 R + p16]
+        // element v of lane (g, p16) in block R is Y[p16][16 R + 4 v + g]
+        f64x4_t q2 = f64x4_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int R = 0; R < NRB; ++R)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                if (16 * R + p16 < DB) sY[wid][4 * v + g][16 * R + p16] = acc[R][v];
-        __builtin_amdgcn_wave_barrier();
-        if (lane < 16) {
-            const int pt = wid * 64 + tile * 16 + lane;
-            double q = 0.0;
-            if (((nfm >> lane) & 0x0001000100010001ull) && pt < cnt) {
+                q2 = __builtin_amdgcn_mfma_f64_16x16x4f64(acc[R][v], acc[R][v], q2, 0, 0, 0);
+        if ((p16 & 3) == g) {
+            const int pt = wid * 64 + tile * 16 + p16;
+            const int vq = p16 >> 2;
+            double q = vq == 0 ? q2[0] : (vq == 1 ? q2[1] : (vq == 2 ? q2[2] : q2[3]));
+            if (((nfm >> p16) & 0x0001000100010001ull) && pt < cnt) {
+                q = 0.0;
                 const GLB(double) *xr = xb + (i64)pt * d;
                 for (int r = 0; r < d; ++r) {
                     double sr = 0.0;
                     for (int k = r; k < d; ++k) sr = fma(ug[r * DB + k], xr[k] - sMean[k], sr);
                     q = fma(sr, sr, q);
                 }
-            } else {
-                for (int r = 0; r < d; ++r) {
-                    const double y = sY[wid][lane][r];
-                    q = fma(y, y, q);
-                }
             }
-            s_q[pt] = q;
+            if (pt < cnt) s_q[pt] = q;
         }
-        __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
 
@@ -1321,10 +1322,11 @@ hipError_t launch_tables(smc_batch *b, hipStream_t s)
 constexpr int kQuadMxMin = 24;
 
 // Highest occupancy aim the kernel of bucket width DB can meet (LDS and
-// registers of the wider rows); larger requests are clamped to it.
+// registers of the wider rows; the matrix-core kernel needs 166 VGPRs at
+// width 64, 150 at 56, 122 at 48); larger requests are clamped to it.
 constexpr int max_quad_waves(int DB)
 {
-    return DB >= kQuadMxMin ? (DB <= 32 ? 3 : 2) : (DB <= 16 ? 4 : (DB <= 40 ? 3 : 2));
+    return DB >= kQuadMxMin ? (DB <= 40 ? 4 : 3) : (DB <= 16 ? 4 : (DB <= 40 ? 3 : 2));
 }
 
 template <int DB, bool kInit>

@@ -32,7 +32,7 @@ BUCKETS = 8
 
 def _max_waves(bucket: int) -> int:
     d = 8 * (bucket + 1)
-    return 4 if d <= 16 else (3 if d <= 32 else 2)
+    return 4 if d <= 40 else 3
 
 
 def cache_path() -> str:

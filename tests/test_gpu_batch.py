@@ -232,7 +232,7 @@ def test_batch_bucket_waves_do_not_change_results(smc, dev):
     print("batch bucket waves", flush=True)
     specs = [spec(120 + k, *m) for k, m in enumerate(MIX)]
     outs = []
-    for waves in (None, 1, 2):
+    for waves in (None, 1, 2, 3):
         B = smc.Batch(len(MIX), device=dev)
         if waves is not None:
             for q in range(8):
