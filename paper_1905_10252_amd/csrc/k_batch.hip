@@ -149,7 +149,8 @@ __device__ inline double row16_sum(double v)
 // thread is issued before the first wait (its address is clamped into the
 // block, so the loads need no branch); a loop that waits for each load in
 // turn spends most of a wave's life on memory latency.
-__device__ inline void stage_rows(double (*sx)[17], const GLB(double) *xb, int d, int cnt, int w)
+template <int CW>
+__device__ inline void stage_rows(double (*sx)[CW], const GLB(double) *xb, int d, int cnt, int w)
 {
     const int tid = threadIdx.x, lc = tid & 15, lr = tid >> 4;
     const int cc = lc < w ? lc : w - 1;
@@ -282,7 +283,8 @@ __global__ __launch_bounds__(256) void k_btables(const BSlot *slots, int cap, in
 // (or x0 ~ q0) in place; at initialisation also leaves the quadratic term of
 // log q0 in lp_scr.  Kept apart from the target so that its register use, and
 // with it the occupancy of the normal generation, does not depend on d.
-template <bool kInit>
+// CW: row stride of the step's LDS staging block, at least 2 G + 1 doubles.
+template <bool kInit, int CW = 17>
 __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_act,
                                                const int *act_list, const int *unit_pref, int G,
                                                int single)
@@ -320,7 +322,7 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
         // lines (16 lanes per row); each thread then updates its own row in
         // LDS.  Strided per-thread row accesses would touch 64 lines per
         // wave instruction.
-        __shared__ double sx[kBChunk][17];
+        __shared__ double sx[kBChunk][CW];
         const int k0 = 2 * kp0, w = (2 * kp1 < d ? 2 * kp1 : d) - k0;
         const i64 base = (i64)chunk * kBChunk;
         const int cnt = (int)((n - base) < kBChunk ? (n - base) : kBChunk);
@@ -1378,8 +1380,18 @@ hipError_t enqueue_step(smc_batch *b, smc_resample_info *info, double *est, hipS
 {
     const BSlot *sl = b->d_slots;
     const BTabs &t = b->tabs;
-    hipLaunchKernelGGL(k_bprop<false>, dim3((unsigned)b->total_units), dim3(256), 0, s, sl,
-                       t.n_act, t.act, t.unit_pref, b->G, -1);
+    // the staging block is sized for the unit (2 G columns, one of padding):
+    // at 5 or 6 pairs its LDS lets 6 or 5 workgroups share a CU instead of 4
+    // (and the kernel needs 73 or 81 VGPRs instead of 97)
+    if (b->G <= 5)
+        hipLaunchKernelGGL((k_bprop<false, 11>), dim3((unsigned)b->total_units), dim3(256), 0, s, sl,
+                           t.n_act, t.act, t.unit_pref, b->G, -1);
+    else if (b->G == 6)
+        hipLaunchKernelGGL((k_bprop<false, 13>), dim3((unsigned)b->total_units), dim3(256), 0, s, sl,
+                           t.n_act, t.act, t.unit_pref, b->G, -1);
+    else
+        hipLaunchKernelGGL((k_bprop<false, 17>), dim3((unsigned)b->total_units), dim3(256), 0, s, sl,
+                           t.n_act, t.act, t.unit_pref, b->G, -1);
     for (int q = 0; q < kBuckets; ++q)
         if (b->btiles[q] > 0) launch_quad_bucket<false>(q, dim3(b->btiles[q]), s, b, -1);
     hipLaunchKernelGGL(k_bscan, dim3(b->total_tiles), dim3(256), 0, s, sl, t.n_act, t.act,

@@ -26,7 +26,7 @@ import torch
 
 from . import smc
 
-GROUP_CANDIDATES = (2, 4, 8)
+GROUP_CANDIDATES = (2, 4, 5, 6, 8)
 BUCKETS = 8
 
 

@@ -210,7 +210,7 @@ def test_batch_unit_size_does_not_change_results(smc, dev):
     print("batch unit size", flush=True)
     specs = [spec(90 + k, *m) for k, m in enumerate(MIX)]
     outs = []
-    for g in (1, 3, 8):
+    for g in (1, 3, 6, 8):
         B = smc.Batch(len(MIX), device=dev)
         B.set_group(g)
         for slot, sp in enumerate(specs):
