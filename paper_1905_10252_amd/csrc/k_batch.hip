@@ -50,6 +50,11 @@ namespace {
 constexpr int kBT = 256;               // threads per workgroup
 constexpr int kBItems = 16;            // particles per thread and tile
 constexpr int kBTile = kBT * kBItems;  // particles per tile
+// LDS position of tile entry i: entries stay in their run of 16, rotated by
+// bits 5..8 of i, so that both the striped and the per-thread accesses of a
+// wave spread over the banks
+__host__ __device__ constexpr int kBPad(int i) { return (i & ~15) | ((i ^ (i >> 5)) & 15); }
+typedef double f64x2b_t __attribute__((ext_vector_type(2)));
 constexpr int kBChunk = 256;           // particles of an update / expand / copy workgroup
 constexpr int kChunksPerTile = kBTile / kBChunk;
 constexpr int kMaxGroup = 8;           // coordinate pairs of a proposal unit (16 columns of LDS)
@@ -791,6 +796,7 @@ __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_
     __shared__ unsigned s_b[4];
     __shared__ double s_z[4], s_z2[4];
     __shared__ u64 s_prefix;
+    __shared__ u64 s_t[kBTile];  // the tile's log-weights in, its prefix out
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     int slot, tile;
     if (!locate(tile_pref, act, n_act[0], blockIdx.x, slot, tile)) return;
@@ -846,10 +852,34 @@ __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_
     U128 q2{0, 0};
     u64 loc[kBItems];
     u64 run = 0;
+    // the tile's log-weights arrive by striped, coalesced loads and pass
+    // through LDS, so that every thread still takes 16 consecutive particles
+    // in order (the same sums as a direct per-thread read, which touched 64
+    // cache lines per wave instruction)
+    {
+        const GLB(double) *lwt = glb(S.logw) + base;
+        if (base + kBTile <= n && ((uintptr_t)lwt & 15) == 0) {
+#pragma unroll
+            for (int r = 0; r < kBItems / 2; ++r) {
+                const int s0 = r * 2 * kBT + 2 * tid;
+                const GLB(f64x2b_t) *p2 = reinterpret_cast<const GLB(f64x2b_t) *>(lwt + s0);
+                const f64x2b_t t2 = *p2;
+                s_t[kBPad(s0)] = (u64)__double_as_longlong(t2.x);
+                s_t[kBPad(s0 + 1)] = (u64)__double_as_longlong(t2.y);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < kBItems; ++e) {
+                const int s0 = (e >> 1) * 2 * kBT + 2 * tid + (e & 1);
+                const double v = base + s0 < n ? lwt[s0] : -__builtin_huge_val();
+                s_t[kBPad(s0)] = (u64)__double_as_longlong(v);
+            }
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < kBItems; ++j) {
-        const i64 i = base + tid * kBItems + j;
-        const double v = i < n ? glb(S.logw)[i] : -__builtin_huge_val();
+        const double v = __longlong_as_double((long long)s_t[kBPad(tid * kBItems + j)]);
         const double e = det_exp(v - m);
         u64 q = 0;
         if (e >= 0.0) {
@@ -919,10 +949,18 @@ __global__ __launch_bounds__(256) void k_bscan(const BSlot *slots, const int *n_
     }
     __syncthreads();
     const u64 pre = s_prefix + texcl;
+    // each thread rewrites the 16 entries it read; the prefix then leaves by
+    // striped, coalesced stores
 #pragma unroll
-    for (int j = 0; j < kBItems; ++j) {
-        const i64 i = base + tid * kBItems + j;
-        if (i < n) glb(S.pref)[i] = pre + loc[j];
+    for (int j = 0; j < kBItems; ++j) s_t[kBPad(tid * kBItems + j)] = pre + loc[j];
+    __syncthreads();
+    {
+        GLB(u64) *pt = glb(S.pref) + base;
+#pragma unroll
+        for (int e = 0; e < kBItems; ++e) {
+            const int s0 = (e >> 1) * 2 * kBT + 2 * tid + (e & 1);
+            if (base + s0 < n) pt[s0] = s_t[kBPad(s0)];
+        }
     }
     if (tid == 0) {
         TilePart p;
