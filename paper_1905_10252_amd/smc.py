@@ -406,7 +406,9 @@ class Batch:
     def attach(self, slot: int, n: int, d: int, mean, chol, *, seed: int = 0,
                sampler_id: int = 0, rw_sd: float = 0.5, init_mean: float = 0.0,
                init_sd: float = 3.0, mode: int = L.MODE_AUTO, ess_num: int = 1,
-               ess_den: int = 2, log_norm=None, init_log_norm=None) -> None:
+               ess_den: int = 2, log_norm=None, init_log_norm=None, logw=None) -> None:
+        """logw: optionally the caller's own float64 [n] device tensor for the
+        log-weights (any 8-byte aligned view); allocated here otherwise."""
         dev = self.device
         n, d = int(n), int(d)
         m = torch.as_tensor(mean, dtype=torch.float64).reshape(-1).contiguous()
@@ -423,7 +425,10 @@ class Batch:
         desc.log_norm = log_norm if log_norm is not None else chol_log_norm(U)
         md, Ud = m.to(dev), U.to(dev)
         x = torch.empty((n, d), dtype=torch.float64, device=dev)
-        logw = torch.empty(n, dtype=torch.float64, device=dev)
+        if logw is None:
+            logw = torch.empty(n, dtype=torch.float64, device=dev)
+        else:
+            _need(logw, torch.float64, n, "logw")
         desc.mean, desc.chol = md.data_ptr(), Ud.data_ptr()
         desc.x, desc.logw = x.data_ptr(), logw.data_ptr()
         nb = self._lib.smc_batch_sampler_bytes(C.byref(desc))
