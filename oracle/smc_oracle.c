@@ -169,7 +169,8 @@ double orc_det_atan(double z)
 /* ------------------------------------------------------------------------ */
 /* Standard normals by the Marsaglia-Bray polar method.  Pair k of particle  */
 /* idx uses counter sub-word (k << 16) | attempt; after 32 rejected attempts */
-/* (probability ~1e-21) the pair is (0, 0).                                  */
+/* (probability ~1e-21) the pair is (0, 0).  With one coordinate a particle, */
+/* particles 2p and 2p + 1 share pair 0 of index p.                          */
 /* ------------------------------------------------------------------------ */
 static void orc_normal_pair(uint64_t seed, uint32_t tag, uint32_t sampler_id, uint32_t t,
                             uint32_t idx, uint32_t pair, double *z1, double *z2)
@@ -198,6 +199,14 @@ static void orc_normal_pair(uint64_t seed, uint32_t tag, uint32_t sampler_id, ui
 void orc_normals(uint64_t seed, uint32_t tag, uint32_t sampler_id, uint32_t t, uint32_t idx,
                  int32_t d, double *z)
 {
+    if (d == 1) {
+        /* one coordinate a particle: particles 2p and 2p + 1 take the two
+           values of pair 0 drawn for index p, so no draw is discarded */
+        double a, b;
+        orc_normal_pair(seed, tag, sampler_id, t, idx >> 1, 0u, &a, &b);
+        z[0] = (idx & 1u) ? b : a;
+        return;
+    }
     for (int32_t k = 0; 2 * k < d; ++k) {
         double a, b;
         orc_normal_pair(seed, tag, sampler_id, t, idx, (uint32_t)k, &a, &b);

@@ -109,6 +109,23 @@ def test_polar_normals_distribution():
     assert abs(np.corrcoef(pairs[:, 0], pairs[:, 1])[0, 1]) < 5.0 / math.sqrt(n)
 
 
+def test_one_dimensional_normals_share_pairs():
+    """With d = 1, particles 2p and 2p + 1 take the two values of the pair
+    drawn for index p (d = 2 at index p gives that pair), so the 1-D stream
+    is the pairs laid end to end: still standard normal and uncorrelated."""
+    for p in (0, 1, 7, 1000):
+        pair = O.normals(5, O.TAG_PROPOSE, 2, 3, p, 2)
+        assert O.normals(5, O.TAG_PROPOSE, 2, 3, 2 * p, 1)[0] == pair[0]
+        assert O.normals(5, O.TAG_PROPOSE, 2, 3, 2 * p + 1, 1)[0] == pair[1]
+    n = 60000
+    z = np.array([O.normals(13, O.TAG_INIT, 1, 0, i, 1)[0] for i in range(n)])
+    assert abs(z.mean()) < 5.0 / math.sqrt(n)
+    assert abs(z.var() - 1.0) < 5.0 * math.sqrt(2.0 / n)
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+    for lag in (1, 2):
+        assert abs(np.corrcoef(z[:-lag], z[lag:])[0, 1]) < 5.0 / math.sqrt(n)
+
+
 def test_normals_counter_layout():
     a = O.normals(1, O.TAG_PROPOSE, 0, 1, 7, 3)
     b = O.normals(1, O.TAG_PROPOSE, 0, 1, 7, 4)
