@@ -317,6 +317,34 @@ __global__ __launch_bounds__(256) void k_bprop(const BSlot *slots, const int *n_
     if (tid == 0 && grp == 0 && (chunk % kChunksPerTile) == 0) S.status[chunk / kChunksPerTile] = 0;
     const uint32_t t = kInit ? 0u : S.ctrl->t;
     const uint32_t tag = kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose;
+    if (d == 1) {
+        // One coordinate a particle: particles 2p and 2p + 1 take the two
+        // values of the pair drawn for index p; the chunk's (at most 128)
+        // pairs go to its first two wavefronts, one pair a lane.
+        if (tid >= kBChunk / 2) return;  // whole wavefronts
+        const i64 p = (i64)chunk * (kBChunk / 2) + tid;
+        const i64 i0 = 2 * p;
+        const bool pact = i0 < n;
+        double z[2];
+        normal_pair_wave(S.seed, tag, S.sampler, t, (uint32_t)p, 0u, pact, z[0], z[1],
+                         s_xch[tid >> 6]);
+        if (!pact) return;
+        GLB(double) *xr = glb(kInit ? S.x : (S.ctrl->cur ? S.x_scr : S.x));
+        for (int h = 0; h < 2; ++h) {
+            const i64 i = i0 + h;
+            if (i >= n) break;
+            const double zh = h == 0 ? z[0] : z[1];
+            if (kInit) {
+                const double xk = S.init_mean + S.init_sd * zh;
+                xr[i] = xk;
+                const double t0 = xk - S.init_mean;
+                glb(S.lp_scr)[i] = 0.0 + (t0 * t0) * S.init_prec;
+            } else {
+                xr[i] = xr[i] + S.rw_sd * zh;
+            }
+        }
+        return;
+    }
     const i64 i = (i64)chunk * kBChunk + tid;
     const bool act = i < n;
     GLB(double) *xi = glb(S.x) + i * d;

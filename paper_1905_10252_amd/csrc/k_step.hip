@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     __shared__ uint4 s_xch[4][64];  // normal generator exchange, one row per wave
     const int tid = threadIdx.x;
     const i64 gtid = (i64)blockIdx.x * 256 + tid, gsz = (i64)gridDim.x * 256;
-    const int d = a.d;
+    const int d = DT == 1 ? 1 : a.d;  // DT > 0 is launched only for d == DT
     const bool uni = !kInit && a.uniform && *a.uniform;  // lazy reset: weights are -ln N
     const uint32_t tag = kInit ? (uint32_t)kTagInit : (uint32_t)kTagPropose;
     const uint32_t tt_ = kInit ? 0u : t;
@@ -217,8 +217,69 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     Online<DA> on;
     on.init();
     double xv[DA];
+    // The weight and what follows it, for particle i whose new row is xw
+    // (and, with DT > 0, also in xv); acc and acc0 are the quadratic forms of
+    // the Gaussian target and of q0.
+    auto tail = [&](i64 i, const double *xw, double acc, double acc0) {
+        const double lq0 = kInit ? a.init_log_norm - 0.5 * acc0 : 0.0;
+        if (kKind == SMC_TARGET_LOGREG) {
+            if (kInit) logw[i] = lq0;  // combined with log pi by k_reweight
+            return;
+        }
+        double lpn;
+        if (kKind == SMC_TARGET_GAUSS) {
+            lpn = a.log_norm - 0.5 * acc;
+        } else {
+            const double tt = xw[0] - a.mu;
+            const double w = 1.0 + (tt * tt) * a.inv_nu;
+            lpn = a.log_norm - a.hnu1 * det_log(w);
+        }
+        const double lw = kInit ? lpn - lq0 : (uni ? a.reset : logw[i]) + (lpn - lp[i]);
+        (kOut ? lpo : lp)[i] = lpn;
+        logw[i] = lw;
+        bad |= (lw != lw) | (lw == __builtin_huge_val());
+        const u64 kk = okey(lw);
+        key = kk > key ? kk : key;
+        if (DT > 0) on.add(lw, xv);
+    };
+    constexpr bool kMay1 = kKind != SMC_TARGET_BEARING && DT <= 1;  // d == 1 possible
+    if (kMay1 && d == 1) {
+        // One coordinate a particle: particles 2p and 2p + 1 take the two
+        // values of the pair drawn for index p, so each lane draws one pair
+        // for two particles (a wave-uniform trip count over the pairs).
+        const i64 np = (n + 1) >> 1;
+        for (i64 base = gtid - (tid & 63); base < np; base += gsz) {
+            const i64 p = base + (tid & 63);
+            const bool pact = p < np;
+            double z[2];
+            normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)p, 0u, pact, z[0], z[1],
+                             s_xch[tid >> 6]);
+            if (!pact) continue;
+#pragma unroll 1
+            for (int h = 0; h < 2; ++h) {
+                const i64 i = 2 * p + h;
+                if (i >= n) break;
+                double *xw = (kOut ? xo : x) + i;
+                const double zh = h == 0 ? z[0] : z[1];
+                const double xk = kInit ? a.init_mean + a.init_sd * zh : x[i] + a.rw_sd * zh;
+                xw[0] = xk;
+                if (DT > 0) xv[0] = xk;
+                if (a.thb) a.thb[i * a.dp] = to_bf16(xk * kLog2e);
+                double acc = 0.0, acc0 = 0.0;
+                if (kKind == SMC_TARGET_GAUSS) {
+                    const double tt = xk - a.mean[0];
+                    acc = acc + (tt * tt) * a.prec[0];
+                }
+                if (kInit) {
+                    const double t0 = xk - a.init_mean;
+                    acc0 = acc0 + (t0 * t0) * a.init_prec;
+                }
+                tail(i, xw, acc, acc0);
+            }
+        }
+    }
     // wave-uniform trip count: the normal generator is wave-cooperative
-    for (i64 base = gtid - (tid & 63); base < n; base += gsz) {
+    for (i64 base = gtid - (tid & 63); base < (kMay1 && d == 1 ? 0 : n); base += gsz) {
         const i64 i = base + (tid & 63);
         const bool act = i < n;
         double *xi = x + i * d;
@@ -284,26 +345,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             }
         }
         if (!act) continue;
-        const double lq0 = kInit ? a.init_log_norm - 0.5 * acc0 : 0.0;
-        if (kKind == SMC_TARGET_LOGREG) {
-            if (kInit) logw[i] = lq0;  // combined with log pi by k_reweight
-            continue;
-        }
-        double lpn;
-        if (kKind == SMC_TARGET_GAUSS) {
-            lpn = a.log_norm - 0.5 * acc;
-        } else {
-            const double tt = xw[0] - a.mu;
-            const double w = 1.0 + (tt * tt) * a.inv_nu;
-            lpn = a.log_norm - a.hnu1 * det_log(w);
-        }
-        const double lw = kInit ? lpn - lq0 : (uni ? a.reset : logw[i]) + (lpn - lp[i]);
-        (kOut ? lpo : lp)[i] = lpn;
-        logw[i] = lw;
-        bad |= (lw != lw) | (lw == __builtin_huge_val());
-        const u64 kk = okey(lw);
-        key = kk > key ? kk : key;
-        if (DT > 0) on.add(lw, xv);
+        tail(i, xw, acc, acc0);
     }
     if (kKind == SMC_TARGET_LOGREG) return;
     if (!kEst || DT > 0) {
@@ -564,18 +606,25 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
     const u64 r = resample_word(a.seed, a.sampler, t);
     double xr[kSmallI], lpr[kSmallI];  // kD1: the items' new x and log-target
 
-    // proposal and weights (items tid + 1024 j)
+    // proposal and weights (items tid + 1024 j; with d = 1 items 2 tid + j,
+    // the two particles that share the pair drawn for index tid)
+    static_assert(kSmallI == 2, "one pair per thread covers its two 1-D items");
     u64 key = 0;
     unsigned bad = 0;
+    double zp[2] = {0.0, 0.0};
+    if (kD1)
+        normal_pair_wave(a.seed, kTagPropose, a.sampler, t, (uint32_t)tid, 0u, 2 * (i64)tid < n,
+                         zp[0], zp[1], s_xch[wid]);
     for (int j = 0; j < kSmallI; ++j) {
-        const i64 i = tid + (i64)kSmallT * j;
+        const i64 i = kD1 ? 2 * (i64)tid + j : tid + (i64)kSmallT * j;
         const bool act = i < n;
         double *xi = x + i * d;
         double acc = 0.0;
         for (int k = 0; 2 * k < d; ++k) {
-            double z[2];
-            normal_pair_wave(a.seed, kTagPropose, a.sampler, t, (uint32_t)i, (uint32_t)k, act,
-                             z[0], z[1], s_xch[wid]);
+            double z[2] = {zp[j == 0 ? 0 : 1], 0.0};
+            if (!kD1)
+                normal_pair_wave(a.seed, kTagPropose, a.sampler, t, (uint32_t)i, (uint32_t)k, act,
+                                 z[0], z[1], s_xch[wid]);
             if (!act) continue;
             for (int h = 0; h < 2; ++h) {
                 const int kk = 2 * k + h;
@@ -673,7 +722,7 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
         double s1[DM], s2[DM];
         for (int k = 0; k < DM; ++k) s1[k] = s2[k] = 0.0;
         for (int j = 0; j < kSmallI; ++j) {
-            const i64 i = tid + (i64)kSmallT * j;
+            const i64 i = kD1 ? 2 * (i64)tid + j : tid + (i64)kSmallT * j;
             if (i >= n) continue;
             const double e = s_e[i];
 #pragma unroll
@@ -706,7 +755,7 @@ __device__ __forceinline__ void small_iteration(const TArgs &a, i64 n, uint32_t 
     if (kD1) {
         // s_e is free now (the decision below does not read it)
         for (int j = 0; j < kSmallI; ++j) {
-            const i64 i = tid + (i64)kSmallT * j;
+            const i64 i = 2 * (i64)tid + j;
             if (i < n) {
                 s_e[i] = xr[j];
                 s_lpv[i] = lpr[j];

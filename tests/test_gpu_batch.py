@@ -74,11 +74,12 @@ def check_step(B, slot, o, out, where):
     assert abs(info["log_c"] - out["log_c"]) <= 1e-10 * max(1.0, abs(out["log_c"])), where
 
 
-# (n, d, mode): ragged tiles, every dimension bucket, all three triggers
+# (n, d, mode): ragged tiles, every dimension bucket, all three triggers, and
+# a 1-D sampler of odd N over several chunks (neighbours share a normal pair)
 MIX = [(1, 1, O.MODE_AUTO), (255, 3, O.MODE_FORCE), (4096, 8, O.MODE_AUTO),
        (4097, 9, O.MODE_FORCE), (10000, 33, O.MODE_AUTO), (20000, 64, O.MODE_NEVER),
-       (7000, 17, O.MODE_FORCE), (3000, 56, O.MODE_AUTO)]
-SLOTS = [3, 0, 9, 1, 5, 2, 4, 7]
+       (7000, 17, O.MODE_FORCE), (3000, 56, O.MODE_AUTO), (4099, 1, O.MODE_FORCE)]
+SLOTS = [3, 0, 9, 1, 5, 2, 4, 7, 8]
 
 
 def test_batch_mix_bit_exact_vs_oracle(smc, dev):

@@ -217,6 +217,21 @@ def test_logreg_steps_per_step_parity(smc, dev, precision, tol):
         assert np.array_equal(nc.cpu().numpy(), onc)
 
 
+def test_logreg_one_feature_proposals(smc, dev):
+    """d = 1 on the general update path: particles 2p and 2p + 1 share the
+    pair drawn for index p; initial particles and proposals bit for bit
+    against the oracle over an odd population, weights within tolerance."""
+    n = 3001
+    g, o = logreg_pair(smc, dev, 400, 1, n, "f64")
+    o.init()
+    assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x))
+    for t in range(1, 4):
+        g.step()
+        o.step()
+        assert np.array_equal(bits(g.x.cpu().numpy()), bits(o.x)), t
+        assert_close(g.logw.cpu().numpy(), o.logw, 1e-11, "logw t=%d" % t)
+
+
 def test_logreg_force_step_structure(smc, dev):
     """A resampling step leaves copies of proposed particles, equal weights."""
     n, d = 2000, 8
