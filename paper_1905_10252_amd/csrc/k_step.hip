@@ -251,6 +251,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         for (i64 base = gtid - (tid & 63); base < np; base += gsz) {
             const i64 p = base + (tid & 63);
             const bool pact = p < np;
+            // the pair's rows are requested before the normals are drawn, so the
+            // loads overlap the generator (the empty asm keeps the compiler from
+            // sinking them into their use): about 1 % faster
+            const i64 ic0 = 2 * p < n ? 2 * p : n - 1, ic1 = 2 * p + 1 < n ? 2 * p + 1 : n - 1;
+            const double xa0 = kInit ? 0.0 : x[ic0], xa1 = kInit ? 0.0 : x[ic1];
+            asm volatile("" ::: "memory");
             double z[2];
             normal_pair_wave(a.seed, tag, a.sampler, tt_, (uint32_t)p, 0u, pact, z[0], z[1],
                              s_xch[tid >> 6]);
@@ -261,7 +267,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 if (i >= n) break;
                 double *xw = (kOut ? xo : x) + i;
                 const double zh = h == 0 ? z[0] : z[1];
-                const double xk = kInit ? a.init_mean + a.init_sd * zh : x[i] + a.rw_sd * zh;
+                const double xh = h == 0 ? xa0 : xa1;
+                const double xk = kInit ? a.init_mean + a.init_sd * zh : xh + a.rw_sd * zh;
                 xw[0] = xk;
                 if (DT > 0) xv[0] = xk;
                 if (a.thb) a.thb[i * a.dp] = to_bf16(xk * kLog2e);
