@@ -293,6 +293,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         double *xw = (kOut ? xo : x) + i * d;
         if (kKind == SMC_TARGET_BEARING) {
             double z[4];
+            // the particle's state and weight are requested before the
+            // normals are drawn, so the loads overlap the generator
+            const i64 ic = act ? i : 0;
+            const double s0 = kInit ? 0.0 : x[ic * 4], s1 = kInit ? 0.0 : x[ic * 4 + 1];
+            const double s2 = kInit ? 0.0 : x[ic * 4 + 2], s3 = kInit ? 0.0 : x[ic * 4 + 3];
+            const double lw0 = (kInit || uni) ? 0.0 : logw[ic];
+            asm volatile("" ::: "memory");
             // coefficients as scalar operands (coef()): 1.5 % faster here;
             // no gain for the other targets, whose uniform values already
             // fill the scalar registers
@@ -311,16 +318,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 const double v1 = a.l21 * z[0] + a.l22 * z[1];
                 const double v2 = a.l11 * z[2];
                 const double v3 = a.l21 * z[2] + a.l22 * z[3];
-                const double n0 = (xi[0] + a.delta * xi[1]) + v0;
-                const double n1 = xi[1] + v1;
-                const double n2 = (xi[2] + a.delta * xi[3]) + v2;
-                const double n3 = xi[3] + v3;
+                const double n0 = (s0 + a.delta * s1) + v0;
+                const double n1 = s1 + v1;
+                const double n2 = (s2 + a.delta * s3) + v2;
+                const double n3 = s3 + v3;
                 xw[0] = n0;
                 xw[1] = n1;
                 xw[2] = n2;
                 xw[3] = n3;
                 const double e = a.obs[t - 1] - det_atan<true>(n2 / n0);
-                lw = (uni ? a.reset : logw[i]) + (a.obs_log_norm - 0.5 * ((e * e) * a.obs_prec));
+                lw = (uni ? a.reset : lw0) + (a.obs_log_norm - 0.5 * ((e * e) * a.obs_prec));
             }
             logw[i] = lw;
             bad |= (lw != lw) | (lw == __builtin_huge_val());
