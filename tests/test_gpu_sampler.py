@@ -106,6 +106,40 @@ def test_student_t(smc, dev, n):
     run_and_compare(g, o, 5)
 
 
+@pytest.mark.parametrize("n,mode", [(6000, "auto"), (6000, "force"), (6001, "never")])
+def test_gauss_1d_multi_kernel(smc, dev, n, mode):
+    """The 1-D Gaussian above one workgroup: even n moves each lane's two
+    particles as 16-byte accesses, odd n takes 8-byte ones; both bit-exact."""
+    _say("gauss 1d n=%d" % n, mode)
+    G, Or = pair_gauss(smc, dev, n, [2.0], [1.0], 41, MODES[mode])
+    run_and_compare(G, Or, 6)
+
+
+@pytest.mark.parametrize("kind", ["student", "gauss"])
+def test_one_dimensional_update_unaligned_arrays(smc, dev, kind):
+    """x and logw handed to smc_step one element past a 16-byte boundary: the
+    update takes its 8-byte accesses and the trajectory stays bit-exact."""
+    import torch
+    _say("unaligned", kind)
+    n = 4096
+    if kind == "student":
+        ln, iln = I.student_log_norm(5.0), I.iso_gauss_log_norm(1, 3.0)
+        g = smc.Sampler(n, 1, "student", seed=9, rw_sd=0.5, nu=5.0, mu=1.0,
+                        mode=O.MODE_AUTO, log_norm=ln, init_log_norm=iln, device=dev)
+        o = O.Sampler(n, 1, O.T_STUDENT, seed=9, rw_sd=0.5, nu=5.0, mu=1.0,
+                      mode=O.MODE_AUTO, log_norm=ln, init_log_norm=iln)
+        o.init()
+    else:
+        g, o = pair_gauss(smc, dev, n, [2.0], [1.0], 9, O.MODE_AUTO)
+    bx = torch.empty((n + 1, 1), dtype=torch.float64, device=dev)
+    bw = torch.empty(n + 1, dtype=torch.float64, device=dev)
+    bx[1:] = g.x
+    bw[1:] = g.logw
+    g.x, g.logw = bx[1:], bw[1:]
+    assert g.x.data_ptr() % 16 == 8 and g.logw.data_ptr() % 16 == 8
+    run_and_compare(g, o, 6)
+
+
 def test_many_samplers_independent_streams(smc, dev):
     """Different seeds / sampler ids give different draws; same ones repeat."""
     g = I.GAUSS1D
