@@ -14,7 +14,9 @@
 // to resample.  A prefix value is the scan's tile-local value plus the offset
 // of its tile of 4096.  The segment boundaries are found by a 64-ary search
 // run by one wavefront; the test A_j + j < k is evaluated as
-// N S_j + U < (k - j) S in 128-bit integers (no division).
+// N S_j + U < (k - j) S in 128-bit integers (no division).  Inside a segment
+// the outputs find their sources without a search: each source with copies
+// marks its first output, and a max-scan over the outputs carries the marks.
 #include <hip/hip_runtime.h>
 
 #include "../../include/smc.h"
@@ -340,8 +342,9 @@ template <int VEC, bool kSum = false>
 __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
 {
     __shared__ unsigned sA[kSegLen + 1];
-    __shared__ unsigned sAnc[kSegLen];
+    __shared__ __attribute__((aligned(16))) unsigned sAnc[kSegLen];
     __shared__ i64 s_j[2];
+    __shared__ u64 s_wmax[kExpandThreads / 64];
     const int tid = threadIdx.x, wid = tid >> 6;
     AFun f;
     if (!make_afun(a.ctrl, a.pref, a.tpre, a.n, a.count_mode, f, blockIdx.x == 0 && tid == 0))
@@ -382,18 +385,55 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a)
     if (a.nc_out)
         for (int i = tid; i < ns; i += kExpandThreads)
             a.nc_out[j0 + i] = (i64)sA[i + 1] - (i64)sA[i];
-    for (int i = tid; i < np; i += kExpandThreads) {
-        const unsigned p = (unsigned)(p0 + i);
-        int lo = 0, hi = ns;  // first t with sA[1 + t] > p
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (sA[1 + mid] <= p) lo = mid + 1;
-            else hi = mid;
+    // Output p comes from local source t, the first with sA[1 + t] > p, so
+    // sA[t] <= p < sA[1 + t] (sA[0] <= p0 by the merge-path cut).  Each source
+    // with copies marks the first of its outputs inside the segment with
+    // t + 1; an inclusive max-scan over the outputs carries every mark over
+    // the rest of its source's outputs.  Local source ns (source j1) owns
+    // whatever follows sA[ns].  Marks land on distinct outputs (sources with
+    // copies start at distinct outputs) and output p0 always holds one.
+    for (int r = tid; r < np; r += kExpandThreads) sAnc[r] = 0u;
+    __syncthreads();
+    for (int t = tid; t <= ns; t += kExpandThreads) {
+        const i64 lo = sA[t];
+        const i64 hi = t < ns ? (i64)sA[t + 1] : INT64_MAX;
+        if (hi > lo && hi > p0) {
+            const i64 st = (lo > p0 ? lo : p0) - p0;
+            if (st < np) sAnc[st] = (unsigned)(t + 1);
         }
-        i64 anc = j0 + lo;
-        anc = anc < n ? anc : n - 1;
-        sAnc[i] = (unsigned)anc;
-        if (a.anc_out) a.anc_out[p0 + i] = anc;
+    }
+    __syncthreads();
+    {
+        constexpr int E = kSegLen / kExpandThreads;  // outputs per thread, contiguous
+        static_assert(E == 8, "two 16-byte LDS reads per thread");
+        const int lane = tid & 63;
+        // entries past np are stale; they reach only positions past np
+        const uint4 q0 = reinterpret_cast<const uint4 *>(sAnc)[2 * tid];
+        const uint4 q1 = reinterpret_cast<const uint4 *>(sAnc)[2 * tid + 1];
+        unsigned v[E] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+        unsigned run = 0u;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            run = v[e] > run ? v[e] : run;
+            v[e] = run;
+        }
+        const u64 incl = wave_scan_u64((u64)run, 0ull, [](u64 x, u64 y) { return y > x ? y : x; });
+        if (lane == 63) s_wmax[wid] = incl;
+        u64 carry = (u64)__shfl_up((long long)incl, 1, 64);
+        carry = lane ? carry : 0ull;
+        __syncthreads();
+        for (int w = 0; w < wid; ++w) carry = s_wmax[w] > carry ? s_wmax[w] : carry;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int r = tid * E + e;
+            if (r < np) {
+                const unsigned m = v[e] > (unsigned)carry ? v[e] : (unsigned)carry;
+                i64 anc = j0 + (i64)m - 1;
+                anc = anc < n ? anc : n - 1;
+                sAnc[r] = (unsigned)anc;
+                if (a.anc_out) a.anc_out[p0 + r] = anc;
+            }
+        }
     }
     __syncthreads();
     if constexpr (kSum) {
