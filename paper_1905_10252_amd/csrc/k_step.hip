@@ -243,23 +243,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         key = kk > key ? kk : key;
         if (DT > 0) on.add(lw, xv);
     };
-    // The same for a 1-D particle of the Gaussian or Student-t target whose
-    // new value is xk and whose previous weight and log-target are given;
-    // returns the weight, lpn the new log-target.
-    auto weigh1 = [&](double xk, double lw_old, double lp_old, double &lpn) {
+    // Log-target of a 1-D particle of the Gaussian or Student-t target: the
+    // same operations as tail's, so a value recomputed from a particle equals
+    // the one computed when the particle was proposed, bit for bit.
+    auto lpt1 = [&](double v) {
+        if (kKind == SMC_TARGET_GAUSS) {
+            const double tt = v - a.mean[0];
+            return a.log_norm - 0.5 * ((tt * tt) * a.prec[0]);
+        }
+        const double tt = v - a.mu;
+        const double w = 1.0 + (tt * tt) * a.inv_nu;
+        return a.log_norm - a.hnu1 * det_log(w);
+    };
+    // tail's weight for such a particle with new value xk, previous weight
+    // lw_old and previous log-target lp_old; returns the weight.
+    auto weigh1 = [&](double xk, double lw_old, double lp_old) {
         double lq0 = 0.0;
         if (kInit) {
             const double t0 = xk - a.init_mean;
             lq0 = a.init_log_norm - 0.5 * ((t0 * t0) * a.init_prec);
         }
-        if (kKind == SMC_TARGET_GAUSS) {
-            const double tt = xk - a.mean[0];
-            lpn = a.log_norm - 0.5 * ((tt * tt) * a.prec[0]);
-        } else {
-            const double tt = xk - a.mu;
-            const double w = 1.0 + (tt * tt) * a.inv_nu;
-            lpn = a.log_norm - a.hnu1 * det_log(w);
-        }
+        const double lpn = lpt1(xk);
         const double lw = kInit ? lpn - lq0 : lw_old + (lpn - lp_old);
         bad |= (lw != lw) | (lw == __builtin_huge_val());
         const u64 kk = okey(lw);
@@ -274,7 +278,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     if (kMay1 && d == 1) {
         // One coordinate a particle: particles 2p and 2p + 1 take the two
         // values of the pair drawn for index p, so each lane draws one pair
-        // for two particles (a wave-uniform trip count over the pairs).
+        // for two particles (a wave-uniform trip count over the pairs).  The
+        // Gaussian and Student-t targets keep no cached log-target here: the
+        // previous one is recomputed from the particle (for the Student-t one
+        // more logarithm, against 16 bytes less read and written per particle
+        // here and in the redistribution, which then moves 8-byte rows only).
+        // The initial pass still writes it, for the one-workgroup iteration
+        // that small populations step with.
         const i64 np = (n + 1) >> 1;
         // v2 (n even, 16-byte aligned arrays, Gaussian or Student-t target): a
         // lane moves its two particles' values as one 16-byte access per
@@ -309,40 +319,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                              s_xch[tid >> 6]);
             if (!pact) continue;
             if (v2) {
-                double lwa = a.reset, lwb = a.reset, lpa = 0.0, lpb = 0.0;
-                if (!kInit) {
-                    if (!uni) {
-                        const f64x2s w = *reinterpret_cast<const f64x2s *>(logw + 2 * p);
-                        lwa = w[0];
-                        lwb = w[1];
-                    }
-                    const f64x2s l = *reinterpret_cast<const f64x2s *>(lp + 2 * p);
-                    lpa = l[0];
-                    lpb = l[1];
+                double lwa = a.reset, lwb = a.reset;
+                if (!kInit && !uni) {
+                    const f64x2s w = *reinterpret_cast<const f64x2s *>(logw + 2 * p);
+                    lwa = w[0];
+                    lwb = w[1];
                 }
-                double xn0 = 0.0, xn1 = 0.0, ln0 = 0.0, ln1 = 0.0, lw0 = 0.0, lw1 = 0.0;
+                double xn0 = 0.0, xn1 = 0.0, lw0 = 0.0, lw1 = 0.0;
 #pragma unroll 1
                 for (int h = 0; h < 2; ++h) {
                     const double zh = h == 0 ? z[0] : z[1];
                     const double xh = h == 0 ? xa0 : xa1;
                     const double xk = kInit ? a.init_mean + a.init_sd * zh : xh + a.rw_sd * zh;
-                    double lpn;
-                    const double lw = weigh1(xk, h == 0 ? lwa : lwb, h == 0 ? lpa : lpb, lpn);
+                    const double lw = weigh1(xk, h == 0 ? lwa : lwb, kInit ? 0.0 : lpt1(xh));
+                    // the one-workgroup iteration (N <= 2048) reads the cache
+                    if (kInit) lp[2 * p + h] = lpt1(xk);
                     if (h == 0) {
                         xn0 = xk;
-                        ln0 = lpn;
                         lw0 = lw;
                     } else {
                         xn1 = xk;
-                        ln1 = lpn;
                         lw1 = lw;
                     }
                 }
                 *reinterpret_cast<f64x2s *>((kOut ? xo : x) + 2 * p) = f64x2s{xn0, xn1};
-                *reinterpret_cast<f64x2s *>((kOut ? lpo : lp) + 2 * p) = f64x2s{ln0, ln1};
                 *reinterpret_cast<f64x2s *>(logw + 2 * p) = f64x2s{lw0, lw1};
                 continue;
             }
+            if constexpr (kKind != SMC_TARGET_LOGREG) {
+#pragma unroll 1
+                for (int h = 0; h < 2; ++h) {
+                    const i64 i = 2 * p + h;
+                    if (i >= n) break;
+                    const double zh = h == 0 ? z[0] : z[1];
+                    const double xh = h == 0 ? xa0 : xa1;
+                    const double xk = kInit ? a.init_mean + a.init_sd * zh : xh + a.rw_sd * zh;
+                    (kOut ? xo : x)[i] = xk;
+                    const double lw_old = (kInit || uni) ? a.reset : logw[i];
+                    logw[i] = weigh1(xk, lw_old, kInit ? 0.0 : lpt1(xh));
+                    if (kInit) lp[i] = lpt1(xk);
+                }
+                continue;
+            }
+            // logistic regression: the likelihood kernels take its weight
 #pragma unroll 1
             for (int h = 0; h < 2; ++h) {
                 const i64 i = 2 * p + h;
@@ -497,7 +516,7 @@ __global__ __launch_bounds__(256) void k_copyback(Ctrl *ctrl, i64 n, int d, doub
     const i64 gtid = (i64)blockIdx.x * 256 + threadIdx.x, gsz = (i64)gridDim.x * 256;
     for (i64 i = gtid; i < n * d; i += gsz) x[i] = x_scr[i];
     for (i64 i = gtid; i < n; i += gsz) {
-        lp[i] = lp_scr[i];
+        if (lp_scr) lp[i] = lp_scr[i];
         if (!uniform) logw[i] = reset;
     }
     if (uniform && gtid == 0) *uniform = 1u;
@@ -1558,12 +1577,16 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
         return SMC_E_DEVICE;
     const double reset = -std::log((double)n);
     unsigned *uni = c.lazy_reset ? &w.ctrl->uniform : nullptr;
+    // the particle filter and the 1-D Gaussian and Student-t samplers carry no
+    // cached log-target
+    const bool lpc = !pf && !(c.d == 1 && (c.target == SMC_TARGET_GAUSS ||
+                                           c.target == SMC_TARGET_STUDENT));
+    double *lp = lpc ? w.lp : nullptr, *lp_scr = lpc ? w.lp_scr : nullptr;
     if (fwd) {
-        // the particle filter carries no cached log-target
         // the filter's row sums ride on 16-byte chunks of its 32-byte rows
         double *ep = (pf && ((uintptr_t)x & 15) == 0) ? w.epart : nullptr;
-        if (launch_expand(w, n, 0, w.x_scr, x, c.d * 8, pf ? nullptr : w.lp_scr,
-                          pf ? nullptr : w.lp, 8, nullptr, nullptr, s, false, ep) != hipSuccess)
+        if (launch_expand(w, n, 0, w.x_scr, x, c.d * 8, lp_scr, lp, 8, nullptr, nullptr, s,
+                          false, ep) != hipSuccess)
             return SMC_E_DEVICE;
         if (pf) {  // Alg 1 takes the mean after resampling
             hipLaunchKernelGGL(k_reset_est<4>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)n,
@@ -1574,16 +1597,16 @@ smc_status step_run(const smc_config &c, const Work &w, int K, int par, uint32_t
                                w.is_grid, c.d, w.rec_num, est, info, 0);
         } else {
             hipLaunchKernelGGL(k_reset_est<0>, dim3(w.is_grid), dim3(256), 0, s, w.ctrl, (i64)n,
-                               c.d, x, w.x_scr, w.lp, w.lp_scr, logw, reset, w.is_part,
+                               c.d, x, w.x_scr, lp, lp_scr, logw, reset, w.is_part,
                                (const double *)nullptr, (i64)0, uni);
         }
         return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
     }
-    if (launch_expand(w, n, 0, x, w.x_scr, c.d * 8, w.lp, w.lp_scr, 8, nullptr, nullptr, s,
-                      true) != hipSuccess)
+    if (launch_expand(w, n, 0, x, w.x_scr, c.d * 8, lp, lp_scr, 8, nullptr, nullptr, s, true) !=
+        hipSuccess)
         return SMC_E_DEVICE;
     hipLaunchKernelGGL(k_copyback, dim3(grid_for(n * c.d)), dim3(256), 0, s, w.ctrl, (i64)n, c.d,
-                       x, w.x_scr, w.lp, w.lp_scr, logw, reset, uni);
+                       x, w.x_scr, lp, lp_scr, logw, reset, uni);
     return hipGetLastError() == hipSuccess ? SMC_OK : SMC_E_DEVICE;
 }
 
