@@ -256,14 +256,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         return a.log_norm - a.hnu1 * det_log(w);
     };
     // tail's weight for such a particle with new value xk, previous weight
-    // lw_old and previous log-target lp_old; returns the weight.
-    auto weigh1 = [&](double xk, double lw_old, double lp_old) {
+    // lw_old and previous log-target lp_old; returns the weight, lpn the new
+    // log-target.
+    auto weigh1 = [&](double xk, double lw_old, double lp_old, double &lpn) {
         double lq0 = 0.0;
         if (kInit) {
             const double t0 = xk - a.init_mean;
             lq0 = a.init_log_norm - 0.5 * ((t0 * t0) * a.init_prec);
         }
-        const double lpn = lpt1(xk);
+        lpn = lpt1(xk);
         const double lw = kInit ? lpn - lq0 : lw_old + (lpn - lp_old);
         bad |= (lw != lw) | (lw == __builtin_huge_val());
         const u64 kk = okey(lw);
@@ -331,9 +332,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     const double zh = h == 0 ? z[0] : z[1];
                     const double xh = h == 0 ? xa0 : xa1;
                     const double xk = kInit ? a.init_mean + a.init_sd * zh : xh + a.rw_sd * zh;
-                    const double lw = weigh1(xk, h == 0 ? lwa : lwb, kInit ? 0.0 : lpt1(xh));
+                    double lpn;
+                    const double lw = weigh1(xk, h == 0 ? lwa : lwb, kInit ? 0.0 : lpt1(xh), lpn);
                     // the one-workgroup iteration (N <= 2048) reads the cache
-                    if (kInit) lp[2 * p + h] = lpt1(xk);
+                    if (kInit) lp[2 * p + h] = lpn;
                     if (h == 0) {
                         xn0 = xk;
                         lw0 = lw;
@@ -356,8 +358,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                     const double xk = kInit ? a.init_mean + a.init_sd * zh : xh + a.rw_sd * zh;
                     (kOut ? xo : x)[i] = xk;
                     const double lw_old = (kInit || uni) ? a.reset : logw[i];
-                    logw[i] = weigh1(xk, lw_old, kInit ? 0.0 : lpt1(xh));
-                    if (kInit) lp[i] = lpt1(xk);
+                    double lpn;
+                    logw[i] = weigh1(xk, lw_old, kInit ? 0.0 : lpt1(xh), lpn);
+                    if (kInit) lp[i] = lpn;
                 }
                 continue;
             }
