@@ -59,6 +59,16 @@ __host__ __device__ inline U128 mul64(u64 a, u64 b)
 #endif
 }
 
+// a * b for a below 2^32: two 32 x 32 -> 64 products instead of a full
+// 64 x 64 -> 128 one
+__host__ __device__ inline U128 mul32x64(unsigned a, u64 b)
+{
+    const u64 lo = (u64)a * (unsigned)b;
+    const u64 hi = (u64)a * (unsigned)(b >> 32);
+    const u64 rlo = lo + (hi << 32);
+    return U128{rlo, (hi >> 32) + (rlo < lo ? 1ull : 0ull)};
+}
+
 __host__ __device__ inline U128 add128(U128 a, U128 b)
 {
     U128 r;

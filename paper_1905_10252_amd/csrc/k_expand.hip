@@ -25,6 +25,8 @@
 
 namespace smc {
 
+// n is below 2^31 (the library's limit), so n, A_j <= n and k - j <= 2n all
+// fit 32 bits and every product below is a 32 x 64-bit one.
 struct AFun {
     i64 n;
     const u64 *pref;  // tile-local inclusive prefix
@@ -42,8 +44,8 @@ struct AFun {
         if (mode == 2) return (i64)pj + j < k;
         const i64 c = k - j;
         if (c <= 0) return false;
-        const U128 lhs = add128(mul64((u64)n, pj), U);
-        const U128 rhs = mul64((u64)c, S);
+        const U128 lhs = add128(mul32x64((unsigned)n, pj), U);
+        const U128 rhs = mul32x64((unsigned)c, S);
         return lt128(lhs, rhs);
     }
 
@@ -59,14 +61,15 @@ struct AFun {
     {
         if (mode == 0) return (u64)(j + 1);
         if (mode == 2) return sj;
-        const U128 num = add128(mul64((u64)n, sj), U);
+        const U128 num = add128(mul32x64((unsigned)n, sj), U);
         const double est = ((double)n * (double)sj + (double)U) * invS;
         u64 a = est > 0.0 ? (u64)est : 0ull;
+        a = a <= (u64)n ? a : (u64)n;  // A_j <= n: keeps a within 32 bits
         // exact correction to a S <= num < (a + 1) S
-        U128 aS = mul64(a, S);
+        U128 aS = mul32x64((unsigned)a, S);
         while (lt128(num, aS)) {
             --a;
-            aS = mul64(a, S);
+            aS = mul32x64((unsigned)a, S);
         }
         U128 a1S = add128(aS, S);
         while (!lt128(num, a1S)) {
