@@ -189,17 +189,19 @@ struct Online {
 };
 
 // ------------------------------------------------------- proposal + weights
+typedef double f64x2s __attribute__((ext_vector_type(2)));
 // DT > 0: d == DT and the estimate sums are accumulated in one pass; DT == 0:
 // any d, sums in a second pass over the block's particles.  The particle filter
 // takes its estimate after resampling, so its update kernel skips them.
 // kOut: the proposal and its log-target go to xo / lpo (the redistribution
 // then maps them back into x); otherwise they overwrite x / lp in place.
-// Five waves per SIMD: the 1-D update needs 99 VGPRs unconstrained (four
-// waves); held to 96 it runs 9 % faster at N = 2^24, with six SGPRs spilled
-// to VGPR lanes (six waves spill vector registers and run slower).
-typedef double f64x2s __attribute__((ext_vector_type(2)));
+// At least four waves per SIMD (up to 128 VGPRs): the 1-D Gaussian and
+// Student-t updates need 102-110 VGPRs and the 4-D Gaussian ones 116-119;
+// held to 96 for five waves they spilled 20-92 bytes a lane, and the Student-t
+// iteration at N = 2^24 ran 6 % slower.  The other instances need fewer
+// registers and keep six or seven waves.
 template <int kKind, bool kInit, int DT, bool kOut>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_is(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_is(
     TArgs a, i64 n, uint32_t t, double *__restrict__ x, double *__restrict__ logw,
     double *__restrict__ lp, u64 *slots_p, double *is_part, double *__restrict__ xo,
     double *__restrict__ lpo)
